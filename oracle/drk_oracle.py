@@ -1,0 +1,759 @@
+"""FP64 CPU oracle for the Deformable Radial Kernel (DRK) rasterizer.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
+with the HIP library (``paper_2412_11752_amd``) and imports nothing from it.
+
+Everything is computed per pixel over every primitive, in float64, from float32
+inputs promoted exactly.  The method is defined by the paper (arXiv 2412.11752,
+"Deformable Radial Kernel Splatting"); each function names the passage it
+follows.  Where the paper is silent or garbled the oracle takes the readings
+listed below (and in the design notes):
+
+  * local axes t_u, t_v and normal n are the COLUMNS of R(q), q = (w, x, y, z)
+    (Sec. 3.3 says "rows", which contradicts R_z being the normal);
+  * polar angle theta = atan2(v, u) mod 2*pi (Sec. 4.1 prints arccos, which only
+    covers [0, pi]); K angles ascending in [0, 2*pi), the last sector wraps
+    from theta_{K-1} to theta_0 + 2*pi, and theta_k < theta <= theta_{k+1};
+  * Sec. 4.4 low-pass: s_l = sqrt(2)/2 px, r_d normalised, the max is taken
+    after opacity and sharpening;
+  * cutoffs as in 3D-GS: alpha_min = 1/255, alpha_max = 0.99, T_min = 1e-4,
+    a contribution whose transmittance would drop below T_min stops the pixel
+    without being added; near plane 0.2;
+  * cache sorting (Sec. 4.4 and Algorithm 1 of the supplement): only
+    contributors enter a cache of L slots kept sorted by r_t (a newcomer goes
+    after equal keys); when the cache is full its head is emitted BEFORE the
+    newcomer is inserted; at the end of the list the cache drains from the
+    head.  The arrival order is the global pre-sort by (float32 view-space
+    depth of the centre, primitive index);
+  * colour: real spherical harmonics of degree <= 3 at the direction from the
+    camera to the centre, plus 0.5, clamped at 0 (3D-GS convention); a plain
+    RGB colour is used as is;
+  * background added with the final transmittance.
+
+Parity unpinned: the low-pass radius s_l, the cutoff constants and the cache
+semantics above have no numeric example in the paper; they are fixed by the
+readings only.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+F64 = torch.float64
+TWO_PI = 2.0 * math.pi
+
+
+@dataclasses.dataclass
+class Opts:
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    near: float = 0.2
+    lowpass_sl: float = math.sqrt(0.5)   # 0 disables the low-pass filter
+    cache_len: int = 8                   # >= 1<<30 means exact per-pixel sort
+    cull_mode: int = 0                   # 0 conservative polygon, 1 paper polygon, 2 all tiles
+
+    def f32(self) -> "Opts":
+        """The same options rounded to float32, as the C ABI carries them."""
+        r = lambda x: float(np.float32(x))
+        return Opts(r(self.alpha_min), r(self.alpha_max), r(self.T_min), r(self.near), r(self.lowpass_sl),
+                    self.cache_len, self.cull_mode)
+
+
+EXACT = 1 << 30
+GRAZING = 1e-6
+
+
+def _f64(a) -> torch.Tensor:
+    return torch.as_tensor(np.asarray(a, dtype=np.float32).astype(np.float64))
+
+
+# ---------------------------------------------------------------------------------------------
+# Elementary pieces
+
+def quat_to_rotmat(q: torch.Tensor) -> torch.Tensor:
+    """Rotation matrix of a (not necessarily unit) quaternion (w, x, y, z), as in 3D-GS (Sec. 3.1).
+    Returns (..., 3, 3); columns are the primitive's local u axis, v axis and plane normal."""
+    q = q / torch.linalg.vector_norm(q, dim=-1, keepdim=True)
+    w, x, y, z = q.unbind(-1)
+    rows = [
+        1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+        2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+        2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y),
+    ]
+    return torch.stack(rows, -1).reshape(q.shape[:-1] + (3, 3))
+
+
+def psi(g, tau):
+    """Edge-sharpening remap (Sec. 4.3): piecewise linear in g with breakpoints (1+tau)/4 and (3-tau)/4."""
+    lo = (1 + tau) / 4
+    hi = (3 - tau) / 4
+    flat = (1 - tau) / (1 + tau)
+    steep = (1 + tau) / (1 - tau)
+    p1 = flat * g
+    p2 = steep * g - tau / (1 - tau)
+    p3 = flat * g + 2 * tau / (1 + tau)
+    return torch.where(g < lo, p1, torch.where(g < hi, p2, p3))
+
+
+def psi_inv(y, tau):
+    """Inverse of ``psi`` (the three pieces inverted; the image breakpoints are (1-tau)/4 and (3+tau)/4)."""
+    y = torch.as_tensor(y, dtype=F64)
+    tau = torch.as_tensor(tau, dtype=F64)
+    p1 = y * (1 + tau) / (1 - tau)
+    p2 = (y * (1 - tau) + tau) / (1 + tau)
+    p3 = (y * (1 + tau) - 2 * tau) / (1 - tau)
+    return torch.where(y < (1 - tau) / 4, p1, torch.where(y < (3 + tau) / 4, p2, p3))
+
+
+_SQ = math.sqrt
+_PI = math.pi
+
+
+def real_sh(deg: int, d: torch.Tensor) -> torch.Tensor:
+    """Real spherical harmonics Y_{l,m}, l <= deg, of unit directions d (..., 3); index l*l + l + m.
+    Standard orthonormal real basis (Cartesian polynomial forms)."""
+    x, y, z = d.unbind(-1)
+    out = [torch.full_like(x, 0.5 / _SQ(_PI))]
+    if deg >= 1:
+        c1 = _SQ(3.0 / (4 * _PI))
+        out += [c1 * y, c1 * z, c1 * x]
+    if deg >= 2:
+        out += [0.5 * _SQ(15.0 / _PI) * x * y,
+                0.5 * _SQ(15.0 / _PI) * y * z,
+                0.25 * _SQ(5.0 / _PI) * (3 * z * z - 1),
+                0.5 * _SQ(15.0 / _PI) * x * z,
+                0.25 * _SQ(15.0 / _PI) * (x * x - y * y)]
+    if deg >= 3:
+        out += [0.25 * _SQ(35.0 / (2 * _PI)) * y * (3 * x * x - y * y),
+                0.5 * _SQ(105.0 / _PI) * x * y * z,
+                0.25 * _SQ(21.0 / (2 * _PI)) * y * (5 * z * z - 1),
+                0.25 * _SQ(7.0 / _PI) * (5 * z * z * z - 3 * z),
+                0.25 * _SQ(21.0 / (2 * _PI)) * x * (5 * z * z - 1),
+                0.25 * _SQ(105.0 / _PI) * z * (x * x - y * y),
+                0.25 * _SQ(35.0 / (2 * _PI)) * x * (x * x - 3 * y * y)]
+    return torch.stack(out, -1)
+
+
+def drk_energy(u, v, s, theta, eta):
+    """E = eta * r1^2 + (1 - eta) * r2^2 / sbar^2 (Sec. 4.1 radial basis + Sec. 4.2 L1 term).
+
+    u, v: (L,) tangent coordinates; s, theta: (L, K) basis lengths and angles; eta: (L,).
+    Returns (E, k) with k the sector index (theta_k < theta <= theta_{k+1}, wrapping)."""
+    K = s.shape[-1]
+    r2sq = u * u + v * v
+    centre = r2sq == 0
+    us = torch.where(centre, torch.ones_like(u), u)
+    vs = torch.where(centre, torch.zeros_like(v), v)
+    th = torch.remainder(torch.atan2(vs, us), TWO_PI)
+    th = torch.where(th <= theta[:, 0], th + TWO_PI, th)
+    k = (theta < th.detach()[:, None]).sum(-1) - 1
+    kn = torch.remainder(k + 1, K)
+    wrap = (k == K - 1).to(F64)
+    th_k = theta.gather(-1, k[:, None]).squeeze(-1)
+    th_n = theta.gather(-1, kn[:, None]).squeeze(-1) + TWO_PI * wrap
+    s_k = s.gather(-1, k[:, None]).squeeze(-1)
+    s_n = s.gather(-1, kn[:, None]).squeeze(-1)
+    # Sec. 4.1: relative angular distance and cosine-interpolated inverse squared scale
+    dtheta = math.pi * (th - th_k) / (th_n - th_k)
+    inv_sbar2 = (1 + torch.cos(dtheta)) / (2 * s_k * s_k) + (1 - torch.cos(dtheta)) / (2 * s_n * s_n)
+    # Sec. 4.2, L1 norm: solve [e_k e_{k+1}] (a, b)^T = (u, v)^T
+    ekx, eky = s_k * torch.cos(th_k), s_k * torch.sin(th_k)
+    enx, eny = s_n * torch.cos(th_n), s_n * torch.sin(th_n)
+    det = ekx * eny - enx * eky
+    a = (us * eny - vs * enx) / det
+    b = (ekx * vs - eky * us) / det
+    r1 = torch.abs(a) + torch.abs(b)
+    E = eta * r1 * r1 + (1 - eta) * r2sq * inv_sbar2
+    E = torch.where(centre, torch.zeros_like(E), E)
+    return E, k
+
+
+def drk_alpha_uv(u, v, s, theta, eta, tau, o):
+    """alpha = o * Psi(g), g = exp(-E/2) (Sec. 4.2 Eq. kernel, Sec. 4.3)."""
+    E, _ = drk_energy(u, v, s, theta, eta)
+    return o * psi(torch.exp(-0.5 * E), tau)
+
+
+# ---------------------------------------------------------------------------------------------
+# Scene / camera containers in float64
+
+@dataclasses.dataclass
+class Prims:
+    """Primitive parameters as (N, ...) float64 tensors (may require grad)."""
+    mu: torch.Tensor      # (N, 3)
+    q: torch.Tensor       # (N, 4)
+    s: torch.Tensor       # (N, K)
+    theta: torch.Tensor   # (N, K)
+    eta: torch.Tensor     # (N,)
+    tau: torch.Tensor     # (N,)
+    o: torch.Tensor       # (N,)
+    color: torch.Tensor   # (N, 3) RGB or (N, C, 3) SH coefficients
+    sh_degree: int
+
+    @staticmethod
+    def from_scene(scene) -> "Prims":
+        n = scene.n
+        if scene.sh_degree < 0:
+            col = _f64(scene.color).T.contiguous()
+        else:
+            nc = (scene.sh_degree + 1) ** 2
+            col = _f64(scene.color).reshape(nc, 3, n).permute(2, 0, 1).contiguous()
+        return Prims(_f64(scene.mu).T.contiguous(), _f64(scene.q).T.contiguous(),
+                     _f64(scene.scale).T.contiguous(), _f64(scene.theta).T.contiguous(),
+                     _f64(scene.eta), _f64(scene.tau), _f64(scene.opacity), col, scene.sh_degree)
+
+    def index(self, idx) -> "Prims":
+        return Prims(self.mu[idx], self.q[idx], self.s[idx], self.theta[idx], self.eta[idx], self.tau[idx],
+                     self.o[idx], self.color[idx], self.sh_degree)
+
+
+@dataclasses.dataclass
+class Cam:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    R: torch.Tensor   # (3, 3) world -> camera
+    t: torch.Tensor   # (3,)
+    bg: torch.Tensor  # (3,)
+
+    @staticmethod
+    def from_camera(c) -> "Cam":
+        f = lambda x: float(np.float32(x))
+        return Cam(int(c.width), int(c.height), f(c.fx), f(c.fy), f(c.cx), f(c.cy),
+                   _f64(c.R).reshape(3, 3), _f64(c.t).reshape(3), _f64(c.bg).reshape(3))
+
+    @property
+    def position(self) -> torch.Tensor:
+        return -(self.R.T @ self.t)
+
+
+# ---------------------------------------------------------------------------------------------
+# Per primitive (view independent of the pixel)
+
+def centre_depth_f32(mu: np.ndarray, cam) -> np.ndarray:
+    """float32 view-space depth of each centre, computed in float64 as ((r20*x + r21*y) + r22*z) + t2
+    and rounded once.  This is the global pre-sort key (3D-GS centre-depth order, Sec. 4.4)."""
+    R = np.asarray(cam.R, np.float32).astype(np.float64).reshape(3, 3)
+    t = np.asarray(cam.t, np.float32).astype(np.float64).reshape(3)
+    m = np.asarray(mu, np.float32).astype(np.float64)
+    z = R[2, 0] * m[0]
+    z = z + R[2, 1] * m[1]
+    z = z + R[2, 2] * m[2]
+    z = z + t[2]
+    return z.astype(np.float32)
+
+
+def prim_colors(P: Prims, cam: Cam) -> torch.Tensor:
+    """Per-primitive RGB: plain colour, or SH at the camera-to-centre direction + 0.5 clamped at 0."""
+    if P.sh_degree < 0:
+        return P.color
+    d = P.mu - cam.position
+    d = d / torch.linalg.vector_norm(d, dim=-1, keepdim=True)
+    Y = real_sh(P.sh_degree, d)                        # (N, C)
+    rgb = torch.einsum("nc,nck->nk", Y, P.color) + 0.5
+    return torch.clamp(rgb, min=0.0)
+
+
+def calibrated_radius(o, tau, alpha_min):
+    """c such that {E <= c^2} is exactly {o * Psi(g) >= alpha_min} (corrected Eq. calibrate, Sec. 4.4):
+    c = sqrt(-2 ln Psi^{-1}(alpha_min / o))."""
+    g_min = psi_inv(torch.as_tensor(alpha_min, dtype=F64) / o, tau)
+    return torch.sqrt(-2.0 * torch.log(g_min))
+
+
+def culled_mask(P: Prims, cam: Cam, opts: Opts) -> torch.Tensor:
+    """Primitives that can never contribute: centre at or behind the near plane, opacity below
+    alpha_min, or invalid parameters."""
+    zc = (P.mu @ cam.R.T + cam.t)[:, 2]
+    bad = ~torch.isfinite(P.mu).all(-1) | ~torch.isfinite(P.s).all(-1) | (P.s <= 0).any(-1)
+    return (zc <= opts.near) | (P.o < opts.alpha_min) | bad
+
+
+# ---------------------------------------------------------------------------------------------
+# Per (pixel, primitive) pair: ray-plane hit (Sec. 3.3), kernel, low-pass (Sec. 4.4)
+
+def pixel_rays(cam: Cam, px: torch.Tensor, py: torch.Tensor):
+    """Unit world-space ray directions through pixel centres (px + 0.5, py + 0.5)."""
+    dc = torch.stack([(px.to(F64) + 0.5 - cam.cx) / cam.fx, (py.to(F64) + 0.5 - cam.cy) / cam.fy,
+                      torch.ones_like(px, dtype=F64)], -1)
+    rd = dc @ cam.R          # R^T dc for each row
+    return rd / torch.linalg.vector_norm(rd, dim=-1, keepdim=True)
+
+
+def eval_pairs(P: Prims, cam: Cam, opts: Opts, px: torch.Tensor, py: torch.Tensor, colors: torch.Tensor):
+    """Evaluate alpha-tilde and r_t for pixel/primitive pairs.  ``P`` and ``colors`` are already
+    gathered per pair (length L).  Returns a dict of (L,) tensors."""
+    R = quat_to_rotmat(P.q)                       # (L, 3, 3)
+    tu, tv, n = R[..., 0], R[..., 1], R[..., 2]
+    ro = cam.position
+    rd = pixel_rays(cam, px, py)                  # (L, 3)
+    den = (rd * n).sum(-1)                        # r_d . R_z
+    ok = den.abs() >= GRAZING
+    den_s = torch.where(ok, den, torch.ones_like(den))
+    rt = ((P.mu - ro) * n).sum(-1) / den_s        # Sec. 4.4 Cache Sorting: r_t
+    zc = rt * (rd @ cam.R[2])                     # view depth of the hit
+    ok = ok & (zc > opts.near)
+    hit = ro + rt[:, None] * rd                   # Sec. 3.3 intersection point
+    u = ((hit - P.mu) * tu).sum(-1)
+    v = ((hit - P.mu) * tv).sum(-1)
+    alpha = drk_alpha_uv(u, v, P.s, P.theta, P.eta, P.tau, P.o)
+    if opts.lowpass_sl > 0:
+        mc = P.mu @ cam.R.T + cam.t
+        pxc = cam.fx * mc[:, 0] / mc[:, 2] + cam.cx
+        pyc = cam.fy * mc[:, 1] / mc[:, 2] + cam.cy
+        d2 = (px.to(F64) + 0.5 - pxc) ** 2 + (py.to(F64) + 0.5 - pyc) ** 2
+        f = P.o * torch.exp(-d2 / (2.0 * den_s * den_s * opts.lowpass_sl ** 2))
+        at = torch.maximum(alpha, f)
+    else:
+        at = alpha
+    at = torch.clamp(at, max=opts.alpha_max)
+    contrib = ok & (at >= opts.alpha_min)
+    return dict(alpha=at, rt=rt, zc=zc, den=den, ok=ok, contrib=contrib, u=u, v=v, color=colors)
+
+
+# ---------------------------------------------------------------------------------------------
+# Candidate prefilter (lossless): every contributing hit lies in the ball of radius c*max_k s_k
+# around the centre (both the L1 chord and sbar are bounded by the larger endpoint length) and in
+# front of the near plane; the low-pass term needs the pixel within s_l*sqrt(2 ln(o/alpha_min)).
+
+def screen_bounds(P: Prims, cam: Cam, opts: Opts) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Conservative pixel-space boxes (N, 4) = (x0, x1, y0, y1) of the possible support, and the
+    culled mask."""
+    with torch.no_grad():
+        cull = culled_mask(P, cam, opts)
+        o = torch.clamp(P.o, min=opts.alpha_min)
+        c = calibrated_radius(o, P.tau, opts.alpha_min)
+        rho = c * P.s.max(-1).values
+        mc = P.mu @ cam.R.T + cam.t
+        X, Y, Z = mc.unbind(-1)
+        zlo = torch.clamp(Z - rho, min=opts.near)
+        zhi = Z + rho
+        inv = lambda a, b: (a / b)
+        xs = torch.stack([inv(X - rho, zlo), inv(X - rho, zhi), inv(X + rho, zlo), inv(X + rho, zhi)], -1)
+        ys = torch.stack([inv(Y - rho, zlo), inv(Y - rho, zhi), inv(Y + rho, zlo), inv(Y + rho, zhi)], -1)
+        box = torch.stack([cam.fx * xs.min(-1).values + cam.cx, cam.fx * xs.max(-1).values + cam.cx,
+                           cam.fy * ys.min(-1).values + cam.cy, cam.fy * ys.max(-1).values + cam.cy], -1)
+        if opts.lowpass_sl > 0:
+            rl = opts.lowpass_sl * torch.sqrt(2.0 * torch.log(torch.clamp(o / opts.alpha_min, min=1.0)))
+            pxc = cam.fx * X / Z + cam.cx
+            pyc = cam.fy * Y / Z + cam.cy
+            box = torch.stack([torch.minimum(box[:, 0], pxc - rl), torch.maximum(box[:, 1], pxc + rl),
+                               torch.minimum(box[:, 2], pyc - rl), torch.maximum(box[:, 3], pyc + rl)], -1)
+        pad = 1e-3 + 1e-9 * box.abs()
+        box = box + torch.stack([-pad[:, 0], pad[:, 1], -pad[:, 2], pad[:, 3]], -1)
+        cull = cull | (zhi <= opts.near)
+    return box, cull
+
+
+# ---------------------------------------------------------------------------------------------
+# Ordering: Algorithm 1 (cache sorting) and the exact sort
+
+def cache_emit(seq: Sequence[Tuple[float, int]], L: int) -> List[Tuple[float, int]]:
+    """Emission order of a pixel's contributors arriving in ``seq`` order through an L-slot cache
+    sorted by r_t (Algorithm 1 of the supplement, reading: a full cache emits its head before the
+    newcomer is inserted; newcomers go after equal keys; the remainder drains from the head)."""
+    cache: List[Tuple[float, int]] = []
+    out: List[Tuple[float, int]] = []
+    for rt, j in seq:
+        if len(cache) >= L:
+            out.append(cache.pop(0))
+        pos = len(cache)
+        while pos > 0 and cache[pos - 1][0] > rt:
+            pos -= 1
+        cache.insert(pos, (rt, j))
+    out.extend(cache)
+    return out
+
+
+def composite(alphas: Sequence[float], cols: Sequence[Sequence[float]], bg, T_min):
+    """Front-to-back alpha blending, Eq. (1): C = sum_i T_i alpha_i c_i + T_final * bg.  A contribution
+    whose resulting transmittance would fall below T_min ends the pixel without being added."""
+    T = 1.0
+    C = [0.0, 0.0, 0.0]
+    n = 0
+    weights = []
+    for a, c in zip(alphas, cols):
+        test = T * (1.0 - a)
+        if test < T_min:
+            break
+        w = T * a
+        for ch in range(3):
+            C[ch] += w * c[ch]
+        weights.append(w)
+        T = test
+        n += 1
+    for ch in range(3):
+        C[ch] += T * float(bg[ch])
+    return C, T, n, weights
+
+
+# ---------------------------------------------------------------------------------------------
+# Full per-pixel renderer
+
+@dataclasses.dataclass
+class PixelResult:
+    rgb: np.ndarray          # (P, 3)
+    T: np.ndarray            # (P,)
+    n_emit: np.ndarray       # (P,) int
+    n_contrib: np.ndarray    # (P,) int
+    knife: np.ndarray        # (P,) bool: some decision within 1e-6 (relative) of its threshold
+    emitted: List[List[int]]  # per pixel, primitive indices actually composited, in order
+    weights: List[List[float]]
+
+
+def render_pixels(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, chunk: int = 64,
+                  prims: Optional[Prims] = None, prefilter: bool = True,
+                  tile_members: Optional[Dict[int, set]] = None) -> PixelResult:
+    """Render the given pixel centres by testing every primitive (through the lossless prefilter
+    unless ``prefilter`` is False).  With ``tile_members`` (tile id -> set of primitive ids) only the
+    primitives binned to the pixel's tile are considered, to show that binning changes nothing."""
+    P = prims if prims is not None else Prims.from_scene(scene)
+    cam = Cam.from_camera(camera)
+    key = centre_depth_f32(scene.mu, camera).view(np.uint32)
+    with torch.no_grad():
+        box, cull = screen_bounds(P, cam, opts)
+        colors = prim_colors(P, cam)
+        alive = torch.nonzero(~cull).squeeze(-1)
+        box_a = box[alive]
+        px_t = torch.as_tensor(np.asarray(px), dtype=torch.int64)
+        py_t = torch.as_tensor(np.asarray(py), dtype=torch.int64)
+        npix = px_t.numel()
+        out_rgb = np.zeros((npix, 3))
+        out_T = np.ones(npix)
+        out_n = np.zeros(npix, np.int64)
+        out_nc = np.zeros(npix, np.int64)
+        knife = np.zeros(npix, bool)
+        emitted: List[List[int]] = [[] for _ in range(npix)]
+        weights: List[List[float]] = [[] for _ in range(npix)]
+        bg = cam.bg.numpy()
+        for c0 in range(0, npix, chunk):
+            cx_ = px_t[c0:c0 + chunk].to(F64)[:, None] + 0.5
+            cy_ = py_t[c0:c0 + chunk].to(F64)[:, None] + 0.5
+            if prefilter:
+                inside = (cx_ >= box_a[None, :, 0]) & (cx_ <= box_a[None, :, 1]) & \
+                         (cy_ >= box_a[None, :, 2]) & (cy_ <= box_a[None, :, 3])
+            else:
+                inside = torch.ones(cx_.shape[0], alive.numel(), dtype=torch.bool)
+            if tile_members is not None:
+                tx = (cam.width + TILE - 1) // TILE
+                tid = (py_t[c0:c0 + chunk] // TILE) * tx + px_t[c0:c0 + chunk] // TILE
+                alive_l = alive.tolist()
+                mem = torch.zeros_like(inside)
+                for r, t in enumerate(tid.tolist()):
+                    members = tile_members.get(t, set())
+                    mem[r] = torch.tensor([a in members for a in alive_l], dtype=torch.bool)
+                inside = inside & mem
+            pl, ml = torch.nonzero(inside, as_tuple=True)
+            pj = alive[ml]
+            pidx = pl + c0
+            res = eval_pairs(P.index(pj), cam, opts, px_t[pidx], py_t[pidx], colors[pj])
+            _finish_pixels(res, pidx, pj, key, opts, bg, out_rgb, out_T, out_n, out_nc, knife, emitted, weights,
+                           c0, min(chunk, npix - c0))
+    return PixelResult(out_rgb, out_T, out_n, out_nc, knife, emitted, weights)
+
+
+def _near(x, thr, rel=1e-6):
+    return np.abs(x - thr) <= rel * abs(thr)
+
+
+def _finish_pixels(res, pidx, pj, key, opts, bg, out_rgb, out_T, out_n, out_nc, knife, emitted, weights,
+                   c0, cnt):
+    contrib = res["contrib"].numpy()
+    ok = res["ok"].numpy()
+    at = res["alpha"].numpy()
+    rt = res["rt"].numpy()
+    zc = res["zc"].numpy()
+    den = res["den"].numpy()
+    col = res["color"].numpy()
+    pidx = pidx.numpy()
+    pj = pj.numpy()
+    # knife-edge decisions (value within 1e-6 relative of a threshold)
+    edge = (_near(at, opts.alpha_min) & ok) | _near(np.abs(den), GRAZING) | _near(zc, opts.near)
+    order = np.argsort(pidx, kind="stable")
+    pidx_s = pidx[order]
+    bounds = np.searchsorted(pidx_s, np.arange(c0, c0 + cnt + 1))
+    for i in range(cnt):
+        sel = order[bounds[i]:bounds[i + 1]]
+        p = c0 + i
+        if edge[sel].any():
+            knife[p] = True
+        sel = sel[contrib[sel]]
+        out_nc[p] = sel.size
+        if sel.size == 0:
+            out_rgb[p] = bg
+            continue
+        if opts.cache_len >= EXACT:
+            seq = sorted(((float(rt[s]), int(pj[s])) for s in sel))
+            em = seq
+        else:
+            arrival = sorted(sel, key=lambda s: (int(key[pj[s]]), int(pj[s])))
+            em = cache_emit([(float(rt[s]), int(pj[s])) for s in arrival], opts.cache_len)
+        rts = np.array([e[0] for e in em])
+        if rts.size > 1:
+            srt = np.sort(rts)
+            if np.any(np.diff(srt) <= 1e-6 * np.abs(srt[1:])):
+                knife[p] = True
+        lut = {int(pj[s]): s for s in sel}
+        em_s = [lut[j] for _, j in em]
+        C, T, n, w = composite([at[s] for s in em_s], [col[s] for s in em_s], bg, opts.T_min)
+        # knife edge on the stopping test: T*(1-a) within 1e-6 of T_min for any tested step
+        Tt = 1.0
+        for s in em_s[:n + 1]:
+            test = Tt * (1 - at[s])
+            if _near(test, opts.T_min):
+                knife[p] = True
+            Tt = test
+        out_rgb[p] = C
+        out_T[p] = T
+        out_n[p] = n
+        emitted[p] = [int(pj[s]) for s in em_s[:n]]
+        weights[p] = w
+
+
+def render_image(scene, camera, opts: Opts, **kw) -> PixelResult:
+    H, W = camera.height, camera.width
+    yy, xx = np.mgrid[0:H, 0:W]
+    return render_pixels(scene, camera, opts, xx.ravel(), yy.ravel(), **kw)
+
+
+# ---------------------------------------------------------------------------------------------
+# Differentiable render of given pixels with the emission order fixed by the forward pass
+
+def render_loss_grad(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, target: np.ndarray,
+                     dL_drgb: Optional[np.ndarray] = None):
+    """Gradients of L = sum over the pixels of (C - target)^2 (or of sum(C * dL_drgb) when given)
+    with respect to every ABI parameter, by float64 autograd through Sec. 3.3 - 4.4 with the discrete
+    decisions (emission order, cutoffs, sector, Psi piece, max branch) taken from the forward pass."""
+    fwd = render_pixels(scene, camera, opts, px, py)
+    P = Prims.from_scene(scene)
+    leaves = {}
+    for name in ("mu", "q", "s", "theta", "eta", "tau", "o", "color"):
+        t = getattr(P, name).clone().requires_grad_(True)
+        leaves[name] = t
+        setattr(P, name, t)
+    cam = Cam.from_camera(camera)
+    pix_l, prim_l, slot_l = [], [], []
+    npix = len(px)
+    maxE = max([len(e) for e in fwd.emitted] + [1])
+    for p, em in enumerate(fwd.emitted):
+        for k, j in enumerate(em):
+            pix_l.append(p)
+            prim_l.append(j)
+            slot_l.append(k)
+    pix_i = torch.as_tensor(pix_l, dtype=torch.int64)
+    prim_i = torch.as_tensor(prim_l, dtype=torch.int64)
+    slot_i = torch.as_tensor(slot_l, dtype=torch.int64)
+    colors = prim_colors(P, cam)
+    pxt = torch.as_tensor(np.asarray(px), dtype=torch.int64)
+    pyt = torch.as_tensor(np.asarray(py), dtype=torch.int64)
+    if prim_i.numel():
+        res = eval_pairs(P.index(prim_i), cam, opts, pxt[pix_i], pyt[pix_i], colors[prim_i])
+        A = torch.zeros(npix, maxE, dtype=F64).index_put((pix_i, slot_i), res["alpha"])
+        Cc = torch.zeros(npix, maxE, 3, dtype=F64).index_put((pix_i, slot_i), res["color"])
+    else:
+        A = torch.zeros(npix, maxE, dtype=F64)
+        Cc = torch.zeros(npix, maxE, 3, dtype=F64)
+    one_minus = 1 - A
+    T_incl = torch.cumprod(one_minus, dim=1)
+    T_excl = torch.cat([torch.ones(npix, 1, dtype=F64), T_incl[:, :-1]], 1)
+    rgb = (T_excl[..., None] * A[..., None] * Cc).sum(1) + T_incl[:, -1:] * cam.bg
+    if dL_drgb is None:
+        tgt = torch.as_tensor(np.asarray(target, np.float64))
+        loss = ((rgb - tgt) ** 2).sum()
+    else:
+        loss = (rgb * torch.as_tensor(np.asarray(dL_drgb, np.float64))).sum()
+    loss.backward()
+    grads = {k: (v.grad if v.grad is not None else torch.zeros_like(v)).detach() for k, v in leaves.items()}
+    return float(loss.detach()), grads, rgb.detach().numpy(), fwd
+
+
+# ---------------------------------------------------------------------------------------------
+# Kernel culling: conservative support polygon and tile lists (Sec. 4.4 Kernel Culling)
+
+TILE = 16
+
+
+def _sbar(theta_abs, th_k, th_n, s_k, s_n):
+    dl = math.pi * (theta_abs - th_k) / (th_n - th_k)
+    w = (1 + math.cos(dl)) / (2 * s_k * s_k) + (1 - math.cos(dl)) / (2 * s_n * s_n)
+    return 1.0 / math.sqrt(w)
+
+
+def _chord(theta_abs, th_k, th_n, s_k, s_n):
+    """Distance from the centre to the segment e_k -- e_{k+1} along direction theta_abs."""
+    phi = theta_abs - th_k
+    dlt = th_n - th_k
+    f = (math.sin(dlt - phi) / s_k + math.sin(phi) / s_n) / math.sin(dlt)
+    return 1.0 / f
+
+
+def support_polygon(s: np.ndarray, theta: np.ndarray, c: float, subarcs: int = 2) -> np.ndarray:
+    """Star polygon (V, 2) in tangent coordinates that contains {E <= c^2}.
+
+    Since E is a convex combination of r1^2 and r2^2/sbar^2, E <= c^2 implies r1 <= c or
+    r2 <= c*sbar.  Along a direction theta both bounds are radii: c*chord(theta) and c*sbar(theta).
+    Within a sector sbar is monotone and chord is convex in theta, so over each sub-arc [a, b] the
+    larger of the two is at most rho = c * max(sbar, chord) at a or b.  The circular sector of
+    radius rho over [a, b] lies inside the quad (rho d(a), rho/cos(h) d(mid), rho d(b)) with the
+    centre, h = (b - a)/2; the union of these quads in angular order is the polygon."""
+    K = s.shape[0]
+    verts = []
+    for k in range(K):
+        th_k = float(theta[k])
+        th_n = float(theta[k + 1]) if k + 1 < K else float(theta[0]) + TWO_PI
+        s_k = float(s[k])
+        s_n = float(s[(k + 1) % K])
+        for j in range(subarcs):
+            a = th_k + (th_n - th_k) * j / subarcs
+            b = th_k + (th_n - th_k) * (j + 1) / subarcs
+            h = 0.5 * (b - a)
+            mid = a + h
+            rho = c * max(_sbar(a, th_k, th_n, s_k, s_n), _sbar(b, th_k, th_n, s_k, s_n),
+                          _chord(a, th_k, th_n, s_k, s_n), _chord(b, th_k, th_n, s_k, s_n))
+            rm = rho / math.cos(h)
+            verts.append((rho * math.cos(a), rho * math.sin(a)))
+            verts.append((rm * math.cos(mid), rm * math.sin(mid)))
+            verts.append((rho * math.cos(b), rho * math.sin(b)))
+    return np.array(verts)
+
+
+def paper_polygon(s: np.ndarray, theta: np.ndarray, o: float, tau: float) -> np.ndarray:
+    """The polygon of Sec. 4.4 as printed: endpoints at s_k * sqrt(-log Psi^{-1}(e^{-9}/o)).
+    Not conservative (the L2 contours bulge past the chords)."""
+    y = math.exp(-9.0) / o
+    g = float(psi_inv(torch.tensor(min(y, 1.0), dtype=F64), torch.tensor(tau, dtype=F64)))
+    sc = s.astype(np.float64) * math.sqrt(max(-math.log(g), 0.0))
+    return np.stack([sc * np.cos(theta.astype(np.float64)), sc * np.sin(theta.astype(np.float64))], -1)
+
+
+def _clip_near(poly3: np.ndarray, near: float) -> np.ndarray:
+    """Sutherland-Hodgman clip of a camera-space polygon to z >= near."""
+    out = []
+    nv = len(poly3)
+    for i in range(nv):
+        a = poly3[i]
+        b = poly3[(i + 1) % nv]
+        ain = a[2] >= near
+        bin_ = b[2] >= near
+        if ain:
+            out.append(a)
+        if ain != bin_:
+            t = (near - a[2]) / (b[2] - a[2])
+            out.append(a + t * (b - a))
+    return np.array(out).reshape(-1, 3)
+
+
+def row_spans(poly2: np.ndarray, disk, W: int, H: int) -> Dict[int, Tuple[int, int]]:
+    """Tile columns [i0, i1] per tile row touched by a screen polygon (and an optional square
+    (cx, cy, r) around the projected centre for the low-pass support).  For a tile row the slab of
+    pixel-centre heights [16j + 0.5, min(16j + 15.5, H - 0.5)] is intersected with every edge; the
+    x-extent of the clipped edges (clamped to the pixel centres [0.5, W - 0.5]) picks the tiles whose
+    centre columns it overlaps."""
+    tx = (W + TILE - 1) // TILE
+    ty = (H + TILE - 1) // TILE
+    spans = {}
+    nv = len(poly2)
+    for j in range(ty):
+        ya = TILE * j + 0.5
+        yb = min(TILE * j + TILE - 0.5, H - 0.5)
+        lo, hi = math.inf, -math.inf
+        for e in range(nv):
+            x0, y0 = poly2[e]
+            x1, y1 = poly2[(e + 1) % nv]
+            if max(y0, y1) < ya or min(y0, y1) > yb:
+                continue
+            if y0 == y1:
+                xa, xb = x0, x1
+            else:
+                ta = (ya - y0) / (y1 - y0)
+                tb = (yb - y0) / (y1 - y0)
+                tlo = max(0.0, min(ta, tb))
+                thi = min(1.0, max(ta, tb))
+                xa = x0 + tlo * (x1 - x0)
+                xb = x0 + thi * (x1 - x0)
+            lo = min(lo, xa, xb)
+            hi = max(hi, xa, xb)
+        if disk is not None:
+            dcx, dcy, r = disk
+            if dcy + r >= ya and dcy - r <= yb:
+                lo = min(lo, dcx - r)
+                hi = max(hi, dcx + r)
+        lo = max(lo, 0.5)
+        hi = min(hi, W - 0.5)
+        if lo > hi:
+            continue
+        i0 = max(math.ceil((lo - (TILE - 0.5)) / TILE), 0)
+        i1 = min(math.floor((hi - 0.5) / TILE), tx - 1)
+        if i0 <= i1:
+            spans[j] = (i0, i1)
+    return spans
+
+
+def primitive_tiles(scene, camera, opts: Opts, j: int) -> List[int]:
+    """Tile ids (row-major, tile_x fastest) that primitive j is binned to."""
+    W, H = camera.width, camera.height
+    tx = (W + TILE - 1) // TILE
+    ty = (H + TILE - 1) // TILE
+    P = Prims.from_scene(scene.subset([j]))
+    cam = Cam.from_camera(camera)
+    if bool(culled_mask(P, cam, opts)[0]):
+        return []
+    if opts.cull_mode == 2:
+        return list(range(tx * ty))
+    R = quat_to_rotmat(P.q)[0].numpy()
+    mu = P.mu[0].numpy()
+    Rc = cam.R.numpy()
+    tc = cam.t.numpy()
+    s = P.s[0].numpy()
+    th = P.theta[0].numpy()
+    o = float(P.o[0])
+    tau = float(P.tau[0])
+    if opts.cull_mode == 1:
+        poly = paper_polygon(s, th, o, tau)
+    else:
+        c = float(calibrated_radius(torch.tensor(o, dtype=F64), torch.tensor(tau, dtype=F64), opts.alpha_min))
+        poly = support_polygon(s, th, c)
+    world = mu[None, :] + poly[:, :1] * R[:, 0][None, :] + poly[:, 1:2] * R[:, 1][None, :]
+    camp = world @ Rc.T + tc[None, :]
+    camp = _clip_near(camp, opts.near)
+    if len(camp):
+        scr = np.stack([cam.fx * camp[:, 0] / camp[:, 2] + cam.cx, cam.fy * camp[:, 1] / camp[:, 2] + cam.cy], -1)
+    else:
+        scr = np.zeros((0, 2))
+    disk = None
+    if opts.lowpass_sl > 0:
+        mc = Rc @ mu + tc
+        r = opts.lowpass_sl * math.sqrt(2.0 * math.log(max(o / opts.alpha_min, 1.0)))
+        disk = (cam.fx * mc[0] / mc[2] + cam.cx, cam.fy * mc[1] / mc[2] + cam.cy, r)
+    spans = row_spans(scr, disk, W, H)
+    out = []
+    for row in sorted(spans):
+        i0, i1 = spans[row]
+        out.extend(row * tx + i for i in range(i0, i1 + 1))
+    return out
+
+
+def tile_lists(scene, camera, opts: Opts, prim_ids: Optional[Sequence[int]] = None):
+    """Reference binning: for every tile, the primitives binned to it ordered by (depth key, index).
+    Returns (tiles dict -> list of (key, j)), per-primitive tile lists, and the depth keys (uint32)."""
+    ids = range(scene.n) if prim_ids is None else prim_ids
+    key = centre_depth_f32(scene.mu, camera).view(np.uint32)
+    per_prim = {}
+    tiles: Dict[int, List[Tuple[int, int]]] = {}
+    for j in ids:
+        tl = primitive_tiles(scene, camera, opts, int(j))
+        per_prim[int(j)] = tl
+        for t in tl:
+            tiles.setdefault(t, []).append((int(key[j]), int(j)))
+    for t in tiles:
+        tiles[t].sort()
+    return tiles, per_prim, key

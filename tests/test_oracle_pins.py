@@ -1,0 +1,454 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix (no GPU needed).
+
+Each test names the passage it pins.  None of them re-types the oracle's own formula: they use
+closed forms (2D Gaussian, isotropic Gaussian, L1 diamond), independent formulations (linear
+solve for the ray-plane hit, heapq for the cache, scipy for spherical harmonics), invariants
+(telescoping weights, Psi identities) and brute force on tiny inputs.
+"""
+import heapq
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from drk_synth import Camera, Scene, config_c1, intrinsics_hfov
+from oracle import drk_oracle as O
+
+F64 = torch.float64
+rng_global = np.random.default_rng(1234)
+
+
+def _t(x):
+    return torch.as_tensor(np.asarray(x, np.float64))
+
+
+def _alpha(u, v, s, th, eta, tau, o):
+    L = len(u)
+    return O.drk_alpha_uv(_t(u), _t(v), _t(np.tile(s, (L, 1))), _t(np.tile(th, (L, 1))),
+                          _t(np.full(L, eta)), _t(np.full(L, tau)), _t(np.full(L, o))).numpy()
+
+
+# ---- Sec. 4.1, "2D Gaussian as a special case" (with the printed cos^2 -> sin^2 typo corrected)
+def test_p1_gaussian_reduction():
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        su, sv = rng.uniform(0.05, 2.0, 2)
+        o = rng.uniform(0.1, 1.0)
+        u, v = rng.normal(0, 1.5, (2, 500))
+        a = _alpha(u, v, [su, sv, su, sv], [0, math.pi / 2, math.pi, 1.5 * math.pi], 0.0, 0.0, o)
+        ref = o * np.exp(-0.5 * (u ** 2 / su ** 2 + v ** 2 / sv ** 2))   # Eq. (3), 2D-GS
+        np.testing.assert_allclose(a, ref, rtol=1e-12, atol=1e-300)
+
+
+# ---- Sec. 4.1: equal radial lengths give an isotropic Gaussian for any basis angles
+def test_p2_equal_scales_isotropic():
+    rng = np.random.default_rng(2)
+    for K in (3, 5, 8, 16):
+        th = np.sort(rng.uniform(0, 2 * math.pi, K))
+        while np.max(np.diff(np.r_[th, th[0] + 2 * math.pi])) >= math.pi:
+            th = np.sort(rng.uniform(0, 2 * math.pi, K))
+        s = rng.uniform(0.1, 1.0)
+        u, v = rng.normal(0, 1, (2, 400))
+        a = _alpha(u, v, np.full(K, s), th, 0.0, 0.0, 1.0)
+        np.testing.assert_allclose(a, np.exp(-(u * u + v * v) / (2 * s * s)), rtol=1e-12)
+
+
+# ---- Sec. 4.2: with eta = 1, equal lengths and axis bases the unit L1 ball is the diamond
+def test_p3_l1_diamond():
+    rng = np.random.default_rng(3)
+    s = 0.7
+    u, v = rng.normal(0, 1, (2, 400))
+    a = _alpha(u, v, np.full(4, s), [0, math.pi / 2, math.pi, 1.5 * math.pi], 1.0, 0.0, 1.0)
+    np.testing.assert_allclose(a, np.exp(-0.5 * ((np.abs(u) + np.abs(v)) / s) ** 2), rtol=1e-12)
+
+
+# ---- Sec. 4.2, Eq. (L1): the L1 level set through the endpoints is the straight segment e_k e_{k+1};
+# a point lam*e_k + mu*e_{k+1} (lam, mu >= 0) has r1 = lam + mu, for arbitrary angles and lengths.
+def test_l1_segment_general():
+    rng = np.random.default_rng(4)
+    for K in (3, 8, 16):
+        for _ in range(5):
+            th = np.sort(rng.uniform(0, 2 * math.pi, K))
+            while np.max(np.diff(np.r_[th, th[0] + 2 * math.pi])) >= math.pi:
+                th = np.sort(rng.uniform(0, 2 * math.pi, K))
+            s = rng.uniform(0.2, 2.0, K)
+            e = np.stack([s * np.cos(th), s * np.sin(th)], -1)
+            k = rng.integers(0, K, 200)
+            lam, mu = rng.uniform(0.01, 2.0, (2, 200))
+            p = lam[:, None] * e[k] + mu[:, None] * e[(k + 1) % K]
+            a = _alpha(p[:, 0], p[:, 1], s, th, 1.0, 0.0, 1.0)
+            np.testing.assert_allclose(a, np.exp(-0.5 * (lam + mu) ** 2), rtol=1e-10)
+
+
+# ---- Sec. 4.1: inside a sector at phi = delta/3 the cosine weight is cos(pi/3) = 1/2, so
+# 1/sbar^2 = 3/(4 s_k^2) + 1/(4 s_{k+1}^2); on a basis direction it is 1/s_k^2.
+def test_l2_interpolation_points():
+    rng = np.random.default_rng(5)
+    K = 8
+    th = np.sort(rng.uniform(0, 2 * math.pi, K))
+    while np.max(np.diff(np.r_[th, th[0] + 2 * math.pi])) >= math.pi:
+        th = np.sort(rng.uniform(0, 2 * math.pi, K))
+    s = rng.uniform(0.2, 2.0, K)
+    for k in range(K):
+        t0 = th[k]
+        t1 = th[k + 1] if k + 1 < K else th[0] + 2 * math.pi
+        ang = t0 + (t1 - t0) / 3
+        r = rng.uniform(0.1, 2.0)
+        a = _alpha([r * math.cos(ang)], [r * math.sin(ang)], s, th, 0.0, 0.0, 1.0)[0]
+        w = 3 / (4 * s[k] ** 2) + 1 / (4 * s[(k + 1) % K] ** 2)
+        assert a == pytest.approx(math.exp(-0.5 * r * r * w), rel=1e-12)
+        a = _alpha([r * math.cos(t0)], [r * math.sin(t0)], s, th, 0.0, 0.0, 1.0)[0]
+        assert a == pytest.approx(math.exp(-0.5 * r * r / s[k] ** 2), rel=1e-10)
+
+
+# ---- Sec. 4.3 sharpening: continuity, fixed points, symmetry, slopes, identity at tau = 0
+@pytest.mark.parametrize("tau", [-0.9, -0.1, 0.0, 0.3, 0.5, 0.99])
+def test_p4_psi_identities(tau):
+    t = torch.tensor(tau, dtype=F64)
+    for gval, want in ((0.0, 0.0), (0.5, 0.5), (1.0, 1.0)):
+        assert float(O.psi(torch.tensor(gval, dtype=F64), t)) == pytest.approx(want, abs=1e-14)
+    g = torch.linspace(0, 1, 20001, dtype=F64)
+    y = O.psi(g, t)
+    assert torch.all(torch.diff(y) > 0)                                  # strictly increasing
+    np.testing.assert_allclose((1 - O.psi(1 - g, t)).numpy(), y.numpy(), atol=1e-14)  # point symmetry
+    for b in ((1 + tau) / 4, (3 - tau) / 4):                               # continuity at breakpoints
+        lo = O.psi(torch.tensor(b - 1e-12, dtype=F64), t)
+        hi = O.psi(torch.tensor(b, dtype=F64), t)
+        steep = max((1 + tau) / (1 - tau), (1 - tau) / (1 + tau))
+        assert abs(float(hi - lo)) <= 1.01e-12 * steep + 1e-15
+    slope_in = float((O.psi(torch.tensor(0.01, dtype=F64), t)) / 0.01)
+    assert slope_in == pytest.approx((1 - tau) / (1 + tau), rel=1e-12)
+    eps = (1 - abs(tau)) / 10            # inside the middle piece [(1+tau)/4, (3-tau)/4)
+    mid = torch.tensor([0.5 - eps, 0.5 + eps], dtype=F64)
+    ym = O.psi(mid, t)
+    assert float((ym[1] - ym[0]) / (2 * eps)) == pytest.approx((1 + tau) / (1 - tau), rel=1e-9)
+    yy = torch.linspace(0, 1, 1001, dtype=F64)
+    np.testing.assert_allclose(O.psi(O.psi_inv(yy, t), t).numpy(), yy.numpy(), atol=1e-13)
+    if tau == 0.0:
+        np.testing.assert_allclose(y.numpy(), g.numpy(), atol=0)
+
+
+# ---- Sec. 4.4 (calibrated length, corrected): on the level set E = c^2 the opacity equals alpha_min
+def test_calibrated_radius_level():
+    rng = np.random.default_rng(6)
+    amin = 1.0 / 255.0
+    o = _t(rng.uniform(0.01, 0.99, 1000))
+    tau = _t(rng.uniform(-0.5, 0.99, 1000))
+    c = O.calibrated_radius(o, tau, amin)
+    a = o * O.psi(torch.exp(-0.5 * c * c), tau)
+    np.testing.assert_allclose(a.numpy(), amin, rtol=1e-10)
+
+
+# ---- Real SH against scipy's complex harmonics (Y_lm real = sqrt2 (-1)^m Re/Im of Y_l^|m|)
+def test_real_sh_matches_scipy():
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(7)
+    d = rng.normal(size=(300, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    polar = np.arccos(np.clip(d[:, 2], -1, 1))
+    azim = np.arctan2(d[:, 1], d[:, 0])
+    Y = O.real_sh(3, _t(d)).numpy()
+    for l in range(4):
+        for m in range(-l, l + 1):
+            if m == 0:
+                ref = sph_harm_y(l, 0, polar, azim).real
+            elif m > 0:
+                ref = math.sqrt(2) * (-1) ** m * sph_harm_y(l, m, polar, azim).real
+            else:
+                ref = math.sqrt(2) * (-1) ** m * sph_harm_y(l, -m, polar, azim).imag
+            np.testing.assert_allclose(Y[:, l * l + l + m], ref, atol=1e-12, err_msg=f"l={l} m={m}")
+
+
+# ---- Sec. 3.3 ray-plane intersection: (u, v) and r_t against a 3x3 linear solve
+#      r_o + t r_d = mu + u t_u + v t_v
+def test_hit_against_linear_solve():
+    rng = np.random.default_rng(8)
+    W = H = 32
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+    Rw, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    Rw = (Rw * np.sign(np.linalg.det(Rw))).astype(np.float32)
+    eye = np.array([0.3, -0.2, -5.0])
+    t = (-(Rw.astype(np.float64) @ eye)).astype(np.float32)
+    cam = O.Cam.from_camera(Camera(W, H, fx, fy, cx, cy, Rw, t))
+    n = 40
+    mu = (eye + (Rw.astype(np.float64).T @ np.array([0, 0, 5.0])) + rng.normal(0, 0.5, (n, 3))).astype(np.float32)
+    q = rng.normal(size=(n, 4)).astype(np.float32)
+    P = O.Prims(_t(mu), _t(q), _t(np.full((n, 4), 0.5)), _t(np.tile([0, 1.5, 3, 4.5], (n, 1))),
+                _t(np.zeros(n)), _t(np.zeros(n)), _t(np.full(n, 0.9)), _t(np.ones((n, 3))), -1)
+    px = torch.as_tensor(rng.integers(0, W, n))
+    py = torch.as_tensor(rng.integers(0, H, n))
+    res = O.eval_pairs(P, cam, O.Opts(lowpass_sl=0.0), px, py, P.color)
+    Rq = O.quat_to_rotmat(_t(q)).numpy()
+    ro = cam.position.numpy()
+    for i in range(n):
+        dcam = np.array([(px[i].item() + 0.5 - cam.cx) / cam.fx, (py[i].item() + 0.5 - cam.cy) / cam.fy, 1.0])
+        rd = cam.R.numpy().T @ dcam
+        rd /= np.linalg.norm(rd)
+        A = np.stack([rd, -Rq[i][:, 0], -Rq[i][:, 1]], 1)
+        tt, uu, vv = np.linalg.solve(A, mu[i].astype(np.float64) - ro)
+        assert res["u"][i].item() == pytest.approx(uu, rel=1e-9, abs=1e-12)
+        assert res["v"][i].item() == pytest.approx(vv, rel=1e-9, abs=1e-12)
+        assert res["rt"][i].item() == pytest.approx(tt, rel=1e-9)
+
+
+# ---- P5 analytic footprint: one fronto-parallel Gaussian-case DRK at depth d in front of a
+# camera at the origin; u = d (x + 0.5 - cx)/fx, v = d (y + 0.5 - cy)/fy exactly, and the image is
+# alpha*c + (1 - alpha)*bg with alpha from Eq. (3) (clamped and cut as the 3D-GS cutoffs say).
+def test_p5_single_primitive_footprint():
+    W, H = 48, 40
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+    d, su, sv, o = 3.0, 0.4, 0.25, 0.8
+    col = np.array([0.9, 0.4, 0.1], np.float32)
+    bg = np.array([0.1, 0.2, 0.3], np.float32)
+    sc = Scene(np.array([[0.0], [0.0], [d]], np.float32), np.array([[1.0], [0], [0], [0]], np.float32),
+               np.array([[su], [sv], [su], [sv]], np.float32),
+               np.array([[0.0], [math.pi / 2], [math.pi], [1.5 * math.pi]], np.float32),
+               np.zeros(1, np.float32), np.zeros(1, np.float32), np.array([o], np.float32), col[:, None], -1)
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.zeros(3, np.float32), bg)
+    opts = O.Opts(lowpass_sl=0.0)
+    r = O.render_image(sc, cam, opts)
+    yy, xx = np.mgrid[0:H, 0:W]
+    u = d * (xx + 0.5 - float(cx)) / float(fx)
+    v = d * (yy + 0.5 - float(cy)) / float(fy)
+    su32, sv32, o32 = (float(np.float32(x)) for x in (su, sv, o))
+    a = o32 * np.exp(-0.5 * (u ** 2 / su32 ** 2 + v ** 2 / sv32 ** 2))
+    a = np.minimum(a, opts.alpha_max)
+    a = np.where(a >= opts.alpha_min, a, 0.0).ravel()
+    ref = a[:, None] * col.astype(np.float64)[None] + (1 - a)[:, None] * bg.astype(np.float64)[None]
+    np.testing.assert_allclose(r.rgb, ref, atol=1e-12)
+    np.testing.assert_allclose(r.T, 1 - a, atol=1e-12)
+
+
+# ---- Eq. (1): two primitives in front of each other composite in closed form
+def test_two_layer_composite_closed_form():
+    C, T, n, w = O.composite([0.3, 0.6], [[1, 0, 0], [0, 1, 0]], [0, 0, 1], 1e-4)
+    assert C == pytest.approx([0.3, 0.7 * 0.6, 0.7 * 0.4])
+    assert T == pytest.approx(0.28) and n == 2
+    # stop rule: T * (1 - a) < T_min ends the pixel without adding that contribution
+    C, T, n, w = O.composite([0.99, 0.99, 0.99], [[1, 1, 1]] * 3, [0, 0, 0], 2e-4)
+    assert n == 1 and T == pytest.approx(0.01) and C == pytest.approx([0.99] * 3)
+    C, T, n, w = O.composite([0.99, 0.99, 0.99], [[1, 1, 1]] * 3, [0, 0, 0], 5e-5)
+    assert n == 2 and T == pytest.approx(1e-4)
+
+
+# ---- P6 telescoping: sum_i T_i alpha_i + T_final = 1 on the full 64x64 workload
+def test_p6_weights_telescope_c1():
+    scene, cam = config_c1()
+    r = O.render_image(scene, cam, O.Opts())
+    w = np.array([sum(x) for x in r.weights])
+    np.testing.assert_allclose(w + r.T, 1.0, atol=1e-12)
+    assert r.n_contrib.max() > 3           # the workload really overlaps
+
+
+# ---- P7 cache semantics (Algorithm 1) against a bounded heap, plus its special cases
+def _heap_emit(seq, L):
+    h, out = [], []
+    for i, (rt, j) in enumerate(seq):
+        if len(h) >= L:
+            out.append(heapq.heappop(h)[2:])
+        heapq.heappush(h, (rt, i, rt, j))
+    while h:
+        out.append(heapq.heappop(h)[2:])
+    return [tuple(x) for x in out]
+
+
+def test_p7_cache_semantics():
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        n = int(rng.integers(0, 30))
+        L = int(rng.integers(1, 12))
+        rts = rng.integers(0, 10, n).astype(float)        # many ties
+        seq = [(float(rts[i]), i) for i in range(n)]
+        assert O.cache_emit(seq, L) == _heap_emit(seq, L)
+        assert O.cache_emit(seq, 1) == seq                                  # L = 1: arrival order
+        assert O.cache_emit(seq, max(n, 1)) == sorted(seq, key=lambda x: (x[0], x[1]))  # L >= n: exact
+    s = [(float(i), i) for i in range(20)]
+    assert O.cache_emit(s, 8) == s                                          # sorted input unchanged
+    r = [(float(8 - i), i) for i in range(8)]
+    assert O.cache_emit(r, 8) == sorted(r)                                  # reversed input, n <= L
+
+
+# ---- P8: fronto-parallel scene (all normals along the optical axis): r_t order equals centre-depth
+# order, so the 8-slot cache reproduces the exact per-pixel sort.
+def test_p8_frontoparallel_cache_equals_exact():
+    scene, cam = config_c1()
+    sc = Scene(scene.mu.copy(), np.tile(np.array([[1.0], [0], [0], [0]], np.float32), (1, scene.n)),
+               scene.scale, scene.theta, scene.eta, scene.tau, scene.opacity, scene.color, -1)
+    a = O.render_image(sc, cam, O.Opts(cache_len=8))
+    b = O.render_image(sc, cam, O.Opts(cache_len=O.EXACT))
+    c = O.render_image(sc, cam, O.Opts(cache_len=1))
+    np.testing.assert_allclose(a.rgb, b.rgb, atol=1e-13)
+    np.testing.assert_allclose(c.rgb, b.rgb, atol=1e-13)
+
+
+# ---- P9 culling is conservative: every sampled tangent-plane point with E <= c^2 lies inside
+# the support polygon, and binning the pixels by the tile lists changes no pixel.
+def _inside(poly, pts):
+    x, y = pts[:, 0], pts[:, 1]
+    inside = np.zeros(len(pts), bool)
+    n = len(poly)
+    for i in range(n):
+        x0, y0 = poly[i]
+        x1, y1 = poly[(i + 1) % n]
+        cond = ((y0 > y) != (y1 > y))
+        xint = x0 + (y - y0) * (x1 - x0) / np.where(y1 != y0, y1 - y0, 1)
+        inside ^= cond & (x < xint)
+    return inside
+
+
+def test_p9_support_polygon_contains_support():
+    rng = np.random.default_rng(10)
+    scene, _ = config_c1()
+    for j in range(60):
+        s = scene.scale[:, j].astype(np.float64)
+        th = scene.theta[:, j].astype(np.float64)
+        o, tau, eta = float(scene.opacity[j]), float(scene.tau[j]), float(scene.eta[j])
+        c = float(O.calibrated_radius(_t(o), _t(tau), 1 / 255))
+        poly = O.support_polygon(s, th, c)
+        R = c * s.max() * 1.05
+        pts = rng.uniform(-R, R, (20000, 2))
+        a = _alpha(pts[:, 0], pts[:, 1], s, th, eta, tau, o)
+        supp = a >= 1 / 255
+        assert supp.any()
+        assert _inside(poly, pts[supp]).all(), j
+
+
+def test_p9_binning_changes_no_pixel_c1():
+    scene, cam = config_c1()
+    opts = O.Opts()
+    tiles, per, key = O.tile_lists(scene, cam, opts)
+    members = {t: {j for _, j in v} for t, v in tiles.items()}
+    a = O.render_image(scene, cam, opts)
+    b = O.render_image(scene, cam, opts, tile_members=members)
+    np.testing.assert_array_equal(a.rgb, b.rgb)
+    np.testing.assert_array_equal(a.n_emit, b.n_emit)
+
+
+def test_prefilter_is_lossless_c1():
+    scene, cam = config_c1()
+    a = O.render_image(scene, cam, O.Opts())
+    b = O.render_image(scene, cam, O.Opts(), prefilter=False)
+    np.testing.assert_array_equal(a.rgb, b.rgb)
+
+
+# ---- The paper's printed endpoint polygon (Sec. 4.4) is not conservative: it misses support.
+def test_paper_polygon_misses_support():
+    rng = np.random.default_rng(11)
+    scene, _ = config_c1()
+    missed = 0
+    for j in range(30):
+        s = scene.scale[:, j].astype(np.float64)
+        th = scene.theta[:, j].astype(np.float64)
+        o, tau, eta = float(scene.opacity[j]), float(scene.tau[j]), float(scene.eta[j])
+        poly = O.paper_polygon(s, th, o, tau)
+        R = 6 * s.max()
+        pts = rng.uniform(-R, R, (20000, 2))
+        supp = _alpha(pts[:, 0], pts[:, 1], s, th, eta, tau, o) >= 1 / 255
+        missed += int((~_inside(poly, pts[supp])).sum())
+    assert missed > 0
+
+
+# ---- P10 gradients: Eq. (3) closed-form derivatives in the Gaussian case, and central finite
+# differences of the full render for a small scene.
+def test_p10_gaussian_scale_gradient_closed_form():
+    rng = np.random.default_rng(12)
+    su, sv, o = 0.6, 0.3, 0.7
+    u, v = rng.normal(0, 0.5, (2, 50))
+    s = torch.tensor([su, sv, su, sv], dtype=F64, requires_grad=True)
+    th = torch.tensor([0, math.pi / 2, math.pi, 1.5 * math.pi], dtype=F64)
+    L = len(u)
+    a = O.drk_alpha_uv(_t(u), _t(v), s.expand(L, 4), th.expand(L, 4), torch.zeros(L, dtype=F64),
+                       torch.zeros(L, dtype=F64), torch.full((L,), o, dtype=F64))
+    a.sum().backward()
+    g = o * np.exp(-0.5 * (u ** 2 / su ** 2 + v ** 2 / sv ** 2))
+    dsu = (g * u ** 2 / su ** 3).sum()
+    dsv = (g * v ** 2 / sv ** 3).sum()
+    gs = s.grad.numpy()
+    assert gs[0] + gs[2] == pytest.approx(dsu, rel=1e-10)
+    assert gs[1] + gs[3] == pytest.approx(dsv, rel=1e-10)
+
+
+def _small_scene(seed, n=12, sh=False):
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-0.5, 0.5, (3, n)).astype(np.float32)
+    q = rng.normal(size=(4, n)).astype(np.float32)
+    K = 8
+    from drk_synth import draw_angles
+    th = draw_angles(rng, K, n)
+    s = np.exp(rng.uniform(math.log(0.15), math.log(0.6), (K, n))).astype(np.float32)
+    eta = rng.uniform(0, 1, n).astype(np.float32)
+    tau = rng.uniform(0, 0.9, n).astype(np.float32)
+    o = rng.uniform(0.3, 0.95, n).astype(np.float32)
+    if sh:
+        col = rng.normal(0, 0.1, (48, n)).astype(np.float32)
+        col[:3] = rng.uniform(0, 1, (3, n))
+        return Scene(mu, q, s, th, eta, tau, o, col, 3)
+    return Scene(mu, q, s, th, eta, tau, o, rng.uniform(0, 1, (3, n)).astype(np.float32), -1)
+
+
+def test_p10_render_gradient_finite_differences():
+    sc = _small_scene(13, sh=True)
+    W = H = 16
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.array([0, 0, 2.5], np.float32),
+                 np.array([0.2, 0.1, 0.0], np.float32))
+    yy, xx = np.mgrid[0:H, 0:W]
+    px, py = xx.ravel(), yy.ravel()
+    rng = np.random.default_rng(14)
+    target = rng.uniform(0, 1, (len(px), 3))
+    opts = O.Opts()
+    loss, grads, rgb, fwd = O.render_loss_grad(sc, cam, opts, px, py, target)
+    assert loss > 0
+    # loss as a function of float64 parameters, emission order / decisions frozen as in the forward
+    base = O.Prims.from_scene(sc)
+
+    def loss_of(P):
+        with torch.no_grad():
+            colors = O.prim_colors(P, O.Cam.from_camera(cam))
+            out = np.zeros((len(px), 3))
+            for p, em in enumerate(fwd.emitted):
+                T = 1.0
+                for j in em:
+                    r = O.eval_pairs(P.index(torch.tensor([j])), O.Cam.from_camera(cam), opts,
+                                     torch.tensor([px[p]]), torch.tensor([py[p]]), colors[[j]])
+                    a = float(r["alpha"][0])
+                    out[p] += T * a * colors[j].numpy()
+                    T *= (1 - a)
+                out[p] += T * cam.bg.astype(np.float64)
+            return ((out - target) ** 2).sum()
+
+    assert loss_of(base) == pytest.approx(loss, rel=1e-12)
+    checked = 0
+    for name, shape_idx in (("mu", (0, 1)), ("q", (1, 2)), ("s", (2, 3)), ("theta", (3, 4)), ("eta", (4,)),
+                            ("tau", (5,)), ("o", (6,)), ("color", (7, 0, 1))):
+        g = grads[name]
+        flat_idx = int(torch.argmax(g.abs().reshape(-1)))
+        P1 = O.Prims.from_scene(sc)
+        P2 = O.Prims.from_scene(sc)
+        x = getattr(base, name).reshape(-1)[flat_idx].item()
+        h = 1e-6 * max(1.0, abs(x))
+        getattr(P1, name).reshape(-1)[flat_idx] += h
+        getattr(P2, name).reshape(-1)[flat_idx] -= h
+        fd = (loss_of(P1) - loss_of(P2)) / (2 * h)
+        assert g.reshape(-1)[flat_idx].item() == pytest.approx(fd, rel=1e-5, abs=1e-8), name
+        checked += 1
+    assert checked == 8
+
+
+# ---- P11: 74 float32 values per DRK (mu 3, q 4, s 8, theta 8, eta, tau, o, SH3 48) reproduce the
+# model sizes of Table 2 (counts printed to three significant figures).
+def test_p11_record_size_matches_table2():
+    path = os.path.join(os.path.dirname(__file__), "golden", "table2_model_sizes.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    floats = 3 + 4 + 8 + 8 + 1 + 1 + 1 + 48
+    assert floats == 74
+    for name, count_k, mb in rows:
+        est = float(count_k) * 1e3 * floats * 4 / 1e6
+        # counts carry 2-3 significant figures; 1 MB = 1e6 bytes
+        assert abs(est - float(mb)) / float(mb) < 0.012, (name, est, mb)
+    # the same accounting for 3D-GS (59 floats: mu 3, q 4, s 3, o, SH3 48): 336K -> 79.7 MB in Table 2
+    assert abs(336e3 * 59 * 4 / 1e6 - 79.7) / 79.7 < 0.012
