@@ -1,0 +1,209 @@
+/*
+ * drk.h -- C ABI of libdrk, a tile-based differentiable rasterizer for Deformable Radial Kernel
+ * (DRK) primitives on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Deformable Radial Kernel Splatting" (arXiv 2412.11752).  A DRK is a planar primitive
+ * with centre mu, rotation q, K radial bases (lengths s_k, polar angles theta_k), an L1/L2 blend
+ * weight eta, a sharpness tau, an opacity o and a colour (Sec. 4).  A pixel's colour is the
+ * front-to-back alpha blend of the kernels its ray hits (Eq. 1, Sec. 3.1), evaluated at the
+ * ray-plane intersection (Sec. 3.3).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns a drk_status.  DRK_OK is 0.  drk_last_error() returns a thread-local
+ *    message for the last failure on the calling thread.  Nothing throws across the ABI.
+ *  - Array arguments are DEVICE pointers (hipMalloc'd or torch tensors on the GPU) unless marked
+ *    "host".  They are borrowed: the caller keeps them alive until the work enqueued on the given
+ *    stream has completed.  Outputs are caller-allocated.
+ *  - Layout: structure-of-arrays, float32, contiguous, primitive index fastest ([rows][n]).
+ *  - The only calls that allocate device memory are drk_ws_create and drk_serve_create /
+ *    drk_serve_add_scene; free with drk_ws_destroy / drk_serve_destroy.
+ *  - Asynchronous errors (pair-buffer overflow) are recorded in a device status word and reported
+ *    by drk_ws_status, which synchronises the stream it is given.
+ *  - `stream` is a hipStream_t passed as void* (0 = the null stream).
+ */
+#ifndef DRK_H
+#define DRK_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DRK_OK = 0,
+  DRK_EINVAL = 1,     /* invalid argument or (validate mode) invalid primitive */
+  DRK_ENOMEM = 2,     /* device allocation failed, or a request can never fit the HBM budget */
+  DRK_EOVERFLOW = 3,  /* tile-pair buffer too small; drk_ws_status reports the size needed */
+  DRK_EAGAIN = 4,     /* try again: request queue full / request still running */
+  DRK_ENOTFOUND = 5,  /* unknown request or scene id */
+  DRK_EDEVICE = 6     /* HIP runtime error */
+} drk_status;
+
+/* Scene: N primitives with K bases (Sec. 4, parameter set Theta).
+ *   mu      [3][n]  centres (world)
+ *   q       [4][n]  rotation quaternion (w, x, y, z); need not be unit length.  The columns of
+ *                   R(q) are the local u axis, v axis and plane normal (3D-GS rotation, Sec. 3.1).
+ *   scale   [K][n]  radial basis lengths s_k > 0 (Sec. 4.1)
+ *   theta   [K][n]  basis polar angles, ascending in [0, 2*pi), every gap (wrap included) < pi
+ *   eta     [n]     L1/L2 blend weight in [0, 1] (Sec. 4.2)
+ *   tau     [n]     sharpness in (-1, 1) (Sec. 4.3)
+ *   opacity [n]     o in (0, 1]
+ *   color   [3][n] (color_mode 0, RGB) or [3*(sh_degree+1)^2][n] (color_mode 1, real SH, row
+ *           3*coef + channel, coefficient index l*l + l + m).  Colour = SH(view dir) + 0.5,
+ *           clamped at 0, view dir = normalize(mu - camera centre).                          */
+typedef struct drk_scene {
+  int64_t n;
+  int32_t K;            /* 3 <= K <= 16 */
+  int32_t color_mode;   /* 0 = RGB, 1 = spherical harmonics */
+  int32_t sh_degree;    /* 0..3 when color_mode == 1 */
+  int32_t reserved;
+  const float* mu;
+  const float* q;
+  const float* scale;
+  const float* theta;
+  const float* eta;
+  const float* tau;
+  const float* opacity;
+  const float* color;
+} drk_scene;
+
+/* Gradient buffers: same shapes as drk_scene's arrays (device, caller-allocated, overwritten). */
+typedef struct drk_scene_grad {
+  float* mu;
+  float* q;
+  float* scale;
+  float* theta;
+  float* eta;
+  float* tau;
+  float* opacity;
+  float* color;
+} drk_scene_grad;
+
+/* Pinhole camera (OpenCV: x right, y down, z forward).  Pixel (x, y) has its centre at
+ * (x + 0.5, y + 0.5).  R (row-major) and t map world to camera: X_c = R X_w + t.            */
+typedef struct drk_camera {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float bg[3];          /* background, added with the final transmittance */
+} drk_camera;
+
+/* Rasterization options.  Defaults (drk_opts_default): alpha_min 1/255, alpha_max 0.99,
+ * T_min 1e-4, near 0.2, lowpass_sl sqrt(2)/2 px (Sec. 4.4 low-pass; 0 disables it),
+ * cache_len 8 (Sec. 4.4 cache sorting; 1..8, 1 = global centre-depth order),
+ * cull_mode 0 (0 = conservative support polygon, 1 = the paper's endpoint polygon (lossy),
+ * 2 = every tile), validate 0 (1 = return DRK_EINVAL for invalid primitives).               */
+typedef struct drk_opts {
+  float alpha_min, alpha_max, T_min, near_plane, lowpass_sl;
+  int32_t cache_len, cull_mode, validate;
+} drk_opts;
+
+typedef struct drk_ws drk_ws;
+
+drk_opts drk_opts_default(void);
+const char* drk_last_error(void);
+const char* drk_version(void);
+
+/* Workspace for up to max_views views of up to max_n primitives with K bases at up to
+ * max_w x max_h pixels, with pair_capacity tile-primitive pairs per view.  Allocates device
+ * memory on the current device.  Returns DRK_ENOMEM / DRK_EINVAL / DRK_EDEVICE on failure. */
+drk_status drk_ws_create(int64_t max_n, int32_t K, int32_t max_views, int32_t max_w, int32_t max_h,
+                         int64_t pair_capacity, drk_ws** out);
+drk_status drk_ws_destroy(drk_ws* ws);
+/* Bytes drk_ws_create would allocate for the same arguments (host-only query). */
+drk_status drk_ws_size_query(int64_t max_n, int32_t K, int32_t max_views, int32_t max_w, int32_t max_h,
+                             int64_t pair_capacity, size_t* bytes);
+
+/* Step 1 (Sec. 4.4 Kernel Culling; Sec. 3.3; SH colour as in 3D-GS).  Per (view, primitive):
+ * rotation, view-space centre depth (the global pre-sort key), near/opacity culling, colour,
+ * calibrated support radius, conservative support polygon projected and clipped to the near
+ * plane, the 16x16 tiles it touches, and the per-primitive record the raster kernels read.
+ * cams: HOST array of n_views cameras (copied into the launch).  The scene must stay alive until
+ * drk_render_fwd / drk_render_bwd of this frame have been enqueued and completed.            */
+drk_status drk_preprocess(drk_ws* ws, const drk_scene* scene, const drk_camera* cams, int32_t n_views,
+                          const drk_opts* opts, void* stream);
+
+/* Step 2 (Sec. 4.4 Kernel Culling + Cache Sorting pre-sort).  Per view: stable radix sort of
+ * primitives by centre depth, duplication into (tile, primitive) pairs in that order, stable
+ * radix sort of the pairs by tile id, and per-tile [start, end) ranges.  The resulting per-tile
+ * lists are ordered by (tile, depth key, primitive index).  If a view needs more pairs than
+ * pair_capacity the overflow is recorded (see drk_ws_status) and that view renders nothing. */
+drk_status drk_bin_sort(drk_ws* ws, void* stream);
+
+/* Step 3 (Eq. 1; Sec. 3.3; Sec. 4.1-4.4; Algorithm 1).  Per pixel: ray-plane hit through each
+ * listed primitive, DRK kernel, low-pass, cutoffs, cache sorting (cache_len slots) and
+ * front-to-back compositing with early termination.
+ *   rgb     [V][3][H][W] float32 output (H, W of each view's camera; views packed back to back)
+ *   T_final [V][H][W]    float32 output: final transmittance (may be NULL)                   */
+drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream);
+
+/* Step 4 (supplement S4: backward front to back, consistent with cache sorting).  Recomputes
+ * each pixel's emission sequence and accumulates dL/dparameter for every primitive:
+ *   rgb      [V][3][H][W]  the forward output (read)
+ *   dL_drgb  [V][3][H][W]  upstream gradient (read)
+ *   grads    same shapes as the scene arrays; zeroed and written by the call.
+ * Gradients of all views are summed into one set of buffers.                                 */
+drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, const float* dL_drgb,
+                          const drk_scene_grad* grads, void* stream);
+
+/* Synchronises `stream` and reports the status word: DRK_OK, or DRK_EOVERFLOW with
+ * *pairs_needed set to the largest pair count any view of the last drk_bin_sort needed.      */
+drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed);
+
+/* Inspection (tests and tools): copy an internal array of view `view` into `dst` (device),
+ * at most `bytes` bytes, enqueued on `stream`.  *out_count (host) receives the element count.
+ * Synchronises `stream` to read counts.  what:
+ *   0 depth keys   uint32 [n]   (float32 bits of the centre depth; 0xFFFFFFFF when culled)
+ *   1 tile counts  uint32 [n]   (tiles touched per primitive, primitive order)
+ *   2 pair tiles   uint32 [P]   (sorted)
+ *   3 pair prims   uint32 [P]   (sorted)
+ *   4 ranges       uint32 [2*tiles] (start, end per tile)
+ *   5 emitted      int32  [H*W] (contributions composited per pixel, from the last forward)
+ *   6 consumed     int32  [H*W] (list entries read per pixel before it terminated)        */
+drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int64_t bytes, int64_t* out_count,
+                         void* stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop.  Scenes are copied into resident device memory
+ * once; requests (scene, camera) arrive at any time and are admitted while the HBM budget and
+ * the in-flight limit allow; admitted requests run concurrently on separate streams with
+ * per-(scene, resolution) workspaces whose launches are captured in HIP graphs.            */
+typedef struct drk_server drk_server;
+
+typedef struct drk_serve_cfg {
+  int64_t hbm_budget_bytes;   /* device memory the server may use for workspaces (0 = 50% of free) */
+  int32_t max_inflight;       /* requests on the GPU at once (streams) */
+  int32_t queue_capacity;     /* pending requests before submit returns DRK_EAGAIN */
+  int32_t use_graphs;         /* 1 = capture per-workspace launch sequences in HIP graphs */
+  int32_t reserved;
+  drk_opts opts;
+} drk_serve_cfg;
+
+typedef struct drk_req_stats {
+  double submit_us, start_us, done_us;   /* host monotonic clock, microseconds */
+  int64_t pairs;                          /* tile pairs the request needed */
+  int32_t status;                         /* drk_status of the request */
+  int32_t width, height;
+} drk_req_stats;
+
+drk_status drk_serve_create(const drk_serve_cfg* cfg, drk_server** out);
+drk_status drk_serve_destroy(drk_server* srv);
+/* Copies the scene's arrays (device pointers) into memory owned by the server. */
+drk_status drk_serve_add_scene(drk_server* srv, const drk_scene* scene, int32_t* scene_id);
+/* Enqueue a render of scene_id from *cam into out_rgb ([3][H][W] float32, device, caller-owned,
+ * must stay alive until the request completes).  DRK_EAGAIN if the queue is full, DRK_ENOMEM if
+ * the request could never fit the budget, DRK_ENOTFOUND for an unknown scene.               */
+drk_status drk_serve_submit(drk_server* srv, int32_t scene_id, const drk_camera* cam, float* out_rgb,
+                            uint64_t* request_id);
+/* DRK_OK when done (stats filled, the request is then forgotten), DRK_EAGAIN while pending
+ * (after waiting up to wait_us microseconds), DRK_ENOTFOUND for an unknown id.               */
+drk_status drk_serve_poll(drk_server* srv, uint64_t request_id, int32_t wait_us, drk_req_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DRK_H */

@@ -274,7 +274,12 @@ def culled_mask(P: Prims, cam: Cam, opts: Opts) -> torch.Tensor:
     """Primitives that can never contribute: centre at or behind the near plane, opacity below
     alpha_min, or invalid parameters."""
     zc = (P.mu @ cam.R.T + cam.t)[:, 2]
-    bad = ~torch.isfinite(P.mu).all(-1) | ~torch.isfinite(P.s).all(-1) | (P.s <= 0).any(-1)
+    th = P.theta
+    gaps = torch.diff(torch.cat([th, th[:, :1] + TWO_PI], 1), dim=1)
+    bad = ~torch.isfinite(P.mu).all(-1) | ~torch.isfinite(P.q).all(-1) | ~torch.isfinite(P.s).all(-1) \
+        | (P.s <= 0).any(-1) | (th < 0).any(-1) | (th >= TWO_PI).any(-1) | (gaps <= 0).any(-1) \
+        | (gaps >= math.pi).any(-1) | (P.o <= 0) | (P.o > 1) | (P.tau <= -1) | (P.tau >= 1) \
+        | (P.eta < 0) | (P.eta > 1)
     return (zc <= opts.near) | (P.o < opts.alpha_min) | bad
 
 
@@ -361,17 +366,30 @@ def cache_emit(seq: Sequence[Tuple[float, int]], L: int) -> List[Tuple[float, in
     """Emission order of a pixel's contributors arriving in ``seq`` order through an L-slot cache
     sorted by r_t (Algorithm 1 of the supplement, reading: a full cache emits its head before the
     newcomer is inserted; newcomers go after equal keys; the remainder drains from the head)."""
+    return cache_trace(seq, L)[0]
+
+
+def cache_trace(seq: Sequence[Tuple[float, int]], L: int):
+    """``cache_emit`` plus, for knife-edge detection: for each emission the number of arrivals seen
+    when it was emitted, and for each arrival the smallest relative key gap to the cache entries it
+    was compared with on insertion."""
     cache: List[Tuple[float, int]] = []
     out: List[Tuple[float, int]] = []
-    for rt, j in seq:
+    at: List[int] = []
+    gaps: List[float] = []
+    for i, (rt, j) in enumerate(seq):
         if len(cache) >= L:
             out.append(cache.pop(0))
+            at.append(i + 1)
+        g = min((abs(rt - c[0]) / max(abs(rt), 1e-300) for c in cache), default=math.inf)
+        gaps.append(g)
         pos = len(cache)
         while pos > 0 and cache[pos - 1][0] > rt:
             pos -= 1
         cache.insert(pos, (rt, j))
     out.extend(cache)
-    return out
+    at.extend([len(seq)] * len(cache))
+    return out, at, gaps
 
 
 def composite(alphas: Sequence[float], cols: Sequence[Sequence[float]], bg, T_min):
@@ -492,16 +510,12 @@ def _finish_pixels(res, pidx, pj, key, opts, bg, out_rgb, out_T, out_n, out_nc, 
             out_rgb[p] = bg
             continue
         if opts.cache_len >= EXACT:
-            seq = sorted(((float(rt[s]), int(pj[s])) for s in sel))
-            em = seq
+            em = sorted(((float(rt[s]), int(pj[s])) for s in sel))
+            emit_at = list(range(1, len(em) + 1))
+            gaps = [math.inf] + [abs(em[i][0] - em[i - 1][0]) / abs(em[i][0]) for i in range(1, len(em))]
         else:
             arrival = sorted(sel, key=lambda s: (int(key[pj[s]]), int(pj[s])))
-            em = cache_emit([(float(rt[s]), int(pj[s])) for s in arrival], opts.cache_len)
-        rts = np.array([e[0] for e in em])
-        if rts.size > 1:
-            srt = np.sort(rts)
-            if np.any(np.diff(srt) <= 1e-6 * np.abs(srt[1:])):
-                knife[p] = True
+            em, emit_at, gaps = cache_trace([(float(rt[s]), int(pj[s])) for s in arrival], opts.cache_len)
         lut = {int(pj[s]): s for s in sel}
         em_s = [lut[j] for _, j in em]
         C, T, n, w = composite([at[s] for s in em_s], [col[s] for s in em_s], bg, opts.T_min)
@@ -512,6 +526,10 @@ def _finish_pixels(res, pidx, pj, key, opts, bg, out_rgb, out_T, out_n, out_nc, 
             if _near(test, opts.T_min):
                 knife[p] = True
             Tt = test
+        # order knife edge: a key comparison made before the pixel stopped was within 1e-6
+        last = emit_at[min(n, len(emit_at) - 1)]
+        if any(g <= 1e-6 for g in gaps[:last]):
+            knife[p] = True
         out_rgb[p] = C
         out_T[p] = T
         out_n[p] = n
@@ -630,9 +648,14 @@ def paper_polygon(s: np.ndarray, theta: np.ndarray, o: float, tau: float) -> np.
     """The polygon of Sec. 4.4 as printed: endpoints at s_k * sqrt(-log Psi^{-1}(e^{-9}/o)).
     Not conservative (the L2 contours bulge past the chords)."""
     y = math.exp(-9.0) / o
-    g = float(psi_inv(torch.tensor(min(y, 1.0), dtype=F64), torch.tensor(tau, dtype=F64)))
-    sc = s.astype(np.float64) * math.sqrt(max(-math.log(g), 0.0))
-    return np.stack([sc * np.cos(theta.astype(np.float64)), sc * np.sin(theta.astype(np.float64))], -1)
+    g = _psi_inv_scalar(min(y, 1.0), tau)
+    ml = -math.log(g)
+    fct = math.sqrt(ml if ml > 0.0 else 0.0)
+    out = []
+    for k in range(len(s)):
+        sc = float(s[k]) * fct
+        out.append((sc * math.cos(float(theta[k])), sc * math.sin(float(theta[k]))))
+    return np.array(out)
 
 
 def _clip_near(poly3: np.ndarray, near: float) -> np.ndarray:
@@ -640,15 +663,15 @@ def _clip_near(poly3: np.ndarray, near: float) -> np.ndarray:
     out = []
     nv = len(poly3)
     for i in range(nv):
-        a = poly3[i]
-        b = poly3[(i + 1) % nv]
+        a = [float(v) for v in poly3[i]]
+        b = [float(v) for v in poly3[(i + 1) % nv]]
         ain = a[2] >= near
         bin_ = b[2] >= near
         if ain:
             out.append(a)
         if ain != bin_:
             t = (near - a[2]) / (b[2] - a[2])
-            out.append(a + t * (b - a))
+            out.append([a[k] + t * (b[k] - a[k]) for k in range(3)])
     return np.array(out).reshape(-1, 3)
 
 
@@ -698,42 +721,95 @@ def row_spans(poly2: np.ndarray, disk, W: int, H: int) -> Dict[int, Tuple[int, i
     return spans
 
 
+def _rot_cols(q) -> List[List[float]]:
+    """R(q) (row-major) for a quaternion (w, x, y, z), products and sums in the order written."""
+    w, x, y, z = (float(a) for a in q)
+    nrm = math.sqrt(((w * w + x * x) + y * y) + z * z)
+    w, x, y, z = w / nrm, x / nrm, y / nrm, z / nrm
+    return [[1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)],
+            [2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)],
+            [2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)]]
+
+
+def _to_cam(Rc, tc, p):
+    return [((Rc[i][0] * p[0] + Rc[i][1] * p[1]) + Rc[i][2] * p[2]) + tc[i] for i in range(3)]
+
+
+def primitive_valid(scene, j: int) -> bool:
+    """Parameter validity (R19 reading: invalid primitives are culled): finite centre and rotation,
+    s_k > 0, angles in [0, 2*pi) with every gap (wrap included) in (0, pi), o in (0, 1],
+    tau in (-1, 1), eta in [0, 1]."""
+    f = lambda a: float(np.float32(a))
+    mu = [f(scene.mu[i, j]) for i in range(3)]
+    q = [f(scene.q[i, j]) for i in range(4)]
+    if not all(math.isfinite(a) for a in mu + q):
+        return False
+    if not (((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3] > 0.0):
+        return False
+    K = scene.K
+    s = [f(scene.scale[k, j]) for k in range(K)]
+    th = [f(scene.theta[k, j]) for k in range(K)]
+    if not all(math.isfinite(a) and a > 0.0 for a in s):
+        return False
+    if not all(0.0 <= a < TWO_PI for a in th):
+        return False
+    for k in range(K):
+        nxt = th[k + 1] if k + 1 < K else th[0] + TWO_PI
+        gap = nxt - th[k]
+        if not (0.0 < gap < math.pi):
+            return False
+    o, tau, eta = f(scene.opacity[j]), f(scene.tau[j]), f(scene.eta[j])
+    return 0.0 < o <= 1.0 and -1.0 < tau < 1.0 and 0.0 <= eta <= 1.0
+
+
+def _psi_inv_scalar(y: float, tau: float) -> float:
+    if y < (1.0 - tau) / 4.0:
+        return y * (1.0 + tau) / (1.0 - tau)
+    if y < (3.0 + tau) / 4.0:
+        return (y * (1.0 - tau) + tau) / (1.0 + tau)
+    return (y * (1.0 + tau) - 2.0 * tau) / (1.0 - tau)
+
+
 def primitive_tiles(scene, camera, opts: Opts, j: int) -> List[int]:
-    """Tile ids (row-major, tile_x fastest) that primitive j is binned to."""
+    """Tile ids (row-major, tile_x fastest) that primitive j is binned to (Sec. 4.4 Kernel Culling,
+    with the conservative polygon of ``support_polygon``).  float64, operations in written order."""
     W, H = camera.width, camera.height
     tx = (W + TILE - 1) // TILE
     ty = (H + TILE - 1) // TILE
-    P = Prims.from_scene(scene.subset([j]))
-    cam = Cam.from_camera(camera)
-    if bool(culled_mask(P, cam, opts)[0]):
+    f = lambda a: float(np.float32(a))
+    if not primitive_valid(scene, j):
+        return []
+    Rc = [[f(camera.R[i][k]) for k in range(3)] for i in range(3)]
+    tc = [f(camera.t[i]) for i in range(3)]
+    fx, fy, cx, cy = f(camera.fx), f(camera.fy), f(camera.cx), f(camera.cy)
+    mu = [f(scene.mu[i, j]) for i in range(3)]
+    mc = _to_cam(Rc, tc, mu)
+    o, tau = f(scene.opacity[j]), f(scene.tau[j])
+    if not mc[2] > opts.near or o < opts.alpha_min:
         return []
     if opts.cull_mode == 2:
         return list(range(tx * ty))
-    R = quat_to_rotmat(P.q)[0].numpy()
-    mu = P.mu[0].numpy()
-    Rc = cam.R.numpy()
-    tc = cam.t.numpy()
-    s = P.s[0].numpy()
-    th = P.theta[0].numpy()
-    o = float(P.o[0])
-    tau = float(P.tau[0])
+    R = _rot_cols([scene.q[i, j] for i in range(4)])
+    tu = [R[0][0], R[1][0], R[2][0]]
+    tv = [R[0][1], R[1][1], R[2][1]]
+    s = np.array([f(scene.scale[k, j]) for k in range(scene.K)])
+    th = np.array([f(scene.theta[k, j]) for k in range(scene.K)])
     if opts.cull_mode == 1:
         poly = paper_polygon(s, th, o, tau)
     else:
-        c = float(calibrated_radius(torch.tensor(o, dtype=F64), torch.tensor(tau, dtype=F64), opts.alpha_min))
+        c = math.sqrt(-2.0 * math.log(_psi_inv_scalar(opts.alpha_min / o, tau)))
         poly = support_polygon(s, th, c)
-    world = mu[None, :] + poly[:, :1] * R[:, 0][None, :] + poly[:, 1:2] * R[:, 1][None, :]
-    camp = world @ Rc.T + tc[None, :]
-    camp = _clip_near(camp, opts.near)
-    if len(camp):
-        scr = np.stack([cam.fx * camp[:, 0] / camp[:, 2] + cam.cx, cam.fy * camp[:, 1] / camp[:, 2] + cam.cy], -1)
-    else:
-        scr = np.zeros((0, 2))
+    camp = []
+    for x, y in poly:
+        x, y = float(x), float(y)
+        wpt = [(mu[i] + x * tu[i]) + y * tv[i] for i in range(3)]
+        camp.append(_to_cam(Rc, tc, wpt))
+    camp = _clip_near(np.array(camp), opts.near)
+    scr = np.array([[(fx * p[0]) / p[2] + cx, (fy * p[1]) / p[2] + cy] for p in camp]).reshape(-1, 2)
     disk = None
     if opts.lowpass_sl > 0:
-        mc = Rc @ mu + tc
         r = opts.lowpass_sl * math.sqrt(2.0 * math.log(max(o / opts.alpha_min, 1.0)))
-        disk = (cam.fx * mc[0] / mc[2] + cam.cx, cam.fy * mc[1] / mc[2] + cam.cy, r)
+        disk = ((fx * mc[0]) / mc[2] + cx, (fy * mc[1]) / mc[2] + cy, r)
     spans = row_spans(scr, disk, W, H)
     out = []
     for row in sorted(spans):

@@ -1,0 +1,451 @@
+// Host side of libdrk: workspace management and the C ABI entry points of include/drk.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "drk_internal.hpp"
+
+namespace drk {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+// kernels in other translation units
+hipError_t launch_preprocess(const SceneDev&, const Views&, const OptsDev&, float*, uint32_t*, uint32_t*, uint32_t*,
+                             int64_t, hipStream_t);
+hipError_t launch_duplicate(const SceneDev&, const Views&, const OptsDev&, int, const uint32_t*, const uint32_t*,
+                            const uint32_t*, uint32_t*, uint32_t*, const uint64_t*, int64_t, hipStream_t);
+hipError_t radix_sort(int, const uint64_t*, uint32_t* const*, uint32_t* const*, uint32_t*, uint32_t*, hipStream_t);
+hipError_t scan_counts(const uint32_t*, const uint32_t*, int64_t, uint32_t*, uint64_t*, uint64_t*, uint64_t*, int64_t,
+                       uint32_t*, hipStream_t);
+hipError_t tile_ranges(const uint32_t*, const uint64_t*, uint32_t*, int, hipStream_t);
+hipError_t set_u64(uint64_t*, uint64_t, hipStream_t);
+hipError_t fill_u32(uint32_t*, uint32_t, int64_t, hipStream_t);
+hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev&, const OptsDev&, float*,
+                             float*, int32_t*, int32_t*, hipStream_t);
+hipError_t launch_render_bwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev&, const OptsDev&,
+                             const float*, const float*, const int32_t*, float*, int64_t, hipStream_t);
+hipError_t launch_preprocess_bwd(const SceneDev&, const Views&, const OptsDev&, const uint32_t*, const float*, int64_t,
+                                 const drk_scene_grad&, hipStream_t);
+
+}  // namespace drk
+
+using namespace drk;
+
+struct drk_ws {
+  int device = 0;
+  int64_t max_n = 0;
+  int K = 0, RF = 0, max_views = 0, max_w = 0, max_h = 0, max_tiles = 0;
+  int64_t cap = 0;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+
+  float* records = nullptr;
+  uint32_t* depth_keys = nullptr;
+  uint32_t* tile_counts = nullptr;
+  uint32_t *dk_a = nullptr, *dv_a = nullptr, *dk_b = nullptr, *dv_b = nullptr;
+  uint32_t* offsets = nullptr;
+  uint64_t* block_tot = nullptr;
+  uint32_t *pk_tmp = nullptr, *pv_tmp = nullptr, *pk_tmp2 = nullptr, *pv_tmp2 = nullptr;
+  uint32_t *pair_tiles = nullptr, *pair_prims = nullptr;
+  uint32_t* ranges = nullptr;
+  uint64_t* totals = nullptr;
+  uint64_t* n_eff = nullptr;
+  uint64_t* n_prims = nullptr;
+  uint32_t* status = nullptr;
+  int32_t *n_emit = nullptr, *consumed = nullptr;
+  uint32_t *hist = nullptr, *tot = nullptr;
+  float* grad_rec = nullptr;
+
+  SceneDev scene{};
+  Views views{};
+  OptsDev opts{};
+  bool have_pre = false, have_bins = false;
+};
+
+namespace {
+
+struct Plan {
+  size_t off = 0;
+  template <class T>
+  size_t add(size_t count) {
+    size_t o = (off + 255) & ~(size_t)255;
+    off = o + count * sizeof(T);
+    return o;
+  }
+};
+
+size_t layout(drk_ws* ws, bool assign, char* base) {
+  Plan p;
+  const size_t N = (size_t)ws->max_n, V = (size_t)ws->max_views, cap = (size_t)ws->cap;
+  const size_t px = (size_t)ws->max_w * ws->max_h;
+#define SLOT(field, T, count)                       \
+  {                                                 \
+    size_t o = p.add<T>(count);                     \
+    if (assign) ws->field = reinterpret_cast<T*>(base + o); \
+  }
+  SLOT(records, float, V * N * ws->RF)
+  SLOT(depth_keys, uint32_t, V * N)
+  SLOT(tile_counts, uint32_t, V * N)
+  SLOT(dk_a, uint32_t, N)
+  SLOT(dv_a, uint32_t, N)
+  SLOT(dk_b, uint32_t, N)
+  SLOT(dv_b, uint32_t, N)
+  SLOT(offsets, uint32_t, N)
+  SLOT(block_tot, uint64_t, N / 1024 + 2)
+  SLOT(pk_tmp, uint32_t, cap)
+  SLOT(pv_tmp, uint32_t, cap)
+  SLOT(pk_tmp2, uint32_t, cap)
+  SLOT(pv_tmp2, uint32_t, cap)
+  SLOT(pair_tiles, uint32_t, V * cap)
+  SLOT(pair_prims, uint32_t, V * cap)
+  SLOT(ranges, uint32_t, V * 2 * ws->max_tiles)
+  SLOT(totals, uint64_t, V)
+  SLOT(n_eff, uint64_t, V)
+  SLOT(n_prims, uint64_t, 1)
+  SLOT(status, uint32_t, V)
+  SLOT(n_emit, int32_t, V * px)
+  SLOT(consumed, int32_t, V * px)
+  SLOT(hist, uint32_t, 256 * 1024)
+  SLOT(tot, uint32_t, 256)
+  SLOT(grad_rec, float, N * grad_fields(ws->K))
+#undef SLOT
+  return p.off;
+}
+
+drk_status check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return DRK_OK;
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return DRK_EDEVICE;
+}
+
+bool valid_ws_args(int64_t max_n, int32_t K, int32_t max_views, int32_t max_w, int32_t max_h, int64_t cap) {
+  if (max_n < 0 || max_n > (int64_t)0xFFFFFFF0) { set_error("max_n out of range"); return false; }
+  if (K < 3 || K > kMaxK) { set_error("K must be in [3, %d]", kMaxK); return false; }
+  if (max_views < 1 || max_views > kMaxViews) { set_error("max_views must be in [1, %d]", kMaxViews); return false; }
+  if (max_w < 1 || max_h < 1 || max_h > kMaxTileRows * kTile || max_w > 8192) {
+    set_error("image size must be within 8192 x %d", kMaxTileRows * kTile);
+    return false;
+  }
+  if (cap < 1 || cap > (int64_t)0xFFFFFF00) { set_error("pair_capacity out of range"); return false; }
+  return true;
+}
+
+}  // namespace
+
+namespace drk {
+
+hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+
+}  // namespace drk
+
+extern "C" {
+
+drk_opts drk_opts_default(void) {
+  drk_opts o;
+  o.alpha_min = 1.0f / 255.0f;
+  o.alpha_max = 0.99f;
+  o.T_min = 1e-4f;
+  o.near_plane = 0.2f;
+  o.lowpass_sl = 0.70710678118654752f;
+  o.cache_len = 8;
+  o.cull_mode = 0;
+  o.validate = 0;
+  return o;
+}
+
+const char* drk_last_error(void) { return g_err.c_str(); }
+
+const char* drk_version(void) { return "libdrk 0.1 (gfx950)"; }
+
+drk_status drk_ws_size_query(int64_t max_n, int32_t K, int32_t max_views, int32_t max_w, int32_t max_h,
+                             int64_t pair_capacity, size_t* bytes) {
+  if (!bytes) { set_error("bytes is null"); return DRK_EINVAL; }
+  if (!valid_ws_args(max_n, K, max_views, max_w, max_h, pair_capacity)) return DRK_EINVAL;
+  drk_ws tmp;
+  tmp.max_n = max_n; tmp.K = K; tmp.RF = rec_floats(K); tmp.max_views = max_views;
+  tmp.max_w = max_w; tmp.max_h = max_h; tmp.cap = pair_capacity;
+  tmp.max_tiles = ((max_w + kTile - 1) / kTile) * ((max_h + kTile - 1) / kTile);
+  *bytes = layout(&tmp, false, nullptr);
+  return DRK_OK;
+}
+
+drk_status drk_ws_create(int64_t max_n, int32_t K, int32_t max_views, int32_t max_w, int32_t max_h,
+                         int64_t pair_capacity, drk_ws** out) {
+  if (!out) { set_error("out is null"); return DRK_EINVAL; }
+  *out = nullptr;
+  if (!valid_ws_args(max_n, K, max_views, max_w, max_h, pair_capacity)) return DRK_EINVAL;
+  drk_ws* ws = new drk_ws();
+  ws->max_n = max_n; ws->K = K; ws->RF = rec_floats(K); ws->max_views = max_views;
+  ws->max_w = max_w; ws->max_h = max_h; ws->cap = pair_capacity;
+  ws->max_tiles = ((max_w + kTile - 1) / kTile) * ((max_h + kTile - 1) / kTile);
+  if (hipGetDevice(&ws->device) != hipSuccess) { delete ws; set_error("hipGetDevice failed"); return DRK_EDEVICE; }
+  size_t bytes = layout(ws, false, nullptr);
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, bytes);
+  if (e != hipSuccess) {
+    delete ws;
+    set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    return DRK_ENOMEM;
+  }
+  ws->allocs.push_back(base);
+  ws->bytes = bytes;
+  layout(ws, true, reinterpret_cast<char*>(base));
+  *out = ws;
+  return DRK_OK;
+}
+
+drk_status drk_ws_destroy(drk_ws* ws) {
+  if (!ws) return DRK_OK;
+  for (void* p : ws->allocs) hipFree(p);
+  delete ws;
+  return DRK_OK;
+}
+
+drk_status drk_preprocess(drk_ws* ws, const drk_scene* scene, const drk_camera* cams, int32_t n_views,
+                          const drk_opts* opts, void* stream) {
+  if (!ws || !scene || !cams || !opts) { set_error("null argument"); return DRK_EINVAL; }
+  if (n_views < 1 || n_views > ws->max_views) { set_error("n_views %d outside [1, %d]", n_views, ws->max_views); return DRK_EINVAL; }
+  if (scene->n < 0 || scene->n > ws->max_n) { set_error("scene n %lld exceeds workspace max_n %lld", (long long)scene->n, (long long)ws->max_n); return DRK_EINVAL; }
+  if (scene->K != ws->K) { set_error("scene K %d != workspace K %d", scene->K, ws->K); return DRK_EINVAL; }
+  if (scene->color_mode != 0 && scene->color_mode != 1) { set_error("color_mode must be 0 or 1"); return DRK_EINVAL; }
+  if (scene->color_mode == 1 && (scene->sh_degree < 0 || scene->sh_degree > 3)) { set_error("sh_degree must be in [0, 3]"); return DRK_EINVAL; }
+  if (scene->n > 0 && (!scene->mu || !scene->q || !scene->scale || !scene->theta || !scene->eta || !scene->tau ||
+                       !scene->opacity || !scene->color)) {
+    set_error("scene array is null");
+    return DRK_EINVAL;
+  }
+  if (!(opts->alpha_min > 0.0f && opts->alpha_min < 1.0f) || !(opts->alpha_max > 0.0f && opts->alpha_max < 1.0f) ||
+      !(opts->T_min > 0.0f && opts->T_min < 1.0f) || !(opts->near_plane > 0.0f) || !(opts->lowpass_sl >= 0.0f) ||
+      opts->cache_len < 1 || opts->cache_len > kMaxCache || opts->cull_mode < 0 || opts->cull_mode > 2) {
+    set_error("invalid drk_opts (cache_len must be in [1, %d])", kMaxCache);
+    return DRK_EINVAL;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  SceneDev sc;
+  sc.n = scene->n; sc.K = scene->K; sc.color_mode = scene->color_mode;
+  sc.sh_degree = scene->color_mode == 1 ? scene->sh_degree : 0;
+  sc.ncol = scene->color_mode == 1 ? 3 * (sc.sh_degree + 1) * (sc.sh_degree + 1) : 3;
+  sc.mu = scene->mu; sc.q = scene->q; sc.scale = scene->scale; sc.theta = scene->theta;
+  sc.eta = scene->eta; sc.tau = scene->tau; sc.opacity = scene->opacity; sc.color = scene->color;
+  Views views{};
+  views.nv = n_views;
+  for (int v = 0; v < n_views; ++v) {
+    const drk_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > ws->max_w || c.height > ws->max_h) {
+      set_error("camera %d size %dx%d exceeds workspace %dx%d", v, c.width, c.height, ws->max_w, ws->max_h);
+      return DRK_EINVAL;
+    }
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f)) { set_error("camera %d focal length must be positive", v); return DRK_EINVAL; }
+    CamDev& d = views.cam[v];
+    d.W = c.width; d.H = c.height;
+    d.tiles_x = (c.width + kTile - 1) / kTile; d.tiles_y = (c.height + kTile - 1) / kTile;
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
+    for (int i = 0; i < 3; ++i) { d.t[i] = c.t[i]; d.bg[i] = c.bg[i]; }
+    for (int i = 0; i < 3; ++i) {
+      double a = 0.0;
+      for (int k = 0; k < 3; ++k) a -= (double)c.R[3 * k + i] * (double)c.t[k];
+      d.campos[i] = (float)a;
+    }
+  }
+  OptsDev od;
+  od.alpha_min = opts->alpha_min; od.alpha_max = opts->alpha_max; od.T_min = opts->T_min;
+  od.near_plane = opts->near_plane; od.lowpass_sl = opts->lowpass_sl; od.cache_len = opts->cache_len;
+  od.cull_mode = opts->cull_mode; od.validate = opts->validate;
+  drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
+  if (st) return st;
+  st = check_hip(launch_preprocess(sc, views, od, ws->records, ws->depth_keys, ws->tile_counts, ws->status, ws->max_n, s),
+                 "preprocess launch");
+  if (st) return st;
+  ws->scene = sc;
+  ws->views = views;
+  ws->opts = od;
+  ws->have_pre = true;
+  ws->have_bins = false;
+  return DRK_OK;
+}
+
+drk_status drk_bin_sort(drk_ws* ws, void* stream) {
+  if (!ws) { set_error("null workspace"); return DRK_EINVAL; }
+  if (!ws->have_pre) { set_error("drk_bin_sort before drk_preprocess"); return DRK_EINVAL; }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t N = ws->scene.n;
+  drk_status st = check_hip(set_u64(ws->n_prims, (uint64_t)N, s), "set n");
+  if (st) return st;
+  for (int v = 0; v < ws->views.nv; ++v) {
+    const CamDev& cam = ws->views.cam[v];
+    const int ntiles = cam.tiles_x * cam.tiles_y;
+    // 1. stable sort of primitives by centre depth (ties keep index order)
+    uint32_t* kb[5] = {ws->depth_keys + (size_t)v * ws->max_n, ws->dk_a, ws->dk_b, ws->dk_a, ws->dk_b};
+    uint32_t* vb[5] = {nullptr, ws->dv_a, ws->dv_b, ws->dv_a, ws->dv_b};
+    if ((st = check_hip(radix_sort(32, ws->n_prims, kb, vb, ws->hist, ws->tot, s), "depth sort"))) return st;
+    const uint32_t* sorted = ws->dv_b;
+    // 2. offsets of each primitive's pairs in depth order
+    const uint32_t* counts = ws->tile_counts + (size_t)v * ws->max_n;
+    if ((st = check_hip(scan_counts(sorted, counts, N, ws->offsets, ws->block_tot, ws->totals + v, ws->n_eff + v,
+                                    ws->cap, ws->status + v, s), "count scan")))
+      return st;
+    // 3. duplicate into (tile, primitive) pairs
+    int bits = 1;
+    while ((1 << bits) < ntiles) ++bits;
+    const int passes = (bits + 7) / 8;
+    uint32_t* fk = ws->pair_tiles + (size_t)v * ws->cap;
+    uint32_t* fv = ws->pair_prims + (size_t)v * ws->cap;
+    if ((st = check_hip(launch_duplicate(ws->scene, ws->views, ws->opts, v, sorted, ws->offsets, counts, ws->pk_tmp,
+                                         ws->pv_tmp, ws->totals + v, ws->cap, s),
+                        "duplicate")))
+      return st;
+    // 4. stable sort of the pairs by tile id -> (tile, depth, index) order
+    uint32_t* pk[3] = {ws->pk_tmp, passes == 2 ? ws->pk_tmp2 : fk, fk};
+    uint32_t* pv[3] = {ws->pv_tmp, passes == 2 ? ws->pv_tmp2 : fv, fv};
+    if ((st = check_hip(radix_sort(bits, ws->n_eff + v, pk, pv, ws->hist, ws->tot, s), "tile sort"))) return st;
+    // 5. ranges
+    if ((st = check_hip(tile_ranges(fk, ws->n_eff + v, ws->ranges + (size_t)v * 2 * ws->max_tiles, ntiles, s),
+                        "ranges")))
+      return st;
+  }
+  ws->have_bins = true;
+  return DRK_OK;
+}
+
+drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream) {
+  if (!ws || !rgb) { set_error("null argument"); return DRK_EINVAL; }
+  if (!ws->have_bins) { set_error("drk_render_fwd before drk_bin_sort"); return DRK_EINVAL; }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  size_t off = 0;
+  const size_t px_max = (size_t)ws->max_w * ws->max_h;
+  for (int v = 0; v < ws->views.nv; ++v) {
+    const CamDev& cam = ws->views.cam[v];
+    const size_t npx = (size_t)cam.W * cam.H;
+    drk_status st = check_hip(
+        launch_render_fwd(ws->K, ws->records + (size_t)v * ws->max_n * ws->RF, ws->ranges + (size_t)v * 2 * ws->max_tiles,
+                          ws->pair_prims + (size_t)v * ws->cap, cam, ws->opts, rgb + 3 * off,
+                          T_final ? T_final + off : nullptr, ws->n_emit + v * px_max, ws->consumed + v * px_max, s),
+        "render_fwd");
+    if (st) return st;
+    off += npx;
+  }
+  return DRK_OK;
+}
+
+drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, const float* dL_drgb,
+                          const drk_scene_grad* grads, void* stream) {
+  if (!ws || !scene || !rgb || !dL_drgb || !grads) { set_error("null argument"); return DRK_EINVAL; }
+  if (!ws->have_bins) { set_error("drk_render_bwd before drk_bin_sort"); return DRK_EINVAL; }
+  if (scene->n != ws->scene.n || scene->mu != ws->scene.mu || scene->q != ws->scene.q) {
+    set_error("drk_render_bwd: scene differs from the one preprocessed");
+    return DRK_EINVAL;
+  }
+  if (!grads->mu || !grads->q || !grads->scale || !grads->theta || !grads->eta || !grads->tau || !grads->opacity ||
+      !grads->color) {
+    set_error("gradient array is null");
+    return DRK_EINVAL;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t N = ws->scene.n;
+  const int GF = grad_fields(ws->K);
+  drk_status st = check_hip(fill_u32(reinterpret_cast<uint32_t*>(ws->grad_rec), 0u, (int64_t)N * GF, s), "clear grads");
+  if (st) return st;
+  size_t off = 0;
+  const size_t px_max = (size_t)ws->max_w * ws->max_h;
+  for (int v = 0; v < ws->views.nv; ++v) {
+    const CamDev& cam = ws->views.cam[v];
+    const size_t npx = (size_t)cam.W * cam.H;
+    st = check_hip(launch_render_bwd(ws->K, ws->records + (size_t)v * ws->max_n * ws->RF,
+                                     ws->ranges + (size_t)v * 2 * ws->max_tiles, ws->pair_prims + (size_t)v * ws->cap,
+                                     cam, ws->opts, rgb + 3 * off, dL_drgb + 3 * off, ws->consumed + v * px_max,
+                                     ws->grad_rec, N, s),
+                   "render_bwd");
+    if (st) return st;
+    off += npx;
+  }
+  return check_hip(launch_preprocess_bwd(ws->scene, ws->views, ws->opts, ws->tile_counts, ws->grad_rec, ws->max_n,
+                                         *grads, s),
+                   "preprocess_bwd");
+}
+
+drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed) {
+  if (!ws) { set_error("null workspace"); return DRK_EINVAL; }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drk_status st = check_hip(hipStreamSynchronize(s), "stream sync");
+  if (st) return st;
+  std::vector<uint32_t> status(ws->max_views);
+  std::vector<uint64_t> totals(ws->max_views);
+  if ((st = check_hip(hipMemcpy(status.data(), ws->status, sizeof(uint32_t) * ws->max_views, hipMemcpyDeviceToHost),
+                      "read status")))
+    return st;
+  if ((st = check_hip(hipMemcpy(totals.data(), ws->totals, sizeof(uint64_t) * ws->max_views, hipMemcpyDeviceToHost),
+                      "read totals")))
+    return st;
+  uint32_t all = 0;
+  uint64_t need = 0;
+  const int nv = ws->have_pre ? ws->views.nv : 0;
+  for (int v = 0; v < nv; ++v) {
+    all |= status[v];
+    need = std::max(need, totals[v]);
+  }
+  if (pairs_needed) *pairs_needed = (int64_t)need;
+  if (all & ST_INVALID) { set_error("invalid primitive parameters (validate mode)"); return DRK_EINVAL; }
+  if (all & ST_OVERFLOW) {
+    set_error("tile-pair buffer overflow: need %llu pairs, capacity %lld", (unsigned long long)need, (long long)ws->cap);
+    return DRK_EOVERFLOW;
+  }
+  return DRK_OK;
+}
+
+drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int64_t bytes, int64_t* out_count,
+                         void* stream) {
+  if (!ws || !out_count) { set_error("null argument"); return DRK_EINVAL; }
+  if (!ws->have_pre || view < 0 || view >= ws->views.nv) { set_error("view %d not available", view); return DRK_EINVAL; }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const CamDev& cam = ws->views.cam[view];
+  const int64_t N = ws->scene.n;
+  const size_t px_max = (size_t)ws->max_w * ws->max_h;
+  const void* src = nullptr;
+  int64_t count = 0;
+  size_t esize = 4;
+  switch (what) {
+    case 0: src = ws->depth_keys + (size_t)view * ws->max_n; count = N; break;
+    case 1: src = ws->tile_counts + (size_t)view * ws->max_n; count = N; break;
+    case 2:
+    case 3: {
+      if (!ws->have_bins) { set_error("no bins yet"); return DRK_EINVAL; }
+      uint64_t ne = 0;
+      drk_status st = check_hip(hipStreamSynchronize(s), "sync");
+      if (st) return st;
+      if ((st = check_hip(hipMemcpy(&ne, ws->n_eff + view, 8, hipMemcpyDeviceToHost), "read n"))) return st;
+      count = (int64_t)ne;
+      src = (what == 2 ? ws->pair_tiles : ws->pair_prims) + (size_t)view * ws->cap;
+      break;
+    }
+    case 4: src = ws->ranges + (size_t)view * 2 * ws->max_tiles; count = 2LL * cam.tiles_x * cam.tiles_y; break;
+    case 5: src = ws->n_emit + view * px_max; count = (int64_t)cam.W * cam.H; break;
+    case 6: src = ws->consumed + view * px_max; count = (int64_t)cam.W * cam.H; break;
+    default: set_error("unknown export %d", what); return DRK_EINVAL;
+  }
+  *out_count = count;
+  if (dst && count > 0) {
+    const int64_t nbytes = std::min<int64_t>(bytes, count * (int64_t)esize);
+    drk_status st = check_hip(hipMemcpyAsync(dst, src, (size_t)nbytes, hipMemcpyDeviceToDevice, s), "export copy");
+    if (st) return st;
+  }
+  return DRK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal definitions shared by the libdrk translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/drk.h"
+
+namespace drk {
+
+constexpr int kTile = 16;            // 16x16 screen tiles (Sec. 4.4 Kernel Culling)
+constexpr int kMaxK = 16;            // radial bases per primitive
+constexpr int kMaxViews = 8;         // views per launch
+constexpr int kMaxTileRows = 136;    // tile rows per view (image height <= 2176)
+constexpr int kMaxCache = 8;         // cache slots (Sec. 4.4 Cache Sorting uses 8)
+constexpr int kSubArcs = 2;          // sub-arcs per sector in the support polygon
+constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
+constexpr double kGrazing = 1e-6;    // |r_d . n| below this is a grazing ray (no hit)
+
+// ---------------------------------------------------------------------------------------------
+// Per (view, primitive) render record, float32, written by the preprocess kernel and read by the
+// raster kernels.  The hit of the ray through pixel centre (px, py) is found with a homography
+// from pixel offsets to the primitive's tangent plane:
+//   dx = px - ax, dy = py - ay,  (U, V, W) = Hm (dx, dy, 1),  u = U/W, v = V/W,
+//   view depth of the hit Z = dN / W,  r_d . n = W / |r_d|   (r_d = K^-1 (px, py, 1)).
+// Hm = adj[t_u | t_v | mu] (camera frame) * K^-1 * T(ax, ay): the adjugate form of the ray-plane
+// intersection of Sec. 3.3, anchored at the quantised projected centre so that FP32 offsets stay
+// small where the kernel is evaluated.
+enum RecField : int {
+  R_H = 0,        // 9 entries, row-major
+  R_DN = 9,       // n_c . mu_c
+  R_AX = 10, R_AY = 11,       // anchor (pixel coordinates, multiple of 1/256)
+  R_OX = 12, R_OY = 13,       // projected centre minus anchor (low-pass centre)
+  R_O = 14, R_ETA = 15,
+  R_PLO = 16, R_PHI = 17,     // Psi breakpoints (1+tau)/4, (3-tau)/4
+  R_PA1 = 18, R_PA2 = 19,     // Psi slopes (1-tau)/(1+tau), (1+tau)/(1-tau)
+  R_PB2 = 20, R_PB3 = 21,     // Psi intercepts -tau/(1-tau), 2 tau/(1+tau)
+  R_RGB = 22,                 // 3 entries
+  R_TAU = 25,
+  R_SEC = 28,                 // per-sector arrays follow, each K long
+};
+// Per-sector arrays (offset R_SEC + field * K + k):
+enum SecField : int {
+  S_PA = 0,    // pseudo-angle of basis direction k (monotone in theta_k)
+  S_C = 1,     // cos theta_k
+  S_S = 2,     // sin theta_k
+  S_ID = 3,    // 1 / delta_k, delta_k = theta_{k+1} - theta_k (wrapping)
+  S_A = 4,     // 1 / (s_k sin delta_k)
+  S_B = 5,     // 1 / (s_{k+1} sin delta_k)
+  S_P = 6,     // (1/s_k^2 + 1/s_{k+1}^2) / 2
+  S_Q = 7,     // (1/s_k^2 - 1/s_{k+1}^2) / 2
+  S_NFIELDS = 8
+};
+__host__ __device__ inline int rec_floats(int K) { return (R_SEC + S_NFIELDS * K + 3) & ~3; }
+
+// ---------------------------------------------------------------------------------------------
+struct CamDev {
+  int32_t W, H, tiles_x, tiles_y;
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float bg[3];
+  float campos[3];   // -R^T t, float64-exact rounding not needed (used for SH direction only in f64)
+};
+
+struct Views {
+  CamDev cam[kMaxViews];
+  int32_t nv;
+};
+
+struct OptsDev {
+  float alpha_min, alpha_max, T_min, near_plane, lowpass_sl;
+  int32_t cache_len, cull_mode, validate;
+};
+
+struct SceneDev {
+  int64_t n;
+  int32_t K, color_mode, sh_degree, ncol;
+  const float* mu;
+  const float* q;
+  const float* scale;
+  const float* theta;
+  const float* eta;
+  const float* tau;
+  const float* opacity;
+  const float* color;
+};
+
+// Status word bits (device), read back by drk_ws_status.
+enum StatusBits : uint32_t { ST_OVERFLOW = 1u, ST_INVALID = 2u };
+
+// Per-primitive gradient of the record quantities (float32, atomically accumulated by the raster
+// backward, consumed by the per-primitive backward): layout [field][n].
+enum GradField : int {
+  G_H = 0,        // 9: dL/dHm
+  G_O = 9,        // dL/do (direct)
+  G_ETA = 10,
+  G_TAU = 11,
+  G_RGB = 12,     // 3
+  G_OX = 15, G_OY = 16,   // dL/d(low-pass centre offset)
+  G_SEC = 17,     // then dL/ds_k [K], dL/dtheta_k [K]
+};
+__host__ __device__ inline int grad_fields(int K) { return G_SEC + 2 * K; }
+
+}  // namespace drk
+
+// Host-side helpers shared by the host translation units.
+namespace drk {
+void set_error(const char* fmt, ...);
+}

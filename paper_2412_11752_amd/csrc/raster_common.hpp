@@ -1,0 +1,168 @@
+// Per-pixel DRK evaluation shared by the forward and backward raster kernels.
+//
+// Both kernels call exactly this code (compiled with -ffp-contract=off, explicit fmaf), so the
+// backward pass recomputes bit-identical opacities and therefore the identical cache-sorted
+// emission sequence of the forward pass.
+#pragma once
+
+#include "drk_internal.hpp"
+
+namespace drk {
+
+constexpr int kBatch = 64;          // primitives staged in LDS per round
+constexpr int kBlock = kTile * kTile;
+
+struct Pix {
+  float px, py;     // pixel centre (x + 0.5, y + 0.5)
+  float rd2;        // |r_d|^2 with r_d = ((px - cx)/fx, (py - cy)/fy, 1)
+};
+
+struct RasterParams {
+  float alpha_min, alpha_max, T_min, near_plane;
+  float lp_coef;    // -1 / (2 s_l^2), 0 when the low-pass filter is off
+  int32_t lowpass;
+  int32_t cache_len;
+};
+
+__device__ inline float diamond_pa(float u, float v) {
+  float r = u / (fabsf(u) + fabsf(v));
+  return v >= 0.0f ? 1.0f - r : 3.0f + r;
+}
+
+// Intermediate values of one (pixel, primitive) evaluation.
+struct Eval {
+  float dx, dy, U, V, W, iW, u, v;
+  float A, B, D, phi, t, cd, ws, r1, r2, E, g, psi, alpha, f;
+  int k, piece;
+  bool lp_wins;
+};
+
+// Evaluates the opacity (after low-pass and clamp) of record r at pixel p.  Returns false when the
+// ray misses (grazing, behind the near plane).  Sec. 3.3 (hit, via the homography), Sec. 4.1-4.3
+// (kernel), Sec. 4.4 (low-pass).
+template <int K>
+__device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix& p, const RasterParams& rp, float& at,
+                                         float& Z, Eval* ev = nullptr) {
+  const float dx = p.px - r[R_AX];
+  const float dy = p.py - r[R_AY];
+  const float U = fmaf(r[R_H + 0], dx, fmaf(r[R_H + 1], dy, r[R_H + 2]));
+  const float V = fmaf(r[R_H + 3], dx, fmaf(r[R_H + 4], dy, r[R_H + 5]));
+  const float W = fmaf(r[R_H + 6], dx, fmaf(r[R_H + 7], dy, r[R_H + 8]));
+  const float W2 = W * W;
+  if (!(W2 >= 1e-12f * p.rd2)) return false;          // |r_d . n| < 1e-6
+  const float iW = 1.0f / W;
+  Z = r[R_DN] * iW;
+  if (!(Z > rp.near_plane)) return false;
+  const float u = U * iW, v = V * iW;
+  const float r2 = fmaf(u, u, v * v);
+  float E = 0.0f;
+  int k = 0;
+  float A = 0.f, B = 0.f, D = 0.f, phi = 0.f, t = 0.f, cd = 1.f, ws = 0.f, r1 = 0.f;
+  if (r2 > 0.0f) {
+    // sector: largest k with pa_k < pa (wrapping to K-1)
+    const float pa = diamond_pa(u, v);
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) cnt += (r[R_SEC + S_PA * K + i] < pa) ? 1 : 0;
+    k = (cnt == 0) ? K - 1 : cnt - 1;
+    const int kn = (k + 1 == K) ? 0 : k + 1;
+    const float* sec = r + R_SEC;
+    const float ck = sec[S_C * K + k], sk = sec[S_S * K + k];
+    const float cn = sec[S_C * K + kn], sn = sec[S_S * K + kn];
+    A = fmaf(ck, v, -(sk * u));          // cross(d_k, p)       = r2 sin(phi)
+    B = fmaf(u, sn, -(v * cn));          // cross(p, d_{k+1})   = r2 sin(delta - phi)
+    D = fmaf(ck, u, sk * v);             // dot(d_k, p)         = r2 cos(phi)
+    phi = atan2f(A, D);
+    t = phi * sec[S_ID * K + k];
+    cd = cospif(t);
+    ws = fmaf(sec[S_Q * K + k], cd, sec[S_P * K + k]);
+    r1 = fmaf(sec[S_A * K + k], fabsf(B), sec[S_B * K + k] * fabsf(A));
+    const float eta = r[R_ETA];
+    E = fmaf(eta, r1 * r1, (1.0f - eta) * (r2 * ws));
+  }
+  const float g = expf(-0.5f * E);
+  float psi;
+  int piece;
+  if (g < r[R_PLO]) { psi = r[R_PA1] * g; piece = 0; }
+  else if (g < r[R_PHI]) { psi = fmaf(r[R_PA2], g, r[R_PB2]); piece = 1; }
+  else { psi = fmaf(r[R_PA1], g, r[R_PB3]); piece = 2; }
+  const float o = r[R_O];
+  float alpha = o * psi;
+  float f = 0.0f;
+  bool lp = false;
+  if (rp.lowpass) {
+    const float ex = dx - r[R_OX], ey = dy - r[R_OY];
+    const float d2 = fmaf(ex, ex, ey * ey);
+    f = o * expf(rp.lp_coef * ((d2 * p.rd2) / W2));
+    lp = f > alpha;
+    alpha = lp ? f : alpha;
+  }
+  at = fminf(alpha, rp.alpha_max);
+  if (ev) {
+    ev->dx = dx; ev->dy = dy; ev->U = U; ev->V = V; ev->W = W; ev->iW = iW; ev->u = u; ev->v = v;
+    ev->A = A; ev->B = B; ev->D = D; ev->phi = phi; ev->t = t; ev->cd = cd; ev->ws = ws; ev->r1 = r1; ev->r2 = r2;
+    ev->E = E; ev->g = g; ev->psi = psi; ev->alpha = alpha; ev->f = f; ev->k = k; ev->piece = piece; ev->lp_wins = lp;
+  }
+  return true;
+}
+
+// Always-full sorted cache of kMaxCache slots (Sec. 4.4 Cache Sorting, Algorithm 1).  Slots hold
+// (key, payload...).  Unused capacity holds -inf sentinels (popped first, emit nothing) and, for
+// cache_len < kMaxCache, +inf sentinels that never reach the head.  An arriving contributor pops
+// the head (emitted if real) and is inserted after all entries with key <= its key.
+template <int NP>
+struct Cache {
+  float key[kMaxCache];
+  float pay[NP][kMaxCache];
+
+  __device__ __forceinline__ void init(int cache_len) {
+#pragma unroll
+    for (int s = 0; s < kMaxCache; ++s) {
+      key[s] = (s < cache_len) ? -INFINITY : INFINITY;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) pay[q][s] = 0.0f;
+    }
+  }
+  // Pops slot 0 into (hk, hp) and inserts (z, x).
+  __device__ __forceinline__ void push(float z, const float (&x)[NP], float& hk, float (&hp)[NP]) {
+    hk = key[0];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) hp[q] = pay[q][0];
+    int p = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxCache; ++i) p += (key[i] <= z) ? 1 : 0;
+#pragma unroll
+    for (int j = 0; j < kMaxCache; ++j) {
+      const bool before = j < p;
+      const bool here = j == p;
+      const int jn = (j + 1 < kMaxCache) ? j + 1 : j;
+      key[j] = before ? key[jn] : (here ? z : key[j]);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) pay[q][j] = before ? pay[q][jn] : (here ? x[q] : pay[q][j]);
+    }
+  }
+};
+
+__device__ inline RasterParams make_params(const OptsDev& o) {
+  RasterParams rp;
+  rp.alpha_min = o.alpha_min;
+  rp.alpha_max = o.alpha_max;
+  rp.T_min = o.T_min;
+  rp.near_plane = o.near_plane;
+  rp.lowpass = o.lowpass_sl > 0.0f;
+  rp.lp_coef = rp.lowpass ? -1.0f / (2.0f * o.lowpass_sl * o.lowpass_sl) : 0.0f;
+  rp.cache_len = o.cache_len;
+  return rp;
+}
+
+__device__ inline Pix make_pix(const CamDev& cam, int x, int y) {
+  Pix p;
+  p.px = (float)x + 0.5f;
+  p.py = (float)y + 0.5f;
+  const float rx = (p.px - cam.cx) / cam.fx;
+  const float ry = (p.py - cam.cy) / cam.fy;
+  p.rd2 = fmaf(rx, rx, fmaf(ry, ry, 1.0f));
+  return p;
+}
+
+}  // namespace drk

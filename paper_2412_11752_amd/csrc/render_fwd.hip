@@ -1,0 +1,129 @@
+// Forward DRK raster (Eq. 1; Sec. 3.3; Sec. 4.1-4.4; Algorithm 1 of the supplement).
+//
+// One 256-lane workgroup (four wave64s) per 16x16 tile; lane = pixel.  The tile's primitive list
+// (ordered by centre depth) is streamed through LDS in batches of kBatch records loaded with
+// coalesced float4 reads.  Every lane evaluates every staged primitive at its pixel; contributors
+// enter the per-pixel sorted cache held in VGPRs, the popped head is composited front to back,
+// and a pixel stops when its transmittance would drop below T_min.  The workgroup leaves the list
+// as soon as all 256 pixels are done.
+#include "raster_common.hpp"
+
+namespace drk {
+
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ prims, CamDev cam, OptsDev opt,
+                                                       float* __restrict__ rgb, float* __restrict__ T_out,
+                                                       int32_t* __restrict__ n_emit_out,
+                                                       int32_t* __restrict__ consumed_out) {
+  constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
+  constexpr int RF4 = RF / 4;
+  __shared__ float4 lds[kBatch * RF4];
+  const int tile = blockIdx.x;
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const int tid = threadIdx.x;
+  const int x = tx * kTile + (tid & (kTile - 1));
+  const int y = ty * kTile + (tid >> 4);
+  const bool inside = x < cam.W && y < cam.H;
+  const RasterParams rp = make_params(opt);
+  const Pix pix = make_pix(cam, x, y);
+  const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  int n_emit = 0;
+  int consumed = (int)(end - start);
+  bool done = !inside;
+  Cache<4> cache;
+  cache.init(rp.cache_len);
+
+  for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int nb = (int)min((uint32_t)kBatch, end - b0);
+    for (int q = tid; q < nb * RF4; q += kBlock) {
+      const int ri = q / RF4, c = q - ri * RF4;
+      const uint32_t j = prims[b0 + ri];
+      lds[q] = reinterpret_cast<const float4*>(records + (size_t)j * RF)[c];
+    }
+    __syncthreads();
+    if (!done) {
+      for (int i = 0; i < nb; ++i) {
+        const float* r = reinterpret_cast<const float*>(lds + i * RF4);
+        float at, Z;
+        if (drk_eval<K>(r, pix, rp, at, Z) && at >= rp.alpha_min) {
+          const float x4[4] = {at, r[R_RGB + 0], r[R_RGB + 1], r[R_RGB + 2]};
+          float hk, hp[4];
+          cache.push(Z, x4, hk, hp);
+          const float a = hp[0];
+          if (a > 0.0f) {
+            const float test = T * (1.0f - a);
+            if (test < rp.T_min) {
+              done = true;
+              consumed = (int)(b0 - start) + i + 1;
+              break;
+            }
+            const float w = a * T;
+            C0 = fmaf(w, hp[1], C0);
+            C1 = fmaf(w, hp[2], C1);
+            C2 = fmaf(w, hp[3], C2);
+            T = test;
+            ++n_emit;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!done) {
+#pragma unroll
+    for (int s = 0; s < kMaxCache; ++s) {
+      const float a = cache.pay[0][s];
+      if (!done && a > 0.0f) {
+        const float test = T * (1.0f - a);
+        if (test < rp.T_min) {
+          done = true;
+        } else {
+          const float w = a * T;
+          C0 = fmaf(w, cache.pay[1][s], C0);
+          C1 = fmaf(w, cache.pay[2][s], C1);
+          C2 = fmaf(w, cache.pay[3][s], C2);
+          T = test;
+          ++n_emit;
+        }
+      }
+    }
+  }
+  if (inside) {
+    const size_t plane = (size_t)cam.W * cam.H;
+    const size_t pidx = (size_t)y * cam.W + x;
+    rgb[pidx] = fmaf(T, cam.bg[0], C0);
+    rgb[plane + pidx] = fmaf(T, cam.bg[1], C1);
+    rgb[2 * plane + pidx] = fmaf(T, cam.bg[2], C2);
+    if (T_out) T_out[pidx] = T;
+    n_emit_out[pidx] = n_emit;
+    consumed_out[pidx] = consumed;
+  }
+}
+
+template <int K>
+static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, const uint32_t* prims, const CamDev& cam,
+                               const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, hipStream_t s) {
+  const int ntiles = cam.tiles_x * cam.tiles_y;
+  hipLaunchKernelGGL(k_render_fwd<K>, dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt, rgb, T, ne,
+                     cons);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_fwd(int K, const float* records, const uint32_t* ranges, const uint32_t* prims,
+                             const CamDev& cam, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
+                             hipStream_t s) {
+  switch (K) {
+#define DRK_CASE(k) \
+  case k: return launch_fwd_k<k>(records, ranges, prims, cam, opt, rgb, T, ne, cons, s);
+    DRK_CASE(3) DRK_CASE(4) DRK_CASE(5) DRK_CASE(6) DRK_CASE(7) DRK_CASE(8) DRK_CASE(9) DRK_CASE(10)
+    DRK_CASE(11) DRK_CASE(12) DRK_CASE(13) DRK_CASE(14) DRK_CASE(15) DRK_CASE(16)
+#undef DRK_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace drk

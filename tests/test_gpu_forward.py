@@ -1,0 +1,211 @@
+"""Forward parity of the HIP path (preprocess -> bin/sort -> raster) against the FP64 oracle.
+
+Bit-exact: depth keys, per-primitive tile counts and the sorted (tile, primitive) lists.
+Images: within 1e-4 per channel on every pixel without a knife-edge decision (a value within
+1e-6 relative of a cutoff, or two contributors at equal depth), and few knife-edge pixels.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from drk_synth import Camera, Scene, config_c1, config_c2, intrinsics_hfov, scene_uniform_box
+from oracle import drk_oracle as O
+from tests._gpu_util import (IMG_TOL, KNIFE_MAX_FRAC, compare_image, gpu_opts, log, need_gpu, oracle_flat_lists,
+                             oracle_opts)
+
+pytestmark = pytest.mark.gpu
+
+
+def _ras(scene, cams, cap=1 << 20):
+    from paper_2412_11752_amd import Rasterizer
+    W = max(c.width for c in cams)
+    H = max(c.height for c in cams)
+    return Rasterizer(max(scene.n, 1), scene.K, W, H, max_views=len(cams), pair_capacity=cap)
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32).astype(np.int64)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene, cam = config_c1()
+    log("c1: 64x64, 256 DRKs")
+    ras = _ras(scene, [cam])
+    ds = DRKScene.from_host(scene)
+    rgb, T = ras.forward(ds, [cam], gpu_opts())
+    torch.cuda.synchronize()
+    orc = O.render_image(scene, cam, oracle_opts())
+    tiles, per, key = O.tile_lists(scene, cam, oracle_opts())
+    return dict(scene=scene, cam=cam, ras=ras, ds=ds, rgb=rgb[0].cpu().numpy(), T=T[0].cpu().numpy(), orc=orc,
+                tiles=tiles, per=per, key=key)
+
+
+def test_c1_depth_keys_bit_exact(c1):
+    gk = _u32(c1["ras"].export("depth_keys"))
+    visible = np.array([len(c1["per"][j]) > 0 for j in range(c1["scene"].n)])
+    assert visible.sum() > 50
+    np.testing.assert_array_equal(gk[visible], c1["key"][visible].astype(np.int64))
+    assert np.all(gk[~visible] == 0xFFFFFFFF)
+
+
+def test_c1_tile_counts_bit_exact(c1):
+    gc = _u32(c1["ras"].export("tile_counts"))
+    oc = np.array([len(c1["per"][j]) for j in range(c1["scene"].n)])
+    np.testing.assert_array_equal(gc, oc)
+
+
+def test_c1_tile_lists_bit_exact(c1):
+    ras = c1["ras"]
+    gt = _u32(ras.export("pair_tiles"))
+    gp = _u32(ras.export("pair_prims"))
+    ot, op = oracle_flat_lists(c1["tiles"])
+    assert gt.size == ot.size > 0
+    np.testing.assert_array_equal(gt, ot)
+    np.testing.assert_array_equal(gp, op)
+    rng = _u32(ras.export("ranges")).reshape(-1, 2)
+    for t in range(rng.shape[0]):
+        s, e = rng[t]
+        assert np.all(gt[s:e] == t)
+        assert (e - s) == len(c1["tiles"].get(t, []))
+
+
+def test_c1_image_parity(c1):
+    H, W = c1["cam"].height, c1["cam"].width
+    worst, nk, worst_k, err = compare_image(c1["rgb"], c1["orc"], H, W)
+    log(f"c1 image: max err {worst:.3e} on unflagged pixels, {nk} knife-edge pixels (max {worst_k:.3e})")
+    assert worst <= IMG_TOL
+    assert nk <= max(2, KNIFE_MAX_FRAC * H * W)
+    knife = c1["orc"].knife
+    np.testing.assert_allclose(c1["T"].ravel()[~knife], c1["orc"].T[~knife], atol=IMG_TOL)
+    ne = c1["ras"].export("emitted").cpu().numpy()
+    np.testing.assert_array_equal(ne[~knife], c1["orc"].n_emit[~knife])
+    assert c1["orc"].n_emit.max() >= 3
+
+
+def test_c1_forward_is_deterministic(c1):
+    ras, ds, cam = c1["ras"], c1["ds"], c1["cam"]
+    a, _ = ras.forward(ds, [cam], gpu_opts())
+    b, _ = ras.forward(ds, [cam], gpu_opts())
+    assert torch.equal(a, b)
+    assert np.array_equal(a[0].cpu().numpy(), c1["rgb"])
+
+
+@pytest.mark.parametrize("cull_mode", [2])
+def test_culling_changes_no_pixel(c1, cull_mode):
+    """Sec. 4.4 culling only removes tiles the support cannot touch: binning every primitive to
+    every tile gives the bitwise-identical image."""
+    ras, ds, cam = c1["ras"], c1["ds"], c1["cam"]
+    a, _ = ras.forward(ds, [cam], gpu_opts(cull_mode=cull_mode))
+    assert np.array_equal(a[0].cpu().numpy(), c1["rgb"])
+
+
+@pytest.mark.parametrize("L", [1, 3, 8])
+def test_cache_lengths_match_oracle(c1, L):
+    ras, ds, cam, scene = c1["ras"], c1["ds"], c1["cam"], c1["scene"]
+    a, _ = ras.forward(ds, [cam], gpu_opts(cache_len=L))
+    orc = O.render_image(scene, cam, oracle_opts(cache_len=L))
+    worst, nk, _, _ = compare_image(a[0].cpu().numpy(), orc, cam.height, cam.width)
+    log(f"cache_len={L}: max err {worst:.3e}, knife {nk}")
+    assert worst <= IMG_TOL
+
+
+def test_no_lowpass_matches_oracle(c1):
+    ras, ds, cam, scene = c1["ras"], c1["ds"], c1["cam"], c1["scene"]
+    a, _ = ras.forward(ds, [cam], gpu_opts(lowpass=False))
+    orc = O.render_image(scene, cam, oracle_opts(lowpass=False))
+    worst, nk, _, _ = compare_image(a[0].cpu().numpy(), orc, cam.height, cam.width)
+    assert worst <= IMG_TOL
+
+
+def test_ragged_image_and_background():
+    """An image that is not a multiple of the tile size, a non-zero background, SH colours."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    rng = np.random.default_rng(5)
+    scene, _ = config_c2(n=2000)
+    W, H = 53, 37
+    from drk_synth import camera_lookat
+    cam = camera_lookat((0.5, -3.5, 1.2), (0, 0, 0), (0, 0, 1), W, H, 60.0, bg=(0.2, 0.3, 0.4))
+    ras = _ras(scene, [cam])
+    rgb, T = ras.forward(DRKScene.from_host(scene), [cam], gpu_opts())
+    orc = O.render_image(scene, cam, oracle_opts())
+    worst, nk, _, _ = compare_image(rgb[0].cpu().numpy(), orc, H, W)
+    log(f"ragged 53x37 SH3: max err {worst:.3e}, knife {nk}")
+    assert worst <= IMG_TOL
+    tiles, per, key = O.tile_lists(scene, cam, oracle_opts())
+    ot, op = oracle_flat_lists(tiles)
+    np.testing.assert_array_equal(_u32(ras.export("pair_tiles")), ot)
+    np.testing.assert_array_equal(_u32(ras.export("pair_prims")), op)
+
+
+def test_empty_and_fully_culled_scenes():
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene, cam = config_c1()
+    cam2 = Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.R, cam.t, np.array([0.1, 0.2, 0.3], np.float32))
+    empty = scene.subset(np.arange(0))
+    ras = _ras(scene, [cam2])
+    rgb, T = ras.forward(DRKScene.from_host(empty), [cam2], gpu_opts())
+    assert torch.allclose(rgb[0], torch.tensor([0.1, 0.2, 0.3], device=rgb.device)[:, None, None].expand_as(rgb[0]))
+    assert torch.all(T == 1)
+    behind = Scene(scene.mu - np.array([[0], [0], [10]], np.float32), scene.q, scene.scale, scene.theta, scene.eta,
+                   scene.tau, scene.opacity, scene.color, -1)
+    rgb, T = ras.forward(DRKScene.from_host(behind), [cam2], gpu_opts())
+    assert torch.all(T == 1)
+    assert int(_u32(ras.export("tile_counts")).sum()) == 0
+
+
+def test_pair_overflow_is_reported_and_recovered(c1):
+    from paper_2412_11752_amd import Rasterizer
+    from paper_2412_11752_amd._lib import DRK_EOVERFLOW
+    scene, cam, ds = c1["scene"], c1["cam"], c1["ds"]
+    ras = Rasterizer(scene.n, scene.K, cam.width, cam.height, pair_capacity=16, grow=False)
+    ras.preprocess(ds, [cam], gpu_opts())
+    ras.bin_sort()
+    code, need = ras.status()
+    assert code == DRK_EOVERFLOW and need == sum(len(v) for v in c1["tiles"].values())
+    rgb, _ = ras.render_fwd()
+    torch.cuda.synchronize()
+    grow = Rasterizer(scene.n, scene.K, cam.width, cam.height, pair_capacity=16, grow=True)
+    rgb, _ = grow.forward(ds, [cam], gpu_opts())
+    assert np.array_equal(rgb[0].cpu().numpy(), c1["rgb"])
+
+
+def test_c2_sampled_pixels_and_tile_sample():
+    """800x800, 100k DRKs on a sphere shell with SH3: 1024 seeded pixels against the oracle (which
+    tests every primitive per pixel) and 200 seeded primitives' tile sets bit-exact."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene, cam = config_c2()
+    log("c2: 800x800, 100k DRKs")
+    ras = _ras(scene, [cam], cap=1 << 26)
+    rgb, T = ras.forward(DRKScene.from_host(scene), [cam], gpu_opts())
+    g = rgb[0].cpu().numpy()
+    rng = np.random.default_rng(21)
+    idx = rng.choice(cam.width * cam.height, 1024, replace=False)
+    px, py = idx % cam.width, idx // cam.width
+    orc = O.render_pixels(scene, cam, oracle_opts(), px, py)
+    err = np.abs(g[:, py, px].T.astype(np.float64) - orc.rgb).max(axis=1)
+    worst = float(err[~orc.knife].max())
+    log(f"c2 sampled: max err {worst:.3e}, knife {int(orc.knife.sum())}, mean emitted {orc.n_emit.mean():.1f}")
+    assert worst <= IMG_TOL
+    assert orc.knife.sum() <= 3
+    # tile sets of sampled primitives
+    gt = _u32(ras.export("pair_tiles"))
+    gp = _u32(ras.export("pair_prims"))
+    keys = _u32(ras.export("depth_keys"))
+    order = np.lexsort((gp, keys[gp], gt))
+    assert np.array_equal(order, np.arange(gt.size))          # sorted by (tile, depth key, index)
+    sample = rng.choice(scene.n, 200, replace=False)
+    okey = O.centre_depth_f32(scene.mu, cam).view(np.uint32)
+    for j in sample:
+        ot = O.primitive_tiles(scene, cam, oracle_opts(), int(j))
+        gtj = np.sort(gt[gp == j])
+        assert np.array_equal(gtj, np.array(ot, np.int64)), j
+        if ot:
+            assert keys[j] == okey[j]
