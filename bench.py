@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the DRK rasterizer on one MI355X.
+
+Workload (default): 1M DRKs (K = 8, SH degree 3) in 64 anisotropic clusters of a 20-unit box,
+rendered at 1920x1080 along a 100-frame camera path inside the box.  Inputs are resident in HBM
+before the timed region starts.
+
+  fwd phase     : per step one view: preprocess -> bin/sort -> forward raster   -> value (Mpix/s)
+  fwd+bwd phase : per step one view: the forward above + backward raster + per-primitive backward
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s fwd and fwd+bwd it/s at 1M DRKs 1080p; served p50/p99 latency vs plain"
+
+# Algorithmic work per unit (see the design notes): FP32 operations with an FMA counted as 2 and an
+# elementary function (reciprocal, exp, atan2, cospi) counted as 1.
+def ops_eval(K: int) -> int:
+    return 76 + 2 * K          # hit, sector search (2K), kernel, sharpening, low-pass, cutoffs
+
+
+OPS_CACHE_PER_SLOT = 6         # per contributor: one compare + key/alpha/rgb move per cache slot
+OPS_COMPOSITE = 10             # per emitted contribution: transmittance test and colour update
+VALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12   # 78.6: non-packed FP32 FMA issue rate
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--phases", default="fwd,fwdbwd")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget (0 = skip)")
+    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU baseline)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU sharding is described in the design notes, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from drk_synth import config_c3
+    from paper_2412_11752_amd import DRKScene, Rasterizer, make_opts
+    from paper_2412_11752_amd._lib import DRK_OK, DrkError
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    W, H = args.width, args.height
+    t0 = time.time()
+    scene, cams = config_c3(n=args.n, width=W, height=H)
+    log(f"scene: {scene.n} DRKs K={scene.K} SH{scene.sh_degree}, {scene.nbytes() / 1e6:.1f} MB; gen {time.time() - t0:.1f}s")
+    ds = DRKScene.from_host(scene, device=dev)
+    opts = make_opts()
+    K = scene.K
+    n_frames = args.warmup + args.steps
+    frames = [cams[i % len(cams)] for i in range(n_frames)]
+
+    # size the pair buffer for every frame used (untimed)
+    ras = Rasterizer(scene.n, K, W, H, pair_capacity=1 << 26)
+    need = 0
+    for cam in frames:
+        ras.preprocess(ds, [cam], opts)
+        ras.bin_sort()
+        code, nd = ras.status()
+        need = max(need, nd)
+    cap = int(need * 1.05) + 4096
+    ras.close()
+    ras = Rasterizer(scene.n, K, W, H, pair_capacity=cap)
+    log(f"pairs per view (max over frames): {need}  capacity {cap}")
+
+    rgb = torch.empty(3 * W * H, device=dev)
+    T = torch.empty(W * H, device=dev)
+    stream = torch.cuda.current_stream()
+    result = {}
+
+    def timed(phase):
+        bwd = phase == "fwdbwd"
+        g_up = torch.ones(3 * W * H, device=dev) * 0.01 if bwd else None
+        for i in range(args.warmup):
+            ras.preprocess(ds, [frames[i]], opts)
+            ras.bin_sort()
+            ras.render_fwd(rgb, T)
+            if bwd:
+                ras.render_bwd(rgb, g_up)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for s in range(args.steps):
+            cam = frames[args.warmup + s]
+            e = ev[s]
+            e[0].record(stream)
+            ras.preprocess(ds, [cam], opts)
+            e[1].record(stream)
+            ras.bin_sort()
+            e[2].record(stream)
+            ras.render_fwd(rgb, T)
+            e[3].record(stream)
+            if bwd:
+                ras.render_bwd(rgb, g_up)
+            e[4].record(stream)
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t_start
+        ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
+                        e[3].elapsed_time(e[4])] for e in ev])
+        code, _ = ras.status()
+        if code != DRK_OK:
+            raise DrkError(code, "timed loop")
+        return t_total, ms
+
+    phases = [p for p in args.phases.split(",") if p]
+    if "fwd" in phases:
+        t_total, ms = timed("fwd")
+        mpix = args.steps * W * H / t_total / 1e6
+        log(f"fwd: {t_total * 1e3 / args.steps:.3f} ms/step, {mpix:.1f} Mpix/s; "
+            f"preprocess {ms[:, 0].mean():.3f} ms, bin/sort {ms[:, 1].mean():.3f} ms, raster {ms[:, 2].mean():.3f} ms")
+        result["fwd"] = dict(t_total=t_total, ms=ms, mpix=mpix)
+    if "fwdbwd" in phases:
+        try:
+            t_total, ms = timed("fwdbwd")
+            its = args.steps / t_total
+            log(f"fwd+bwd: {t_total * 1e3 / args.steps:.3f} ms/step, {its:.2f} it/s; bwd {ms[:, 3].mean():.3f} ms")
+            result["fwdbwd"] = dict(t_total=t_total, ms=ms, its=its)
+        except DrkError as e:
+            log(f"fwd+bwd unavailable: {e}")
+
+    # algorithmic work of the forward raster over the timed frames (same frames, deterministic)
+    evals = contribs = emits = 0
+    for s in range(args.steps):
+        ras.preprocess(ds, [frames[args.warmup + s]], opts)
+        ras.bin_sort()
+        ras.render_fwd(rgb, T)
+        evals += int(ras.export("consumed").sum().item())
+        contribs += int(ras.export("contributors").sum().item())
+        emits += int(ras.export("emitted").sum().item())
+    pairs_last = int(ras.export("pair_tiles").numel())
+    flops = evals * ops_eval(K) + contribs * 8 * OPS_CACHE_PER_SLOT + emits * OPS_COMPOSITE
+    fwd = result.get("fwd")
+    roofline = None
+    if fwd is not None:
+        raster_s = fwd["ms"][:, 2].sum() / 1e3
+        achieved = flops / raster_s / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
+                    "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                    "kernel": "k_render_fwd", "avg_launch_ms": round(float(fwd["ms"][:, 2].mean()), 4),
+                    "evaluated_pairs_per_launch": evals // args.steps,
+                    "contributors_per_launch": contribs // args.steps,
+                    "emitted_per_launch": emits // args.steps}
+        log(f"raster work: {evals / args.steps / 1e6:.1f}M evaluated pairs, {contribs / args.steps / 1e6:.1f}M "
+            f"contributors, {emits / args.steps / 1e6:.1f}M emitted per view -> {achieved:.2f} TFLOP/s")
+
+    # CPU oracle on a bounded sample of the same workload (first timed frame)
+    cpu = None
+    if args.cpu_seconds > 0 and not args.profile:
+        import torch as _t
+        from oracle import drk_oracle as O
+        ncores = os.cpu_count() or 1
+        _t.set_num_threads(ncores)
+        cam = frames[args.warmup]
+        ras.preprocess(ds, [cam], opts)
+        ras.bin_sort()
+        ras.render_fwd(rgb, T)
+        g = rgb.view(3, H, W).cpu().numpy()
+        rng = np.random.default_rng(7)
+        order = rng.permutation(W * H)
+        done = 0
+        errs = []
+        t_c = time.perf_counter()
+        oopts = O.Opts().f32()
+        while time.perf_counter() - t_c < args.cpu_seconds and done < 4096:
+            idx = order[done:done + 32]
+            px, py = idx % W, idx // W
+            r = O.render_pixels(scene, cam, oopts, px, py)
+            e = np.abs(g[:, py, px].T - r.rgb).max(axis=1)
+            errs.extend(e[~r.knife].tolist())
+            done += idx.size
+        el = time.perf_counter() - t_c
+        cpu = {"value": round(done / el / 1e6, 9), "unit": "Mpix/s", "cores": _t.get_num_threads(),
+               "kind": "oracle", "sample": f"{done} seeded pixels of the first timed 1920x1080 view (every primitive "
+                                          f"tested per pixel through a lossless bounding prefilter), {el:.1f} s",
+               "parity_max_err": float(max(errs)) if errs else None}
+        log(f"cpu oracle: {done} px in {el:.1f}s -> {cpu['value']:.2e} Mpix/s; max |gpu-oracle| {cpu['parity_max_err']}")
+
+    ms_step = fwd["t_total"] * 1e3 / args.steps if fwd else None
+    line = {
+        "metric": METRIC,
+        "value": round(fwd["mpix"], 3) if fwd else None,
+        "unit": "Mpix/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4) if ms_step else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{scene.n} DRKs (K={K}, SH3) in 64 anisotropic clusters of a 20-unit box, "
+                               f"{W}x{H}, camera path inside the box, one view per step",
+                   "n_prims": scene.n, "K": K, "width": W, "height": H, "pairs_per_view": pairs_last},
+        "fwd_bwd_it_per_s": round(result["fwdbwd"]["its"], 3) if "fwdbwd" in result else None,
+        "ms_breakdown": {k: round(float(fwd["ms"][:, i].mean()), 4) for i, k in
+                         enumerate(["preprocess", "bin_sort", "render_fwd"])} if fwd else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if "fwdbwd" in result:
+        line["ms_breakdown"]["render_bwd"] = round(float(result["fwdbwd"]["ms"][:, 3].mean()), 4)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -162,7 +162,8 @@ drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed);
  *   3 pair prims   uint32 [P]   (sorted)
  *   4 ranges       uint32 [2*tiles] (start, end per tile)
  *   5 emitted      int32  [H*W] (contributions composited per pixel, from the last forward)
- *   6 consumed     int32  [H*W] (list entries read per pixel before it terminated)        */
+ *   6 consumed     int32  [H*W] (list entries read per pixel before it terminated)
+ *   7 contributors int32  [H*W] (entries with alpha >= alpha_min that entered the cache)     */
 drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int64_t bytes, int64_t* out_count,
                          void* stream);
 

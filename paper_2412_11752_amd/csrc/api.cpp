@@ -37,7 +37,7 @@ hipError_t tile_ranges(const uint32_t*, const uint64_t*, uint32_t*, int, hipStre
 hipError_t set_u64(uint64_t*, uint64_t, hipStream_t);
 hipError_t fill_u32(uint32_t*, uint32_t, int64_t, hipStream_t);
 hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev&, const OptsDev&, float*,
-                             float*, int32_t*, int32_t*, hipStream_t);
+                             float*, int32_t*, int32_t*, int32_t*, hipStream_t);
 hipError_t launch_render_bwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev&, const OptsDev&,
                              const float*, const float*, const int32_t*, float*, int64_t, hipStream_t);
 hipError_t launch_preprocess_bwd(const SceneDev&, const Views&, const OptsDev&, const uint32_t*, const float*, int64_t,
@@ -68,7 +68,7 @@ struct drk_ws {
   uint64_t* n_eff = nullptr;
   uint64_t* n_prims = nullptr;
   uint32_t* status = nullptr;
-  int32_t *n_emit = nullptr, *consumed = nullptr;
+  int32_t *n_emit = nullptr, *consumed = nullptr, *contrib = nullptr;
   uint32_t *hist = nullptr, *tot = nullptr;
   float* grad_rec = nullptr;
 
@@ -121,6 +121,7 @@ size_t layout(drk_ws* ws, bool assign, char* base) {
   SLOT(status, uint32_t, V)
   SLOT(n_emit, int32_t, V * px)
   SLOT(consumed, int32_t, V * px)
+  SLOT(contrib, int32_t, V * px)
   SLOT(hist, uint32_t, 256 * 1024)
   SLOT(tot, uint32_t, 256)
   SLOT(grad_rec, float, N * grad_fields(ws->K))
@@ -336,7 +337,8 @@ drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream) 
     drk_status st = check_hip(
         launch_render_fwd(ws->K, ws->records + (size_t)v * ws->max_n * ws->RF, ws->ranges + (size_t)v * 2 * ws->max_tiles,
                           ws->pair_prims + (size_t)v * ws->cap, cam, ws->opts, rgb + 3 * off,
-                          T_final ? T_final + off : nullptr, ws->n_emit + v * px_max, ws->consumed + v * px_max, s),
+                          T_final ? T_final + off : nullptr, ws->n_emit + v * px_max, ws->consumed + v * px_max,
+                          ws->contrib + v * px_max, s),
         "render_fwd");
     if (st) return st;
     off += npx;
@@ -437,6 +439,7 @@ drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int6
     case 4: src = ws->ranges + (size_t)view * 2 * ws->max_tiles; count = 2LL * cam.tiles_x * cam.tiles_y; break;
     case 5: src = ws->n_emit + view * px_max; count = (int64_t)cam.W * cam.H; break;
     case 6: src = ws->consumed + view * px_max; count = (int64_t)cam.W * cam.H; break;
+    case 7: src = ws->contrib + view * px_max; count = (int64_t)cam.W * cam.H; break;
     default: set_error("unknown export %d", what); return DRK_EINVAL;
   }
   *out_count = count;

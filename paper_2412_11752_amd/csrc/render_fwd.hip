@@ -15,7 +15,8 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
                                                        const uint32_t* __restrict__ prims, CamDev cam, OptsDev opt,
                                                        float* __restrict__ rgb, float* __restrict__ T_out,
                                                        int32_t* __restrict__ n_emit_out,
-                                                       int32_t* __restrict__ consumed_out) {
+                                                       int32_t* __restrict__ consumed_out,
+                                                       int32_t* __restrict__ contrib_out) {
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
   __shared__ float4 lds[kBatch * RF4];
@@ -30,7 +31,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
 
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  int n_emit = 0;
+  int n_emit = 0, n_contrib = 0;
   int consumed = (int)(end - start);
   bool done = !inside;
   Cache<4> cache;
@@ -50,6 +51,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
         const float* r = reinterpret_cast<const float*>(lds + i * RF4);
         float at, Z;
         if (drk_eval<K>(r, pix, rp, at, Z) && at >= rp.alpha_min) {
+          ++n_contrib;
           const float x4[4] = {at, r[R_RGB + 0], r[R_RGB + 1], r[R_RGB + 2]};
           float hk, hp[4];
           cache.push(Z, x4, hk, hp);
@@ -101,24 +103,26 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
     if (T_out) T_out[pidx] = T;
     n_emit_out[pidx] = n_emit;
     consumed_out[pidx] = consumed;
+    contrib_out[pidx] = n_contrib;
   }
 }
 
 template <int K>
 static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, const uint32_t* prims, const CamDev& cam,
-                               const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, hipStream_t s) {
+                               const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
+                               hipStream_t s) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
   hipLaunchKernelGGL(k_render_fwd<K>, dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt, rgb, T, ne,
-                     cons);
+                     cons, nc);
   return hipGetLastError();
 }
 
 hipError_t launch_render_fwd(int K, const float* records, const uint32_t* ranges, const uint32_t* prims,
                              const CamDev& cam, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
-                             hipStream_t s) {
+                             int32_t* nc, hipStream_t s) {
   switch (K) {
 #define DRK_CASE(k) \
-  case k: return launch_fwd_k<k>(records, ranges, prims, cam, opt, rgb, T, ne, cons, s);
+  case k: return launch_fwd_k<k>(records, ranges, prims, cam, opt, rgb, T, ne, cons, nc, s);
     DRK_CASE(3) DRK_CASE(4) DRK_CASE(5) DRK_CASE(6) DRK_CASE(7) DRK_CASE(8) DRK_CASE(9) DRK_CASE(10)
     DRK_CASE(11) DRK_CASE(12) DRK_CASE(13) DRK_CASE(14) DRK_CASE(15) DRK_CASE(16)
 #undef DRK_CASE

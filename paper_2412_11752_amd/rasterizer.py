@@ -15,8 +15,8 @@ from . import _lib
 from ._lib import DRK_OK, DRK_EOVERFLOW, check, lib
 
 EXPORT = {"depth_keys": 0, "tile_counts": 1, "pair_tiles": 2, "pair_prims": 3, "ranges": 4, "emitted": 5,
-          "consumed": 6}
-_INT_EXPORTS = {"emitted", "consumed"}
+          "consumed": 6, "contributors": 7}
+_INT_EXPORTS = {"emitted", "consumed", "contributors"}
 
 
 def _stream_handle(device=None) -> int:
@@ -170,13 +170,10 @@ class Rasterizer:
         cnt = C.c_int64()
         code = EXPORT[what]
         check(lib().drk_ws_export(self._ws, view, code, None, 0, C.byref(cnt), C.c_void_p(_stream_handle())))
-        dt = torch.int32 if what in _INT_EXPORTS else torch.int32
-        out = torch.empty(int(cnt.value), dtype=dt, device=self._scene.mu.device)
+        out = torch.empty(int(cnt.value), dtype=torch.int32, device=self._scene.mu.device)
         check(lib().drk_ws_export(self._ws, view, code, _ptr(out), out.numel() * 4, C.byref(cnt),
                                   C.c_void_p(_stream_handle())), "drk_ws_export")
-        if what in _INT_EXPORTS:
-            return out
-        return out.view(torch.int32)   # caller reinterprets as uint32 where needed
+        return out   # int32; unsigned exports are reinterpreted by the caller
 
     # -- convenience ------------------------------------------------------------------------
     def forward(self, scene: DRKScene, cams: Sequence, opts=None, check_overflow: bool = True):
