@@ -179,7 +179,8 @@ typedef struct drk_serve_cfg {
   int32_t max_inflight;       /* requests on the GPU at once (streams) */
   int32_t queue_capacity;     /* pending requests before submit returns DRK_EAGAIN */
   int32_t use_graphs;         /* 1 = capture per-workspace launch sequences in HIP graphs */
-  int32_t reserved;
+  int32_t initial_pairs;      /* first pair capacity of a new workspace (0 = from scene and image size);
+                                 a request that overflows is rerun with a larger workspace */
   drk_opts opts;
 } drk_serve_cfg;
 

@@ -547,11 +547,12 @@ def render_image(scene, camera, opts: Opts, **kw) -> PixelResult:
 # Differentiable render of given pixels with the emission order fixed by the forward pass
 
 def render_loss_grad(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, target: np.ndarray,
-                     dL_drgb: Optional[np.ndarray] = None):
+                     dL_drgb: Optional[np.ndarray] = None, fwd: Optional[PixelResult] = None):
     """Gradients of L = sum over the pixels of (C - target)^2 (or of sum(C * dL_drgb) when given)
     with respect to every ABI parameter, by float64 autograd through Sec. 3.3 - 4.4 with the discrete
     decisions (emission order, cutoffs, sector, Psi piece, max branch) taken from the forward pass."""
-    fwd = render_pixels(scene, camera, opts, px, py)
+    if fwd is None:
+        fwd = render_pixels(scene, camera, opts, px, py)
     P = Prims.from_scene(scene)
     leaves = {}
     for name in ("mu", "q", "s", "theta", "eta", "tau", "o", "color"):

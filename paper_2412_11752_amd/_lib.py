@@ -44,7 +44,7 @@ class Opts(C.Structure):
 
 class ServeCfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32), ("queue_capacity", C.c_int32),
-                ("use_graphs", C.c_int32), ("reserved", C.c_int32), ("opts", Opts)]
+                ("use_graphs", C.c_int32), ("initial_pairs", C.c_int32), ("opts", Opts)]
 
 
 class ReqStats(C.Structure):

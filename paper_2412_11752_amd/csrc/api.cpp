@@ -26,9 +26,10 @@ void set_error(const char* fmt, ...) {
 }
 
 // kernels in other translation units
-hipError_t launch_preprocess(const SceneDev&, const Views&, const OptsDev&, float*, uint32_t*, uint32_t*, uint32_t*,
+hipError_t set_views(Views*, const Views&, hipStream_t);
+hipError_t launch_preprocess(const SceneDev&, const Views*, int, const OptsDev&, float*, uint32_t*, uint32_t*, uint32_t*,
                              int64_t, hipStream_t);
-hipError_t launch_duplicate(const SceneDev&, const Views&, const OptsDev&, int, const uint32_t*, const uint32_t*,
+hipError_t launch_duplicate(const SceneDev&, const Views*, const OptsDev&, int, const uint32_t*, const uint32_t*,
                             const uint32_t*, uint32_t*, uint32_t*, const uint64_t*, int64_t, hipStream_t);
 hipError_t radix_sort(int, const uint64_t*, uint32_t* const*, uint32_t* const*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t scan_counts(const uint32_t*, const uint32_t*, int64_t, uint32_t*, uint64_t*, uint64_t*, uint64_t*, int64_t,
@@ -36,11 +37,11 @@ hipError_t scan_counts(const uint32_t*, const uint32_t*, int64_t, uint32_t*, uin
 hipError_t tile_ranges(const uint32_t*, const uint64_t*, uint32_t*, int, hipStream_t);
 hipError_t set_u64(uint64_t*, uint64_t, hipStream_t);
 hipError_t fill_u32(uint32_t*, uint32_t, int64_t, hipStream_t);
-hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev&, const OptsDev&, float*,
-                             float*, int32_t*, int32_t*, int32_t*, hipStream_t);
-hipError_t launch_render_bwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev&, const OptsDev&,
-                             const float*, const float*, const int32_t*, float*, int64_t, hipStream_t);
-hipError_t launch_preprocess_bwd(const SceneDev&, const Views&, const OptsDev&, const uint32_t*, const float*, int64_t,
+hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
+                             float*, float*, int32_t*, int32_t*, int32_t*, hipStream_t);
+hipError_t launch_render_bwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
+                             const float*, const float*, float*, int64_t, hipStream_t);
+hipError_t launch_preprocess_bwd(const SceneDev&, const Views*, const OptsDev&, const uint32_t*, const float*, int64_t,
                                  const drk_scene_grad&, hipStream_t);
 
 }  // namespace drk
@@ -71,6 +72,8 @@ struct drk_ws {
   int32_t *n_emit = nullptr, *consumed = nullptr, *contrib = nullptr;
   uint32_t *hist = nullptr, *tot = nullptr;
   float* grad_rec = nullptr;
+  Views* views_dev = nullptr;     // cameras read by every kernel (set by a one-thread kernel)
+  float* out_rgb = nullptr;       // internal output image [3][max_h][max_w] (graph-captured renders)
 
   SceneDev scene{};
   Views views{};
@@ -124,7 +127,9 @@ size_t layout(drk_ws* ws, bool assign, char* base) {
   SLOT(contrib, int32_t, V * px)
   SLOT(hist, uint32_t, 256 * 1024)
   SLOT(tot, uint32_t, 256)
-  SLOT(grad_rec, float, N * grad_fields(ws->K))
+  SLOT(grad_rec, float, V * N * grad_fields(ws->K))
+  SLOT(views_dev, Views, 1)
+  SLOT(out_rgb, float, 3 * px)
 #undef SLOT
   return p.off;
 }
@@ -152,6 +157,118 @@ bool valid_ws_args(int64_t max_n, int32_t K, int32_t max_views, int32_t max_w, i
 namespace drk {
 
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+
+}  // namespace drk
+
+namespace drk {
+
+drk_status ws_set_cameras(drk_ws* ws, const drk_camera* cams, int32_t n_views, hipStream_t s) {
+  if (!ws || !cams) { set_error("null argument"); return DRK_EINVAL; }
+  if (n_views < 1 || n_views > ws->max_views) { set_error("n_views %d outside [1, %d]", n_views, ws->max_views); return DRK_EINVAL; }
+  Views views{};
+  views.nv = n_views;
+  for (int v = 0; v < n_views; ++v) {
+    const drk_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > ws->max_w || c.height > ws->max_h) {
+      set_error("camera %d size %dx%d exceeds workspace %dx%d", v, c.width, c.height, ws->max_w, ws->max_h);
+      return DRK_EINVAL;
+    }
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f)) { set_error("camera %d focal length must be positive", v); return DRK_EINVAL; }
+    for (int i = 0; i < 9; ++i)
+      if (!isfinite(c.R[i])) { set_error("camera %d rotation is not finite", v); return DRK_EINVAL; }
+    CamDev& d = views.cam[v];
+    d.W = c.width; d.H = c.height;
+    d.tiles_x = (c.width + kTile - 1) / kTile; d.tiles_y = (c.height + kTile - 1) / kTile;
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
+    for (int i = 0; i < 3; ++i) { d.t[i] = c.t[i]; d.bg[i] = c.bg[i]; }
+    for (int i = 0; i < 3; ++i) {
+      double a = 0.0;
+      for (int k = 0; k < 3; ++k) a -= (double)c.R[3 * k + i] * (double)c.t[k];
+      d.campos[i] = (float)a;
+    }
+  }
+  drk_status st = check_hip(set_views(ws->views_dev, views, s), "set cameras");
+  if (st) return st;
+  ws->views = views;
+  return DRK_OK;
+}
+
+drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts* opts, hipStream_t s) {
+  if (!ws || !scene || !opts) { set_error("null argument"); return DRK_EINVAL; }
+  if (ws->views.nv < 1) { set_error("no cameras set"); return DRK_EINVAL; }
+  if (scene->n < 0 || scene->n > ws->max_n) { set_error("scene n %lld exceeds workspace max_n %lld", (long long)scene->n, (long long)ws->max_n); return DRK_EINVAL; }
+  if (scene->K != ws->K) { set_error("scene K %d != workspace K %d", scene->K, ws->K); return DRK_EINVAL; }
+  if (scene->color_mode != 0 && scene->color_mode != 1) { set_error("color_mode must be 0 or 1"); return DRK_EINVAL; }
+  if (scene->color_mode == 1 && (scene->sh_degree < 0 || scene->sh_degree > 3)) { set_error("sh_degree must be in [0, 3]"); return DRK_EINVAL; }
+  if (scene->n > 0 && (!scene->mu || !scene->q || !scene->scale || !scene->theta || !scene->eta || !scene->tau ||
+                       !scene->opacity || !scene->color)) {
+    set_error("scene array is null");
+    return DRK_EINVAL;
+  }
+  if (!(opts->alpha_min > 0.0f && opts->alpha_min < 1.0f) || !(opts->alpha_max > 0.0f && opts->alpha_max < 1.0f) ||
+      !(opts->T_min > 0.0f && opts->T_min < 1.0f) || !(opts->near_plane > 0.0f) || !(opts->lowpass_sl >= 0.0f) ||
+      opts->cache_len < 1 || opts->cache_len > kMaxCache || opts->cull_mode < 0 || opts->cull_mode > 2) {
+    set_error("invalid drk_opts (cache_len must be in [1, %d])", kMaxCache);
+    return DRK_EINVAL;
+  }
+  SceneDev sc;
+  sc.n = scene->n; sc.K = scene->K; sc.color_mode = scene->color_mode;
+  sc.sh_degree = scene->color_mode == 1 ? scene->sh_degree : 0;
+  sc.ncol = scene->color_mode == 1 ? 3 * (sc.sh_degree + 1) * (sc.sh_degree + 1) : 3;
+  sc.mu = scene->mu; sc.q = scene->q; sc.scale = scene->scale; sc.theta = scene->theta;
+  sc.eta = scene->eta; sc.tau = scene->tau; sc.opacity = scene->opacity; sc.color = scene->color;
+  OptsDev od;
+  od.alpha_min = opts->alpha_min; od.alpha_max = opts->alpha_max; od.T_min = opts->T_min;
+  od.near_plane = opts->near_plane; od.lowpass_sl = opts->lowpass_sl; od.cache_len = opts->cache_len;
+  od.cull_mode = opts->cull_mode; od.validate = opts->validate;
+  drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
+  if (st) return st;
+  st = check_hip(launch_preprocess(sc, ws->views_dev, ws->views.nv, od, ws->records, ws->depth_keys, ws->tile_counts,
+                                   ws->status, ws->max_n, s),
+                 "preprocess launch");
+  if (st) return st;
+  ws->scene = sc;
+  ws->opts = od;
+  ws->have_pre = true;
+  ws->have_bins = false;
+  return DRK_OK;
+}
+
+float* ws_out_rgb(drk_ws* ws) { return ws->out_rgb; }
+void ws_status_ptrs(drk_ws* ws, uint32_t** status, uint64_t** totals) {
+  *status = ws->status;
+  *totals = ws->totals;
+}
+size_t ws_bytes(drk_ws* ws) { return ws->bytes; }
+int64_t ws_capacity(drk_ws* ws) { return ws->cap; }
+
+// Reads the status words (the caller has synchronised the stream).
+drk_status ws_read_status(drk_ws* ws, int64_t* pairs_needed) {
+  std::vector<uint32_t> status(ws->max_views);
+  std::vector<uint64_t> totals(ws->max_views);
+  drk_status st;
+  if ((st = check_hip(hipMemcpy(status.data(), ws->status, sizeof(uint32_t) * ws->max_views, hipMemcpyDeviceToHost),
+                      "read status")))
+    return st;
+  if ((st = check_hip(hipMemcpy(totals.data(), ws->totals, sizeof(uint64_t) * ws->max_views, hipMemcpyDeviceToHost),
+                      "read totals")))
+    return st;
+  uint32_t all = 0;
+  uint64_t need = 0;
+  const int nv = ws->have_pre ? ws->views.nv : 0;
+  for (int v = 0; v < nv; ++v) {
+    all |= status[v];
+    need = std::max(need, totals[v]);
+  }
+  if (pairs_needed) *pairs_needed = (int64_t)need;
+  if (all & ST_INVALID) { set_error("invalid primitive parameters (validate mode)"); return DRK_EINVAL; }
+  if (all & ST_OVERFLOW) {
+    set_error("tile-pair buffer overflow: need %llu pairs, capacity %lld", (unsigned long long)need, (long long)ws->cap);
+    return DRK_EOVERFLOW;
+  }
+  return DRK_OK;
+}
 
 }  // namespace drk
 
@@ -220,66 +337,10 @@ drk_status drk_ws_destroy(drk_ws* ws) {
 
 drk_status drk_preprocess(drk_ws* ws, const drk_scene* scene, const drk_camera* cams, int32_t n_views,
                           const drk_opts* opts, void* stream) {
-  if (!ws || !scene || !cams || !opts) { set_error("null argument"); return DRK_EINVAL; }
-  if (n_views < 1 || n_views > ws->max_views) { set_error("n_views %d outside [1, %d]", n_views, ws->max_views); return DRK_EINVAL; }
-  if (scene->n < 0 || scene->n > ws->max_n) { set_error("scene n %lld exceeds workspace max_n %lld", (long long)scene->n, (long long)ws->max_n); return DRK_EINVAL; }
-  if (scene->K != ws->K) { set_error("scene K %d != workspace K %d", scene->K, ws->K); return DRK_EINVAL; }
-  if (scene->color_mode != 0 && scene->color_mode != 1) { set_error("color_mode must be 0 or 1"); return DRK_EINVAL; }
-  if (scene->color_mode == 1 && (scene->sh_degree < 0 || scene->sh_degree > 3)) { set_error("sh_degree must be in [0, 3]"); return DRK_EINVAL; }
-  if (scene->n > 0 && (!scene->mu || !scene->q || !scene->scale || !scene->theta || !scene->eta || !scene->tau ||
-                       !scene->opacity || !scene->color)) {
-    set_error("scene array is null");
-    return DRK_EINVAL;
-  }
-  if (!(opts->alpha_min > 0.0f && opts->alpha_min < 1.0f) || !(opts->alpha_max > 0.0f && opts->alpha_max < 1.0f) ||
-      !(opts->T_min > 0.0f && opts->T_min < 1.0f) || !(opts->near_plane > 0.0f) || !(opts->lowpass_sl >= 0.0f) ||
-      opts->cache_len < 1 || opts->cache_len > kMaxCache || opts->cull_mode < 0 || opts->cull_mode > 2) {
-    set_error("invalid drk_opts (cache_len must be in [1, %d])", kMaxCache);
-    return DRK_EINVAL;
-  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  SceneDev sc;
-  sc.n = scene->n; sc.K = scene->K; sc.color_mode = scene->color_mode;
-  sc.sh_degree = scene->color_mode == 1 ? scene->sh_degree : 0;
-  sc.ncol = scene->color_mode == 1 ? 3 * (sc.sh_degree + 1) * (sc.sh_degree + 1) : 3;
-  sc.mu = scene->mu; sc.q = scene->q; sc.scale = scene->scale; sc.theta = scene->theta;
-  sc.eta = scene->eta; sc.tau = scene->tau; sc.opacity = scene->opacity; sc.color = scene->color;
-  Views views{};
-  views.nv = n_views;
-  for (int v = 0; v < n_views; ++v) {
-    const drk_camera& c = cams[v];
-    if (c.width < 1 || c.height < 1 || c.width > ws->max_w || c.height > ws->max_h) {
-      set_error("camera %d size %dx%d exceeds workspace %dx%d", v, c.width, c.height, ws->max_w, ws->max_h);
-      return DRK_EINVAL;
-    }
-    if (!(c.fx > 0.0f) || !(c.fy > 0.0f)) { set_error("camera %d focal length must be positive", v); return DRK_EINVAL; }
-    CamDev& d = views.cam[v];
-    d.W = c.width; d.H = c.height;
-    d.tiles_x = (c.width + kTile - 1) / kTile; d.tiles_y = (c.height + kTile - 1) / kTile;
-    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
-    for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
-    for (int i = 0; i < 3; ++i) { d.t[i] = c.t[i]; d.bg[i] = c.bg[i]; }
-    for (int i = 0; i < 3; ++i) {
-      double a = 0.0;
-      for (int k = 0; k < 3; ++k) a -= (double)c.R[3 * k + i] * (double)c.t[k];
-      d.campos[i] = (float)a;
-    }
-  }
-  OptsDev od;
-  od.alpha_min = opts->alpha_min; od.alpha_max = opts->alpha_max; od.T_min = opts->T_min;
-  od.near_plane = opts->near_plane; od.lowpass_sl = opts->lowpass_sl; od.cache_len = opts->cache_len;
-  od.cull_mode = opts->cull_mode; od.validate = opts->validate;
-  drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
+  drk_status st = drk::ws_set_cameras(ws, cams, n_views, s);
   if (st) return st;
-  st = check_hip(launch_preprocess(sc, views, od, ws->records, ws->depth_keys, ws->tile_counts, ws->status, ws->max_n, s),
-                 "preprocess launch");
-  if (st) return st;
-  ws->scene = sc;
-  ws->views = views;
-  ws->opts = od;
-  ws->have_pre = true;
-  ws->have_bins = false;
-  return DRK_OK;
+  return drk::ws_preprocess_core(ws, scene, opts, s);
 }
 
 drk_status drk_bin_sort(drk_ws* ws, void* stream) {
@@ -308,7 +369,7 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
     const int passes = (bits + 7) / 8;
     uint32_t* fk = ws->pair_tiles + (size_t)v * ws->cap;
     uint32_t* fv = ws->pair_prims + (size_t)v * ws->cap;
-    if ((st = check_hip(launch_duplicate(ws->scene, ws->views, ws->opts, v, sorted, ws->offsets, counts, ws->pk_tmp,
+    if ((st = check_hip(launch_duplicate(ws->scene, ws->views_dev, ws->opts, v, sorted, ws->offsets, counts, ws->pk_tmp,
                                          ws->pv_tmp, ws->totals + v, ws->cap, s),
                         "duplicate")))
       return st;
@@ -336,7 +397,8 @@ drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream) 
     const size_t npx = (size_t)cam.W * cam.H;
     drk_status st = check_hip(
         launch_render_fwd(ws->K, ws->records + (size_t)v * ws->max_n * ws->RF, ws->ranges + (size_t)v * 2 * ws->max_tiles,
-                          ws->pair_prims + (size_t)v * ws->cap, cam, ws->opts, rgb + 3 * off,
+                          ws->pair_prims + (size_t)v * ws->cap, &ws->views_dev->cam[v], cam.tiles_x * cam.tiles_y,
+                          ws->opts, rgb + 3 * off,
                           T_final ? T_final + off : nullptr, ws->n_emit + v * px_max, ws->consumed + v * px_max,
                           ws->contrib + v * px_max, s),
         "render_fwd");
@@ -362,7 +424,9 @@ drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t N = ws->scene.n;
   const int GF = grad_fields(ws->K);
-  drk_status st = check_hip(fill_u32(reinterpret_cast<uint32_t*>(ws->grad_rec), 0u, (int64_t)N * GF, s), "clear grads");
+  const int64_t stride = ws->max_n;
+  drk_status st = check_hip(
+      fill_u32(reinterpret_cast<uint32_t*>(ws->grad_rec), 0u, (int64_t)ws->views.nv * GF * stride, s), "clear grads");
   if (st) return st;
   size_t off = 0;
   const size_t px_max = (size_t)ws->max_w * ws->max_h;
@@ -371,13 +435,14 @@ drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, 
     const size_t npx = (size_t)cam.W * cam.H;
     st = check_hip(launch_render_bwd(ws->K, ws->records + (size_t)v * ws->max_n * ws->RF,
                                      ws->ranges + (size_t)v * 2 * ws->max_tiles, ws->pair_prims + (size_t)v * ws->cap,
-                                     cam, ws->opts, rgb + 3 * off, dL_drgb + 3 * off, ws->consumed + v * px_max,
-                                     ws->grad_rec, N, s),
+                                     &ws->views_dev->cam[v], cam.tiles_x * cam.tiles_y, ws->opts, rgb + 3 * off,
+                                     dL_drgb + 3 * off,
+                                     ws->grad_rec + (size_t)v * GF * stride, stride, s),
                    "render_bwd");
     if (st) return st;
     off += npx;
   }
-  return check_hip(launch_preprocess_bwd(ws->scene, ws->views, ws->opts, ws->tile_counts, ws->grad_rec, ws->max_n,
+  return check_hip(launch_preprocess_bwd(ws->scene, ws->views_dev, ws->opts, ws->tile_counts, ws->grad_rec, ws->max_n,
                                          *grads, s),
                    "preprocess_bwd");
 }
@@ -387,28 +452,7 @@ drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   drk_status st = check_hip(hipStreamSynchronize(s), "stream sync");
   if (st) return st;
-  std::vector<uint32_t> status(ws->max_views);
-  std::vector<uint64_t> totals(ws->max_views);
-  if ((st = check_hip(hipMemcpy(status.data(), ws->status, sizeof(uint32_t) * ws->max_views, hipMemcpyDeviceToHost),
-                      "read status")))
-    return st;
-  if ((st = check_hip(hipMemcpy(totals.data(), ws->totals, sizeof(uint64_t) * ws->max_views, hipMemcpyDeviceToHost),
-                      "read totals")))
-    return st;
-  uint32_t all = 0;
-  uint64_t need = 0;
-  const int nv = ws->have_pre ? ws->views.nv : 0;
-  for (int v = 0; v < nv; ++v) {
-    all |= status[v];
-    need = std::max(need, totals[v]);
-  }
-  if (pairs_needed) *pairs_needed = (int64_t)need;
-  if (all & ST_INVALID) { set_error("invalid primitive parameters (validate mode)"); return DRK_EINVAL; }
-  if (all & ST_OVERFLOW) {
-    set_error("tile-pair buffer overflow: need %llu pairs, capacity %lld", (unsigned long long)need, (long long)ws->cap);
-    return DRK_EOVERFLOW;
-  }
-  return DRK_OK;
+  return drk::ws_read_status(ws, pairs_needed);
 }
 
 drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int64_t bytes, int64_t* out_count,

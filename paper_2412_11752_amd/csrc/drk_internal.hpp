@@ -107,4 +107,12 @@ __host__ __device__ inline int grad_fields(int K) { return G_SEC + 2 * K; }
 // Host-side helpers shared by the host translation units.
 namespace drk {
 void set_error(const char* fmt, ...);
+// Split of drk_preprocess used by the serving loop: the camera is written to device memory by a
+// one-thread kernel launched outside any captured graph; the rest reads it from there.
+drk_status ws_set_cameras(drk_ws* ws, const drk_camera* cams, int32_t n_views, hipStream_t s);
+drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts* opts, hipStream_t s);
+drk_status ws_read_status(drk_ws* ws, int64_t* pairs_needed);
+float* ws_out_rgb(drk_ws* ws);
+size_t ws_bytes(drk_ws* ws);
+int64_t ws_capacity(drk_ws* ws);
 }

@@ -343,7 +343,7 @@ __device__ inline float diamond_angle(float c, float s) {
 
 // ---------------------------------------------------------------------------------------------
 // Preprocess: one thread per (primitive, view).
-__global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, Views views, OptsDev opt, float* __restrict__ records,
+__global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, const Views* __restrict__ views, OptsDev opt, float* __restrict__ records,
                                                     uint32_t* __restrict__ depth_keys,
                                                     uint32_t* __restrict__ tile_counts,
                                                     uint32_t* __restrict__ status, int64_t stride) {
@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, Views views, Op
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
   if (j >= sc.n) return;
-  const CamDev& cam = views.cam[v];
+  const CamDev& cam = views->cam[v];
   const int64_t n = sc.n;
   const int K = sc.K;
   const int RF = rec_floats(K);
@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, Views views, Op
 // Duplication: for the depth-sorted primitive order, write (tile id, primitive) pairs at the
 // scanned offsets, row-major over each primitive's tiles.  Spans are recomputed with the same
 // float64 code as the count, so counts and pairs agree exactly.
-__global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, Views views, OptsDev opt, int v,
+__global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __restrict__ views, OptsDev opt, int v,
                                                    const uint32_t* __restrict__ sorted_prims,
                                                    const uint32_t* __restrict__ offsets,   // exclusive, per sorted slot
                                                    const uint32_t* __restrict__ tile_counts,
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, Views views, Opt
   if (cnt == 0) return;
   if ((int64_t)*total_ptr > capacity) return;   // overflow: the status word already says so
   uint32_t off = offsets[i];
-  const CamDev& cam = views.cam[v];
+  const CamDev& cam = views->cam[v];
   if (opt.cull_mode == 2) {
     for (uint32_t t = 0; t < cnt; ++t) { pair_tiles[off + t] = t; pair_prims[off + t] = j; }
     return;
@@ -499,17 +499,24 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, Views views, Opt
 // Host launchers ------------------------------------------------------------------------------
 namespace drk {
 
-hipError_t launch_preprocess(const SceneDev& sc, const Views& views, const OptsDev& opt, float* records,
+__global__ void k_set_views(Views* dst, Views src) { *dst = src; }
+
+hipError_t set_views(Views* d_views, const Views& views, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_views, dim3(1), dim3(1), 0, s, d_views, views);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const SceneDev& sc, const Views* views, int nv, const OptsDev& opt, float* records,
                              uint32_t* depth_keys, uint32_t* tile_counts, uint32_t* status, int64_t stride,
                              hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
-  dim3 grid((unsigned)((sc.n + 127) / 128), (unsigned)views.nv);
+  dim3 grid((unsigned)((sc.n + 127) / 128), (unsigned)nv);
   hipLaunchKernelGGL(k_preprocess, grid, dim3(128), 0, s, sc, views, opt, records, depth_keys, tile_counts, status,
                      stride);
   return hipGetLastError();
 }
 
-hipError_t launch_duplicate(const SceneDev& sc, const Views& views, const OptsDev& opt, int v,
+hipError_t launch_duplicate(const SceneDev& sc, const Views* views, const OptsDev& opt, int v,
                             const uint32_t* sorted_prims, const uint32_t* offsets, const uint32_t* tile_counts,
                             uint32_t* pair_tiles, uint32_t* pair_prims, const uint64_t* total_ptr, int64_t capacity,
                             hipStream_t s) {

@@ -12,7 +12,7 @@ namespace drk {
 
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
-                                                       const uint32_t* __restrict__ prims, CamDev cam, OptsDev opt,
+                                                       const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp, OptsDev opt,
                                                        float* __restrict__ rgb, float* __restrict__ T_out,
                                                        int32_t* __restrict__ n_emit_out,
                                                        int32_t* __restrict__ consumed_out,
@@ -20,6 +20,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
   __shared__ float4 lds[kBatch * RF4];
+  const CamDev& cam = *camp;
   const int tile = blockIdx.x;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   const int tid = threadIdx.x;
@@ -108,21 +109,20 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
 }
 
 template <int K>
-static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, const uint32_t* prims, const CamDev& cam,
-                               const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
+static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, const uint32_t* prims, const CamDev* cam,
+                               int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
                                hipStream_t s) {
-  const int ntiles = cam.tiles_x * cam.tiles_y;
   hipLaunchKernelGGL(k_render_fwd<K>, dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt, rgb, T, ne,
                      cons, nc);
   return hipGetLastError();
 }
 
 hipError_t launch_render_fwd(int K, const float* records, const uint32_t* ranges, const uint32_t* prims,
-                             const CamDev& cam, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
+                             const CamDev* cam, int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
                              int32_t* nc, hipStream_t s) {
   switch (K) {
 #define DRK_CASE(k) \
-  case k: return launch_fwd_k<k>(records, ranges, prims, cam, opt, rgb, T, ne, cons, nc, s);
+  case k: return launch_fwd_k<k>(records, ranges, prims, cam, ntiles, opt, rgb, T, ne, cons, nc, s);
     DRK_CASE(3) DRK_CASE(4) DRK_CASE(5) DRK_CASE(6) DRK_CASE(7) DRK_CASE(8) DRK_CASE(9) DRK_CASE(10)
     DRK_CASE(11) DRK_CASE(12) DRK_CASE(13) DRK_CASE(14) DRK_CASE(15) DRK_CASE(16)
 #undef DRK_CASE

@@ -61,3 +61,21 @@ def test_workspace_size_query():
     assert L.drk_ws_size_query(1_000_000, 8, 1, 1920, 1080, 1 << 26, C.byref(b8)) == 0
     assert L.drk_ws_size_query(1_000_000, 16, 1, 1920, 1080, 1 << 26, C.byref(b16)) == 0
     assert b16.value > b8.value > 1_000_000 * 92 * 4
+
+
+def test_serve_config_errors_without_gpu_work():
+    L = _lib.lib()
+    srv = C.c_void_p()
+    cfg = _lib.ServeCfg()
+    cfg.opts = L.drk_opts_default()
+    cfg.max_inflight = 0
+    cfg.queue_capacity = 16
+    assert L.drk_serve_create(C.byref(cfg), C.byref(srv)) == _lib.DRK_EINVAL       # no slots
+    cfg.max_inflight = 4
+    cfg.queue_capacity = 0
+    assert L.drk_serve_create(C.byref(cfg), C.byref(srv)) == _lib.DRK_EINVAL       # no queue
+    cfg.queue_capacity = 16
+    cfg.opts.cache_len = 9
+    assert L.drk_serve_create(C.byref(cfg), C.byref(srv)) == _lib.DRK_EINVAL       # cache too long
+    assert L.drk_serve_submit(None, 0, None, None, None) == _lib.DRK_EINVAL
+    assert L.drk_serve_poll(None, 1, 0, None) == _lib.DRK_EINVAL

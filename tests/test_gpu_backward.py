@@ -1,0 +1,150 @@
+"""Backward parity of the HIP path against the FP64 oracle's autograd gradients.
+
+The same upstream gradient dL/dC is given to both sides (zero on knife-edge pixels, whose discrete
+decisions may differ between FP32 and FP64).  Tolerance per parameter group: 1e-3 relative, with an
+absolute floor of 1e-3 * max |oracle gradient| of the group.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from drk_synth import Camera, Scene, config_c2, draw_angles, intrinsics_hfov, random_target
+from oracle import drk_oracle as O
+from tests._gpu_util import gpu_opts, log, need_gpu, oracle_opts
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = ("mu", "q", "scale", "theta", "eta", "tau", "opacity", "color")
+ORACLE_NAME = {"scale": "s", "opacity": "o"}
+
+
+def _oracle_group(grads, name, scene):
+    g = grads[ORACLE_NAME.get(name, name)].numpy()
+    if name == "color" and scene.sh_degree >= 0:
+        return g.reshape(g.shape[0], -1).T
+    return g.T if g.ndim == 2 else g
+
+
+def _compare(gpu, grads, scene, rel=1e-3, floor_frac=1e-3, groups=GROUPS):
+    report = {}
+    for name in groups:
+        o = _oracle_group(grads, name, scene).astype(np.float64)
+        gg = getattr(gpu, name).detach().cpu().numpy().astype(np.float64)
+        assert gg.shape == o.shape, (name, gg.shape, o.shape)
+        floor = floor_frac * max(np.abs(o).max(), 1e-30)
+        err = np.abs(gg - o)
+        bad = err > rel * np.abs(o) + floor
+        report[name] = (float((err / (np.abs(o) + floor)).max()), int(bad.sum()), float(np.abs(o).max()))
+        assert not bad.any(), (name, report[name], np.argwhere(bad)[:5])
+    return report
+
+
+def _small_scene(seed, n=12):
+    rng = np.random.default_rng(seed)
+    K = 8
+    mu = rng.uniform(-0.5, 0.5, (3, n)).astype(np.float32)
+    q = rng.normal(size=(4, n)).astype(np.float32)
+    th = draw_angles(rng, K, n)
+    s = np.exp(rng.uniform(math.log(0.15), math.log(0.6), (K, n))).astype(np.float32)
+    col = rng.normal(0, 0.1, (48, n)).astype(np.float32)
+    col[:3] = rng.uniform(0, 1, (3, n))
+    return Scene(mu, q, s, th, rng.uniform(0, 1, n).astype(np.float32), rng.uniform(0, 0.9, n).astype(np.float32),
+                 rng.uniform(0.3, 0.95, n).astype(np.float32), col, 3)
+
+
+def _gpu_grads(scene, cam, opts, G):
+    from paper_2412_11752_amd import DRKScene, Rasterizer
+    ras = Rasterizer(scene.n, scene.K, cam.width, cam.height, pair_capacity=1 << 22)
+    ds = DRKScene.from_host(scene)
+    rgb, T = ras.forward(ds, [cam], opts)
+    g = ras.render_bwd(rgb.reshape(-1), torch.as_tensor(G, dtype=torch.float32, device=rgb.device).reshape(-1))
+    torch.cuda.synchronize()
+    return rgb[0].cpu().numpy(), g, ras, ds
+
+
+@pytest.mark.parametrize("lowpass", [False, True])
+def test_small_scene_gradients(lowpass):
+    need_gpu()
+    sc = _small_scene(13)
+    W = H = 24
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.array([0, 0, 2.5], np.float32),
+                 np.array([0.2, 0.1, 0.0], np.float32))
+    oo = oracle_opts(lowpass=lowpass)
+    yy, xx = np.mgrid[0:H, 0:W]
+    px, py = xx.ravel(), yy.ravel()
+    fwd = O.render_pixels(sc, cam, oo, px, py)
+    rng = np.random.default_rng(3)
+    G = rng.normal(0, 1, (H * W, 3))
+    G[fwd.knife] = 0.0
+    loss, grads, rgb_o, _ = O.render_loss_grad(sc, cam, oo, px, py, None, dL_drgb=G, fwd=fwd)
+    rgb, g, _, _ = _gpu_grads(sc, cam, gpu_opts(lowpass=lowpass), G.T.reshape(3, H, W))
+    assert np.abs(rgb.reshape(3, -1).T - rgb_o).max() < 1e-4
+    rep = _compare(g, grads, sc)
+    log(f"small scene lowpass={lowpass}: " + ", ".join(f"{k}: {v[0]:.1e}" for k, v in rep.items()))
+
+
+def test_c2_crop_gradients():
+    """800x800, 100k DRKs (SH3): L2 loss against a random target on a seeded 32x32 crop inside the
+    object's screen footprint; gradients of every parameter group against oracle autograd."""
+    need_gpu()
+    scene, cam = config_c2()
+    W, H = cam.width, cam.height
+    rng = np.random.default_rng(31)
+    x0 = int(rng.integers(W // 2 - 150, W // 2 + 150 - 32))
+    y0 = int(rng.integers(H // 2 - 150, H // 2 + 150 - 32))
+    yy, xx = np.mgrid[y0:y0 + 32, x0:x0 + 32]
+    px, py = xx.ravel(), yy.ravel()
+    oo = oracle_opts()
+    fwd = O.render_pixels(scene, cam, oo, px, py)
+    target = random_target(1, H, W)[:, py, px].T.astype(np.float64)
+    G = 2.0 * (fwd.rgb - target)
+    G[fwd.knife] = 0.0
+    log(f"c2 crop at ({x0},{y0}): {int(fwd.knife.sum())} knife pixels, mean emitted {fwd.n_emit.mean():.1f}")
+    loss, grads, rgb_o, _ = O.render_loss_grad(scene, cam, oo, px, py, None, dL_drgb=G, fwd=fwd)
+    Gfull = np.zeros((3, H, W))
+    Gfull[:, py, px] = G.T
+    rgb, g, _, _ = _gpu_grads(scene, cam, gpu_opts(), Gfull)
+    assert np.abs(rgb[:, py, px].T - rgb_o).max() < 1e-4
+    rep = _compare(g, grads, scene)
+    log("c2 crop: " + ", ".join(f"{k}: {v[0]:.1e} (max {v[2]:.1e})" for k, v in rep.items()))
+
+
+def test_autograd_function_matches_direct_backward():
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene, Rasterizer, render
+    sc = _small_scene(17, n=30)
+    W = H = 32
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.array([0, 0, 2.5], np.float32))
+    ras = Rasterizer(sc.n, sc.K, W, H, pair_capacity=1 << 20)
+    ds = DRKScene.from_host(sc)
+    leaves = [t.clone().requires_grad_(True) for t in ds.tensors()]
+    scene_leaf = DRKScene(*leaves, sh_degree=sc.sh_degree)
+    rgb, T = render(ras, scene_leaf, [cam], gpu_opts())
+    target = torch.rand_like(rgb)
+    loss = ((rgb - target) ** 2).sum()
+    loss.backward()
+    G = (2 * (rgb - target)).detach()
+    ras2 = Rasterizer(sc.n, sc.K, W, H, pair_capacity=1 << 20)
+    rgb2, _ = ras2.forward(ds, [cam], gpu_opts())
+    g = ras2.render_bwd(rgb2.reshape(-1), G.reshape(-1))
+    for leaf, name in zip(leaves, DRKScene.FIELDS):
+        assert torch.allclose(leaf.grad, getattr(g, name), rtol=1e-5, atol=1e-6), name
+
+
+def test_backward_is_repeatable():
+    """Float atomics make the accumulation order free; two runs agree to rounding."""
+    need_gpu()
+    sc = _small_scene(19, n=40)
+    W = H = 32
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.array([0, 0, 2.5], np.float32))
+    G = np.random.default_rng(4).normal(size=(3, H, W))
+    _, g1, ras, ds = _gpu_grads(sc, cam, gpu_opts(), G)
+    _, g2, _, _ = _gpu_grads(sc, cam, gpu_opts(), G)
+    for name in GROUPS:
+        a, b = getattr(g1, name), getattr(g2, name)
+        assert torch.allclose(a, b, rtol=1e-4, atol=1e-6 * float(a.abs().max()) + 1e-12), name

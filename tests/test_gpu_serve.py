@@ -1,0 +1,124 @@
+"""Serving loop: continuous batching over resident scenes and mixed resolutions.
+
+Each served result must be bitwise identical to the same request rendered alone (the forward pass is
+deterministic), within 1e-4 of the oracle on a small request, and the admission errors must be
+reported (queue full, never fits the budget, unknown scene)."""
+import numpy as np
+import pytest
+import torch
+
+from drk_synth import camera_lookat, config_c1, config_c2, scene_uniform_box
+from oracle import drk_oracle as O
+from tests._gpu_util import IMG_TOL, compare_image, gpu_opts, log, need_gpu, oracle_opts
+
+pytestmark = pytest.mark.gpu
+
+
+def _cams(seed, sizes, n):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        az, el = rng.uniform(0, 2 * np.pi), rng.uniform(-0.5, 0.5)
+        eye = 3.5 * np.array([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)])
+        W, H = sizes[i % len(sizes)]
+        out.append(camera_lookat(eye, (0, 0, 0), (0, 0, 1), W, H, 60.0, bg=(0.05, 0.1, 0.15)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    hs = [config_c2(n=20_000)[0], scene_uniform_box(7, 5000, K=8), config_c2(n=60_000)[0]]
+    return hs, [DRKScene.from_host(s) for s in hs]
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_mixed_requests_match_alone(scenes, use_graphs):
+    from paper_2412_11752_amd import Rasterizer
+    from paper_2412_11752_amd.serving import Server
+    hs, ds = scenes
+    sizes = [(64, 64), (200, 120), (331, 257), (800, 800)]
+    cams = _cams(1, sizes, 24)
+    srv = Server(max_inflight=4, use_graphs=use_graphs, opts=gpu_opts())
+    ids = [srv.add_scene(d) for d in ds]
+    outs, rids, which = [], [], []
+    for i, cam in enumerate(cams):
+        s = i % len(ids)
+        out = torch.empty(3 * cam.height * cam.width, device="cuda")
+        outs.append(out)
+        which.append(s)
+        rids.append(srv.submit(ids[s], cam, out))
+    stats = [srv.wait(r) for r in rids]
+    assert all(st["status"] == 0 for st in stats)
+    overlap = sum(1 for a, b in zip(stats, stats[1:]) if b["start_us"] < a["done_us"])
+    log(f"graphs={use_graphs}: {len(stats)} requests, {overlap} started before the previous finished")
+    torch.cuda.synchronize()
+    for i, cam in enumerate(cams):
+        h = hs[which[i]]
+        ras = Rasterizer(h.n, h.K, cam.width, cam.height, pair_capacity=1 << 22)
+        alone, _ = ras.forward(ds[which[i]], [cam], gpu_opts())
+        assert torch.equal(alone.reshape(-1), outs[i]), i
+    srv.close()
+
+
+def test_served_request_matches_oracle(scenes):
+    from paper_2412_11752_amd.serving import Server
+    hs, ds = scenes
+    cam = _cams(2, [(48, 40)], 1)[0]
+    srv = Server(max_inflight=2, opts=gpu_opts())
+    sid = srv.add_scene(ds[1])
+    out = torch.empty(3 * 48 * 40, device="cuda")
+    st = srv.wait(srv.submit(sid, cam, out))
+    assert st["status"] == 0 and st["pairs"] > 0
+    orc = O.render_image(hs[1], cam, oracle_opts())
+    worst, nk, _, _ = compare_image(out.view(3, 40, 48).cpu().numpy(), orc, 40, 48)
+    assert worst <= IMG_TOL
+    srv.close()
+
+
+def test_admission_errors(scenes):
+    from paper_2412_11752_amd._lib import DRK_EAGAIN, DRK_ENOMEM, DRK_ENOTFOUND, DrkError
+    from paper_2412_11752_amd.serving import Server
+    hs, ds = scenes
+    cam = _cams(3, [(800, 800)], 1)[0]
+    small = Server(hbm_budget_bytes=1 << 20, max_inflight=1, opts=gpu_opts())
+    sid = small.add_scene(ds[0])
+    out = torch.empty(3 * 800 * 800, device="cuda")
+    code, _ = small.try_submit(sid, cam, out)
+    assert code == DRK_ENOMEM
+    code, _ = small.try_submit(sid + 5, cam, out)
+    assert code == DRK_ENOTFOUND
+    small.close()
+    q = Server(max_inflight=1, queue_capacity=2, opts=gpu_opts())
+    sid = q.add_scene(ds[2])
+    codes = []
+    rids = []
+    bufs = [torch.empty(3 * 800 * 800, device="cuda") for _ in range(12)]
+    for b in bufs:
+        c, r = q.try_submit(sid, cam, b)
+        codes.append(c)
+        if c == 0:
+            rids.append(r)
+    assert DRK_EAGAIN in codes
+    for r in rids:
+        assert q.wait(r)["status"] == 0
+    q.close()
+
+
+def test_overflow_is_retried_with_a_larger_workspace(scenes):
+    """A workspace whose first capacity guess is too small is regrown and the request re-run."""
+    from paper_2412_11752_amd import Rasterizer
+    from paper_2412_11752_amd.serving import Server
+    hs, ds = scenes
+    cam = _cams(4, [(800, 800)], 1)[0]
+    cam_near = camera_lookat((0, 0, -1.6), (0, 0, 0), (0, 1, 0), 800, 800, 90.0)
+    srv = Server(max_inflight=1, opts=gpu_opts(), initial_pairs=1000)
+    sid = srv.add_scene(ds[2])
+    out = torch.empty(3 * 800 * 800, device="cuda")
+    st = srv.wait(srv.submit(sid, cam_near, out))
+    assert st["status"] == 0 and st["pairs"] > 1000
+    ras = Rasterizer(hs[2].n, hs[2].K, 800, 800, pair_capacity=1 << 20)
+    alone, _ = ras.forward(ds[2], [cam_near], gpu_opts())
+    assert torch.equal(alone.reshape(-1), out)
+    srv.close()
