@@ -601,29 +601,18 @@ def render_loss_grad(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, 
 TILE = 16
 
 
-def _sbar(theta_abs, th_k, th_n, s_k, s_n):
-    dl = math.pi * (theta_abs - th_k) / (th_n - th_k)
-    w = (1 + math.cos(dl)) / (2 * s_k * s_k) + (1 - math.cos(dl)) / (2 * s_n * s_n)
-    return 1.0 / math.sqrt(w)
+def support_polygon(s: np.ndarray, theta: np.ndarray, c: float) -> np.ndarray:
+    """Star polygon (6K, 2) in tangent coordinates that contains {E <= c^2}.
 
-
-def _chord(theta_abs, th_k, th_n, s_k, s_n):
-    """Distance from the centre to the segment e_k -- e_{k+1} along direction theta_abs."""
-    phi = theta_abs - th_k
-    dlt = th_n - th_k
-    f = (math.sin(dlt - phi) / s_k + math.sin(phi) / s_n) / math.sin(dlt)
-    return 1.0 / f
-
-
-def support_polygon(s: np.ndarray, theta: np.ndarray, c: float, subarcs: int = 2) -> np.ndarray:
-    """Star polygon (V, 2) in tangent coordinates that contains {E <= c^2}.
-
-    Since E is a convex combination of r1^2 and r2^2/sbar^2, E <= c^2 implies r1 <= c or
-    r2 <= c*sbar.  Along a direction theta both bounds are radii: c*chord(theta) and c*sbar(theta).
-    Within a sector sbar is monotone and chord is convex in theta, so over each sub-arc [a, b] the
-    larger of the two is at most rho = c * max(sbar, chord) at a or b.  The circular sector of
-    radius rho over [a, b] lies inside the quad (rho d(a), rho/cos(h) d(mid), rho d(b)) with the
-    centre, h = (b - a)/2; the union of these quads in angular order is the polygon."""
+    E is a convex combination of r1^2 and r2^2/sbar^2, so E <= c^2 implies r1 <= c or r2 <= c*sbar:
+    along a direction theta the support reaches at most c * max(chord(theta), sbar(theta)), with
+    chord(theta) the distance to the segment e_k e_{k+1} (Eq. L1 level set) and sbar from Eq. radial.
+    Within a sector sbar is monotone and chord = d / cos(theta - theta_p) is convex, so on each half
+    of the sector [theta_k, mid] and [mid, theta_{k+1}] the larger bound is attained at an end.  At
+    theta_k both equal s_k, at theta_{k+1} both equal s_{k+1}, and at the bisector (cos Delta = 0)
+        sbar = (1/(2 s_k^2) + 1/(2 s_{k+1}^2))^(-1/2),   chord = 2 cos(delta/2) / (1/s_k + 1/s_{k+1}).
+    Each half (half-angle h = delta/4 < pi/4) is covered by the quad of its circular sector of radius
+    rho: vertices rho d(a), rho / cos(h) d(a + h), rho d(a + 2h) around the centre."""
     K = s.shape[0]
     verts = []
     for k in range(K):
@@ -631,17 +620,22 @@ def support_polygon(s: np.ndarray, theta: np.ndarray, c: float, subarcs: int = 2
         th_n = float(theta[k + 1]) if k + 1 < K else float(theta[0]) + TWO_PI
         s_k = float(s[k])
         s_n = float(s[(k + 1) % K])
-        for j in range(subarcs):
-            a = th_k + (th_n - th_k) * j / subarcs
-            b = th_k + (th_n - th_k) * (j + 1) / subarcs
-            h = 0.5 * (b - a)
-            mid = a + h
-            rho = c * max(_sbar(a, th_k, th_n, s_k, s_n), _sbar(b, th_k, th_n, s_k, s_n),
-                          _chord(a, th_k, th_n, s_k, s_n), _chord(b, th_k, th_n, s_k, s_n))
-            rm = rho / math.cos(h)
-            verts.append((rho * math.cos(a), rho * math.sin(a)))
-            verts.append((rm * math.cos(mid), rm * math.sin(mid)))
-            verts.append((rho * math.cos(b), rho * math.sin(b)))
+        dl = th_n - th_k
+        sbar_mid = 1.0 / math.sqrt(0.5 * (1.0 / (s_k * s_k) + 1.0 / (s_n * s_n)))
+        chord_mid = 2.0 * math.cos(0.5 * dl) / (1.0 / s_k + 1.0 / s_n)
+        r_mid = max(sbar_mid, chord_mid)
+        rho0 = c * max(s_k, r_mid)
+        rho1 = c * max(s_n, r_mid)
+        sec = 1.0 / math.cos(0.25 * dl)
+        a1 = th_k + 0.5 * dl
+        m0 = th_k + 0.25 * dl
+        m1 = th_k + 0.75 * dl
+        verts.append((rho0 * math.cos(th_k), rho0 * math.sin(th_k)))
+        verts.append((rho0 * sec * math.cos(m0), rho0 * sec * math.sin(m0)))
+        verts.append((rho0 * math.cos(a1), rho0 * math.sin(a1)))
+        verts.append((rho1 * math.cos(a1), rho1 * math.sin(a1)))
+        verts.append((rho1 * sec * math.cos(m1), rho1 * sec * math.sin(m1)))
+        verts.append((rho1 * math.cos(th_n), rho1 * math.sin(th_n)))
     return np.array(verts)
 
 

@@ -452,3 +452,26 @@ def test_p11_record_size_matches_table2():
         assert abs(est - float(mb)) / float(mb) < 0.012, (name, est, mb)
     # the same accounting for 3D-GS (59 floats: mu 3, q 4, s 3, o, SH3 48): 336K -> 79.7 MB in Table 2
     assert abs(336e3 * 59 * 4 / 1e6 - 79.7) / 79.7 < 0.012
+
+
+# ---- P9 (adversarial): thin sectors, extreme length ratios, K in {3, 8, 16}, eta in {0, 1, U}, sharp
+# and soft tau; points sampled densely near the support boundary must lie inside the polygon, and the
+# polygon stays within the disc of radius sqrt(2) c max_k s_k used by the frustum cull.
+def test_p9_support_polygon_adversarial():
+    rng = np.random.default_rng(110)
+    from drk_synth import draw_angles
+    for trial in range(60):
+        K = (3, 8, 16)[trial % 3]
+        th = draw_angles(rng, K, 1)[:, 0].astype(np.float64)
+        s = np.exp(rng.uniform(math.log(0.005), math.log(0.5), K))
+        eta = (0.0, 1.0, float(rng.uniform()))[trial % 3]
+        tau = float(rng.uniform(-0.9, 0.99))
+        o = float(rng.uniform(0.02, 1.0))
+        c = float(O.calibrated_radius(_t(o), _t(tau), 1 / 255))
+        poly = O.support_polygon(s, th, c)
+        assert np.hypot(poly[:, 0], poly[:, 1]).max() <= math.sqrt(2) * c * s.max() * (1 + 1e-12)
+        ang = rng.uniform(0, 2 * math.pi, 40000)
+        rad = c * s.max() * rng.uniform(0, 1, 40000) ** 0.5
+        pts = np.stack([rad * np.cos(ang), rad * np.sin(ang)], -1)
+        supp = _alpha(pts[:, 0], pts[:, 1], s, th, eta, tau, o) >= 1 / 255
+        assert _inside(poly, pts[supp]).all(), trial
