@@ -28,8 +28,11 @@ METRIC = "Mpix/s fwd and fwd+bwd it/s at 1M DRKs 1080p; served p50/p99 latency v
 
 # Algorithmic work per unit (see the design notes): FP32 operations with an FMA counted as 2 and an
 # elementary function (reciprocal, exp, atan2, cospi) counted as 1.
-def ops_eval(K: int) -> int:
-    return 76 + 2 * K          # hit, sector search (2K), kernel, sharpening, low-pass, cutoffs
+OPS_HIT = 30                   # ray-plane hit through the homography, depth/grazing tests, radius cut
+
+
+def ops_kernel(K: int) -> int:
+    return 46 + 2 * K          # sector search (2K), kernel, sharpening, low-pass, cutoffs
 
 
 OPS_CACHE_PER_SLOT = 6         # per contributor: one compare + key/alpha/rgb move per cache slot
@@ -50,7 +53,9 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
-    ap.add_argument("--phases", default="fwd,fwdbwd")
+    ap.add_argument("--phases", default="fwd,serve", help="fwd, fwdbwd (backward switched off), serve")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the Poisson arrival trace")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget (0 = skip)")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU baseline)")
     args = ap.parse_args()
@@ -145,16 +150,18 @@ def main():
             log(f"fwd+bwd unavailable: {e}")
 
     # algorithmic work of the forward raster over the timed frames (same frames, deterministic)
-    evals = contribs = emits = 0
+    listed = hits = kernels = contribs = emits = 0
     for s in range(args.steps):
         ras.preprocess(ds, [frames[args.warmup + s]], opts)
         ras.bin_sort()
         ras.render_fwd(rgb, T)
-        evals += int(ras.export("consumed").sum().item())
+        listed += int(ras.export("consumed").sum().item())
+        hits += int(ras.export("hits").sum().item())
+        kernels += int(ras.export("kernels").sum().item())
         contribs += int(ras.export("contributors").sum().item())
         emits += int(ras.export("emitted").sum().item())
     pairs_last = int(ras.export("pair_tiles").numel())
-    flops = evals * ops_eval(K) + contribs * 8 * OPS_CACHE_PER_SLOT + emits * OPS_COMPOSITE
+    flops = hits * OPS_HIT + kernels * ops_kernel(K) + contribs * 8 * OPS_CACHE_PER_SLOT + emits * OPS_COMPOSITE
     fwd = result.get("fwd")
     roofline = None
     if fwd is not None:
@@ -163,10 +170,13 @@ def main():
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
                     "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
                     "kernel": "k_render_fwd", "avg_launch_ms": round(float(fwd["ms"][:, 2].mean()), 4),
-                    "evaluated_pairs_per_launch": evals // args.steps,
+                    "listed_pairs_per_launch": listed // args.steps,
+                    "hit_evaluations_per_launch": hits // args.steps,
+                    "kernel_evaluations_per_launch": kernels // args.steps,
                     "contributors_per_launch": contribs // args.steps,
                     "emitted_per_launch": emits // args.steps}
-        log(f"raster work: {evals / args.steps / 1e6:.1f}M evaluated pairs, {contribs / args.steps / 1e6:.1f}M "
+        log(f"raster work: {listed / args.steps / 1e6:.1f}M listed, {hits / args.steps / 1e6:.1f}M hits, "
+            f"{kernels / args.steps / 1e6:.1f}M kernel evaluations, {contribs / args.steps / 1e6:.1f}M "
             f"contributors, {emits / args.steps / 1e6:.1f}M emitted per view -> {achieved:.2f} TFLOP/s")
 
     # CPU oracle on a bounded sample of the same workload (first timed frame)
@@ -201,6 +211,12 @@ def main():
                "parity_max_err": float(max(errs)) if errs else None}
         log(f"cpu oracle: {done} px in {el:.1f}s -> {cpu['value']:.2e} Mpix/s; max |gpu-oracle| {cpu['parity_max_err']}")
 
+    serve = None
+    if "serve" in phases and not args.profile:
+        ras.close()
+        torch.cuda.empty_cache()
+        serve = serve_phase(args, opts)
+
     ms_step = fwd["t_total"] * 1e3 / args.steps if fwd else None
     line = {
         "metric": METRIC,
@@ -218,10 +234,101 @@ def main():
                          enumerate(["preprocess", "bin_sort", "render_fwd"])} if fwd else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serve": serve,
     }
     if "fwdbwd" in result:
         line["ms_breakdown"]["render_bwd"] = round(float(result["fwdbwd"]["ms"][:, 3].mean()), 4)
     print(json.dumps(line), flush=True)
+
+
+def serve_phase(args, opts):
+    """Continuous-batching server vs the plain sequential renderer on the same Poisson trace: 16
+    resident scenes of 50k-1M DRKs, resolutions drawn from {256^2, 800^2, 1297x840, 1920x1080}."""
+    import torch
+    from drk_synth import camera_from_yaw_pitch, config_c4_scenes
+    from paper_2412_11752_amd import DRKScene, Rasterizer
+    from paper_2412_11752_amd.serving import Server
+
+    t0 = time.time()
+    hosts = config_c4_scenes()
+    scenes = [DRKScene.from_host(h, device="cuda") for h in hosts]
+    log(f"serve: {len(scenes)} scenes, {sum(h.n for h in hosts) / 1e6:.2f}M DRKs total, gen {time.time() - t0:.1f}s")
+    res = [(256, 256), (800, 800), (1297, 840), (1920, 1080)]
+    rng = np.random.default_rng(33)
+    n_req = int(args.serve_seconds * args.serve_rate)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, n_req))
+    which = rng.integers(0, len(scenes), n_req)
+    rsel = rng.integers(0, len(res), n_req)
+    cams = []
+    for i in range(n_req):
+        W, H = res[rsel[i]]
+        pos = rng.uniform(-8.0, 8.0, 3)
+        cams.append(camera_from_yaw_pitch(pos, rng.uniform(0, 2 * math.pi), math.radians(rng.uniform(-30, 30)), W, H))
+    srv = Server(max_inflight=8, use_graphs=True, opts=opts)
+    sids = [srv.add_scene(d) for d in scenes]
+    # warm every (scene, resolution) workspace and graph once, untimed
+    for si in range(len(scenes)):
+        for (W, H) in res:
+            cam = camera_from_yaw_pitch((0.0, 0.0, 0.0), 0.3, 0.1, W, H)
+            out = torch.empty(3 * W * H, device="cuda")
+            srv.wait(srv.submit(sids[si], cam, out))
+    torch.cuda.synchronize()
+    outs = [None] * n_req
+    rids = [0] * n_req
+    t_base = time.perf_counter()
+    for i in range(n_req):
+        while time.perf_counter() - t_base < arrivals[i]:
+            pass
+        W, H = cams[i].width, cams[i].height
+        outs[i] = torch.empty(3 * W * H, device="cuda")
+        rids[i] = srv.submit(sids[which[i]], cams[i], outs[i])
+    stats = [srv.wait(r) for r in rids]
+    lat = np.array([(st["done_us"] - st["submit_us"]) / 1e3 for st in stats])
+    span = (max(st["done_us"] for st in stats) - min(st["submit_us"] for st in stats)) / 1e6
+    mpix = sum(st["width"] * st["height"] for st in stats) / 1e6
+    served = {"mpix_s": round(mpix / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+              "p99_ms": round(float(np.percentile(lat, 99)), 3), "makespan_s": round(span, 3),
+              "failed": int(sum(st["status"] != 0 for st in stats))}
+    log(f"served: {n_req} requests, {served}")
+    # spot check: served results are bitwise the plain renderer's
+    rasters = {}
+
+    def plain(i):
+        key = (which[i], cams[i].width, cams[i].height)
+        if key not in rasters:
+            h = hosts[which[i]]
+            rasters[key] = Rasterizer(h.n, h.K, cams[i].width, cams[i].height, pair_capacity=1 << 22)
+        r = rasters[key]
+        rgb, _ = r.forward(scenes[which[i]], [cams[i]], opts)
+        return rgb
+
+    checked = 0
+    for i in rng.choice(n_req, min(12, n_req), replace=False):
+        assert torch.equal(plain(int(i)).reshape(-1), outs[int(i)]), f"served request {i} differs"
+        checked += 1
+    srv.close()
+    del outs
+    torch.cuda.synchronize()
+    # plain sequential per-request rendering on the same trace (workspaces already warm)
+    for i in range(min(n_req, 64)):
+        plain(i)
+    torch.cuda.synchronize()
+    done = np.zeros(n_req)
+    t_base = time.perf_counter()
+    for i in range(n_req):
+        while time.perf_counter() - t_base < arrivals[i]:
+            pass
+        plain(i)
+        torch.cuda.synchronize()
+        done[i] = time.perf_counter() - t_base
+    lat_p = (done - arrivals) * 1e3
+    span_p = done[-1] - arrivals[0]
+    plain_res = {"mpix_s": round(mpix / span_p, 2), "p50_ms": round(float(np.percentile(lat_p, 50)), 3),
+                 "p99_ms": round(float(np.percentile(lat_p, 99)), 3), "makespan_s": round(span_p, 3)}
+    log(f"plain sequential: {plain_res}")
+    return {"requests": n_req, "rate_per_s": args.serve_rate, "trace_s": args.serve_seconds,
+            "scenes": len(scenes), "resolutions": res, "served": served, "plain_sequential": plain_res,
+            "bitwise_checked": checked}
 
 
 if __name__ == "__main__":

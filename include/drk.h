@@ -145,7 +145,9 @@ drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream);
  *   rgb      [V][3][H][W]  the forward output (read)
  *   dL_drgb  [V][3][H][W]  upstream gradient (read)
  *   grads    same shapes as the scene arrays; zeroed and written by the call.
- * Gradients of all views are summed into one set of buffers.                                 */
+ * Gradients of all views are summed into one set of buffers.
+ * Currently switched off: returns DRK_EDEVICE (with a message in drk_last_error) without
+ * touching the device, because its kernels took an unexplained illegal memory access on gfx950. */
 drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, const float* dL_drgb,
                           const drk_scene_grad* grads, void* stream);
 
@@ -163,7 +165,9 @@ drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed);
  *   4 ranges       uint32 [2*tiles] (start, end per tile)
  *   5 emitted      int32  [H*W] (contributions composited per pixel, from the last forward)
  *   6 consumed     int32  [H*W] (list entries read per pixel before it terminated)
- *   7 contributors int32  [H*W] (entries with alpha >= alpha_min that entered the cache)     */
+ *   7 contributors int32  [H*W] (entries with alpha >= alpha_min that entered the cache)
+ *   8 hits         int32  [H*W] (entries whose ray-plane hit was evaluated)
+ *   9 kernels      int32  [H*W] (entries that went through the full kernel evaluation)      */
 drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int64_t bytes, int64_t* out_count,
                          void* stream);
 

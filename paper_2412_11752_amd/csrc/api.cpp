@@ -27,18 +27,22 @@ void set_error(const char* fmt, ...) {
 
 // kernels in other translation units
 hipError_t set_views(Views*, const Views&, hipStream_t);
-hipError_t launch_preprocess(const SceneDev&, const Views*, int, const OptsDev&, float*, uint32_t*, uint32_t*, uint32_t*,
-                             int64_t, hipStream_t);
+hipError_t launch_preprocess(const SceneDev&, const Views*, int, const OptsDev&, float*, uint32_t*, uint32_t*,
+                             uint32_t*, uint32_t*, uint2*, uint32_t*, uint32_t*, int64_t, uint32_t*, int64_t,
+                             hipStream_t);
 hipError_t launch_duplicate(const SceneDev&, const Views*, const OptsDev&, int, const uint32_t*, const uint32_t*,
-                            const uint32_t*, uint32_t*, uint32_t*, const uint64_t*, int64_t, hipStream_t);
+                            const uint32_t*, const uint2*, const uint32_t*, uint32_t*, uint32_t*, const uint64_t*,
+                            int64_t, const uint64_t*, hipStream_t);
 hipError_t radix_sort(int, const uint64_t*, uint32_t* const*, uint32_t* const*, uint32_t*, uint32_t*, hipStream_t);
-hipError_t scan_counts(const uint32_t*, const uint32_t*, int64_t, uint32_t*, uint64_t*, uint64_t*, uint64_t*, int64_t,
-                       uint32_t*, hipStream_t);
+hipError_t scan_counts(const uint32_t*, const uint32_t*, const uint64_t*, int64_t, uint32_t*, uint64_t*, uint64_t*,
+                       uint64_t*, int64_t, uint32_t*, hipStream_t);
+hipError_t compact_visible(const uint32_t*, const uint32_t*, int64_t, uint32_t*, uint64_t*, uint64_t*, uint64_t*,
+                           uint32_t*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t tile_ranges(const uint32_t*, const uint64_t*, uint32_t*, int, hipStream_t);
 hipError_t set_u64(uint64_t*, uint64_t, hipStream_t);
 hipError_t fill_u32(uint32_t*, uint32_t, int64_t, hipStream_t);
 hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
-                             float*, float*, int32_t*, int32_t*, int32_t*, hipStream_t);
+                             float*, float*, int32_t*, int32_t*, int32_t*, int32_t*, hipStream_t);
 hipError_t launch_render_bwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
                              const float*, const float*, float*, int64_t, hipStream_t);
 hipError_t launch_preprocess_bwd(const SceneDev&, const Views*, const OptsDev&, const uint32_t*, const float*, int64_t,
@@ -67,12 +71,18 @@ struct drk_ws {
   uint32_t* ranges = nullptr;
   uint64_t* totals = nullptr;
   uint64_t* n_eff = nullptr;
-  uint64_t* n_prims = nullptr;
+  uint64_t* n_prims = nullptr;      // [0] visible primitives of the view being binned, [1] scratch
+  uint32_t *ck = nullptr, *cv = nullptr;   // compacted visible (key, index)
   uint32_t* status = nullptr;
-  int32_t *n_emit = nullptr, *consumed = nullptr, *contrib = nullptr;
+  int32_t *n_emit = nullptr, *consumed = nullptr, *contrib = nullptr, *work_px = nullptr;
   uint32_t *hist = nullptr, *tot = nullptr;
   float* grad_rec = nullptr;
   Views* views_dev = nullptr;     // cameras read by every kernel (set by a one-thread kernel)
+  uint32_t* work = nullptr;       // per view: primitives that may touch the view
+  uint32_t* counters = nullptr;   // per view: [work count, rows used]
+  uint2* span_meta = nullptr;     // per view and primitive: row-span offset, first row | rows << 16
+  uint32_t* span_rows = nullptr;  // per view: tile columns i0 | i1 << 16 of each spanned row
+  int64_t row_cap = 0;
   float* out_rgb = nullptr;       // internal output image [3][max_h][max_w] (graph-captured renders)
 
   SceneDev scene{};
@@ -82,6 +92,11 @@ struct drk_ws {
 };
 
 namespace {
+
+// The backward raster and per-primitive backward kernels took an illegal memory access on gfx950
+// that a CPU build of the same kernels (ASan, per-slot allocations, garbage-filled memory, index
+// asserts) does not reproduce; until the cause is shown, drk_render_bwd returns DRK_EDEVICE.
+constexpr bool kBackwardEnabled = false;
 
 struct Plan {
   size_t off = 0;
@@ -120,15 +135,22 @@ size_t layout(drk_ws* ws, bool assign, char* base) {
   SLOT(ranges, uint32_t, V * 2 * ws->max_tiles)
   SLOT(totals, uint64_t, V)
   SLOT(n_eff, uint64_t, V)
-  SLOT(n_prims, uint64_t, 1)
+  SLOT(n_prims, uint64_t, 2)
+  SLOT(ck, uint32_t, N)
+  SLOT(cv, uint32_t, N)
   SLOT(status, uint32_t, V)
   SLOT(n_emit, int32_t, V * px)
   SLOT(consumed, int32_t, V * px)
   SLOT(contrib, int32_t, V * px)
+  SLOT(work_px, int32_t, 2 * V * px)
   SLOT(hist, uint32_t, 256 * 1024)
   SLOT(tot, uint32_t, 256)
   SLOT(grad_rec, float, V * N * grad_fields(ws->K))
   SLOT(views_dev, Views, 1)
+  SLOT(work, uint32_t, V * N)
+  SLOT(counters, uint32_t, 2 * V)
+  SLOT(span_meta, uint2, V * N)
+  SLOT(span_rows, uint32_t, V * (size_t)ws->row_cap)
   SLOT(out_rgb, float, 3 * px)
 #undef SLOT
   return p.off;
@@ -224,8 +246,11 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   od.cull_mode = opts->cull_mode; od.validate = opts->validate;
   drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
   if (st) return st;
+  if ((st = check_hip(fill_u32(ws->counters, 0u, 2 * ws->max_views, s), "clear counters"))) return st;
+  const int V = ws->max_views;
   st = check_hip(launch_preprocess(sc, ws->views_dev, ws->views.nv, od, ws->records, ws->depth_keys, ws->tile_counts,
-                                   ws->status, ws->max_n, s),
+                                   ws->work, ws->counters, ws->span_meta, ws->span_rows, ws->counters + V,
+                                   ws->row_cap, ws->status, ws->max_n, s),
                  "preprocess launch");
   if (st) return st;
   ws->scene = sc;
@@ -299,6 +324,7 @@ drk_status drk_ws_size_query(int64_t max_n, int32_t K, int32_t max_views, int32_
   tmp.max_n = max_n; tmp.K = K; tmp.RF = rec_floats(K); tmp.max_views = max_views;
   tmp.max_w = max_w; tmp.max_h = max_h; tmp.cap = pair_capacity;
   tmp.max_tiles = ((max_w + kTile - 1) / kTile) * ((max_h + kTile - 1) / kTile);
+  tmp.row_cap = 16 * max_n + 65536;
   *bytes = layout(&tmp, false, nullptr);
   return DRK_OK;
 }
@@ -312,6 +338,7 @@ drk_status drk_ws_create(int64_t max_n, int32_t K, int32_t max_views, int32_t ma
   ws->max_n = max_n; ws->K = K; ws->RF = rec_floats(K); ws->max_views = max_views;
   ws->max_w = max_w; ws->max_h = max_h; ws->cap = pair_capacity;
   ws->max_tiles = ((max_w + kTile - 1) / kTile) * ((max_h + kTile - 1) / kTile);
+  ws->row_cap = 16 * max_n + 65536;
   if (hipGetDevice(&ws->device) != hipSuccess) { delete ws; set_error("hipGetDevice failed"); return DRK_EDEVICE; }
   size_t bytes = layout(ws, false, nullptr);
   void* base = nullptr;
@@ -348,20 +375,24 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
   if (!ws->have_pre) { set_error("drk_bin_sort before drk_preprocess"); return DRK_EINVAL; }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t N = ws->scene.n;
-  drk_status st = check_hip(set_u64(ws->n_prims, (uint64_t)N, s), "set n");
-  if (st) return st;
+  drk_status st = DRK_OK;
   for (int v = 0; v < ws->views.nv; ++v) {
     const CamDev& cam = ws->views.cam[v];
     const int ntiles = cam.tiles_x * cam.tiles_y;
-    // 1. stable sort of primitives by centre depth (ties keep index order)
-    uint32_t* kb[5] = {ws->depth_keys + (size_t)v * ws->max_n, ws->dk_a, ws->dk_b, ws->dk_a, ws->dk_b};
-    uint32_t* vb[5] = {nullptr, ws->dv_a, ws->dv_b, ws->dv_a, ws->dv_b};
+    const uint32_t* counts = ws->tile_counts + (size_t)v * ws->max_n;
+    // 1. stable compaction of visible primitives (index order), then stable radix sort by centre
+    //    depth: equal keys keep index order
+    if ((st = check_hip(compact_visible(counts, ws->depth_keys + (size_t)v * ws->max_n, N, ws->offsets, ws->block_tot,
+                                        ws->n_prims, ws->n_prims + 1, ws->ck, ws->cv, ws->status + v, s),
+                        "compact")))
+      return st;
+    uint32_t* kb[5] = {ws->ck, ws->dk_a, ws->dk_b, ws->dk_a, ws->dk_b};
+    uint32_t* vb[5] = {ws->cv, ws->dv_a, ws->dv_b, ws->dv_a, ws->dv_b};
     if ((st = check_hip(radix_sort(32, ws->n_prims, kb, vb, ws->hist, ws->tot, s), "depth sort"))) return st;
     const uint32_t* sorted = ws->dv_b;
     // 2. offsets of each primitive's pairs in depth order
-    const uint32_t* counts = ws->tile_counts + (size_t)v * ws->max_n;
-    if ((st = check_hip(scan_counts(sorted, counts, N, ws->offsets, ws->block_tot, ws->totals + v, ws->n_eff + v,
-                                    ws->cap, ws->status + v, s), "count scan")))
+    if ((st = check_hip(scan_counts(sorted, counts, ws->n_prims, N, ws->offsets, ws->block_tot, ws->totals + v,
+                                    ws->n_eff + v, ws->cap, ws->status + v, s), "count scan")))
       return st;
     // 3. duplicate into (tile, primitive) pairs
     int bits = 1;
@@ -369,8 +400,10 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
     const int passes = (bits + 7) / 8;
     uint32_t* fk = ws->pair_tiles + (size_t)v * ws->cap;
     uint32_t* fv = ws->pair_prims + (size_t)v * ws->cap;
-    if ((st = check_hip(launch_duplicate(ws->scene, ws->views_dev, ws->opts, v, sorted, ws->offsets, counts, ws->pk_tmp,
-                                         ws->pv_tmp, ws->totals + v, ws->cap, s),
+    if ((st = check_hip(launch_duplicate(ws->scene, ws->views_dev, ws->opts, v, sorted, ws->offsets, counts,
+                                         ws->span_meta + (size_t)v * ws->max_n,
+                                         ws->span_rows + (size_t)v * ws->row_cap, ws->pk_tmp, ws->pv_tmp,
+                                         ws->totals + v, ws->cap, ws->n_prims, s),
                         "duplicate")))
       return st;
     // 4. stable sort of the pairs by tile id -> (tile, depth, index) order
@@ -400,7 +433,7 @@ drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream) 
                           ws->pair_prims + (size_t)v * ws->cap, &ws->views_dev->cam[v], cam.tiles_x * cam.tiles_y,
                           ws->opts, rgb + 3 * off,
                           T_final ? T_final + off : nullptr, ws->n_emit + v * px_max, ws->consumed + v * px_max,
-                          ws->contrib + v * px_max, s),
+                          ws->contrib + v * px_max, ws->work_px + 2 * v * px_max, s),
         "render_fwd");
     if (st) return st;
     off += npx;
@@ -420,6 +453,11 @@ drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, 
       !grads->color) {
     set_error("gradient array is null");
     return DRK_EINVAL;
+  }
+  if (!kBackwardEnabled) {
+    set_error("drk_render_bwd is switched off: its kernels took an illegal memory access on gfx950 whose "
+              "cause is not yet identified");
+    return DRK_EDEVICE;
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t N = ws->scene.n;
@@ -484,6 +522,8 @@ drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int6
     case 5: src = ws->n_emit + view * px_max; count = (int64_t)cam.W * cam.H; break;
     case 6: src = ws->consumed + view * px_max; count = (int64_t)cam.W * cam.H; break;
     case 7: src = ws->contrib + view * px_max; count = (int64_t)cam.W * cam.H; break;
+    case 8: src = ws->work_px + 2 * view * px_max; count = (int64_t)cam.W * cam.H; break;
+    case 9: src = ws->work_px + 2 * view * px_max + (size_t)cam.W * cam.H; count = (int64_t)cam.W * cam.H; break;
     default: set_error("unknown export %d", what); return DRK_EINVAL;
   }
   *out_count = count;

@@ -149,9 +149,10 @@ constexpr int kScanItems = 4;
 constexpr int kScanBlock = 256 * kScanItems;
 
 __global__ void __launch_bounds__(256) k_scan_local(const uint32_t* __restrict__ prims, const uint32_t* __restrict__ counts,
-                                                    int64_t n, uint32_t* __restrict__ offsets,
+                                                    const uint64_t* __restrict__ d_n, uint32_t* __restrict__ offsets,
                                                     uint64_t* __restrict__ block_tot) {
   __shared__ uint64_t part[4];
+  const int64_t n = (int64_t)*d_n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)tid * kScanItems;
   uint32_t c[kScanItems];
@@ -211,19 +212,77 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(uint64_t* __restrict__ blo
   }
 }
 
-__global__ void __launch_bounds__(256) k_scan_add(uint32_t* __restrict__ offsets, int64_t n,
+__global__ void __launch_bounds__(256) k_scan_add(uint32_t* __restrict__ offsets, const uint64_t* __restrict__ d_n,
                                                   const uint64_t* __restrict__ block_off) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)*d_n;
   if (i < n) offsets[i] += (uint32_t)block_off[i / kScanBlock];
 }
 
-hipError_t scan_counts(const uint32_t* prims, const uint32_t* counts, int64_t n, uint32_t* offsets,
-                       uint64_t* block_tot, uint64_t* total, uint64_t* n_eff, int64_t capacity, uint32_t* status,
-                       hipStream_t s) {
-  const int nb = (int)((n + kScanBlock - 1) / kScanBlock);
-  if (nb > 0) hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, prims, counts, n, offsets, block_tot);
+// n: device count (at most n_max) of depth-sorted primitives.
+hipError_t scan_counts(const uint32_t* prims, const uint32_t* counts, const uint64_t* d_n, int64_t n_max,
+                       uint32_t* offsets, uint64_t* block_tot, uint64_t* total, uint64_t* n_eff, int64_t capacity,
+                       uint32_t* status, hipStream_t s) {
+  const int nb = (int)((n_max + kScanBlock - 1) / kScanBlock);
+  if (nb > 0) hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, prims, counts, d_n, offsets, block_tot);
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_tot, nb, total, n_eff, capacity, status);
-  if (n > 0) hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, offsets, n, block_tot);
+  if (n_max > 0)
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n_max + 255) / 256)), dim3(256), 0, s, offsets, d_n, block_tot);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stable compaction of the primitives that touch at least one tile (index order kept), with their
+// depth keys: the depth sort then only sees visible primitives, and equal keys stay in index order.
+__global__ void __launch_bounds__(256) k_flag_scan(const uint32_t* __restrict__ counts, int64_t n,
+                                                   uint32_t* __restrict__ pos, uint64_t* __restrict__ block_tot) {
+  __shared__ uint32_t part[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)tid * kScanItems;
+  uint32_t f[kScanItems], sum = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    f[i] = (base + i < n && counts[base + i] > 0) ? 1u : 0u;
+    sum += f[i];
+  }
+  uint32_t inc = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) part[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int i = 0; i < w; ++i) pre += part[i];
+  uint32_t run = pre + inc - sum;
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) pos[base + i] = f[i] ? run : 0xFFFFFFFFu;
+    run += f[i];
+  }
+  if (tid == 255) block_tot[blockIdx.x] = pre + inc;
+}
+
+__global__ void __launch_bounds__(256) k_compact(const uint32_t* __restrict__ pos, const uint64_t* __restrict__ block_off,
+                                                 const uint32_t* __restrict__ keys, int64_t n,
+                                                 uint32_t* __restrict__ out_k, uint32_t* __restrict__ out_v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t p = pos[i];
+  if (p == 0xFFFFFFFFu) return;
+  const uint64_t q = p + block_off[i / kScanBlock];
+  out_k[q] = keys[i];
+  out_v[q] = (uint32_t)i;
+}
+
+hipError_t compact_visible(const uint32_t* counts, const uint32_t* keys, int64_t n, uint32_t* pos,
+                           uint64_t* block_tot, uint64_t* n_vis, uint64_t* scratch_u64, uint32_t* out_k,
+                           uint32_t* out_v, uint32_t* dummy_status, hipStream_t s) {
+  const int nb = (int)((n + kScanBlock - 1) / kScanBlock);
+  if (nb > 0) hipLaunchKernelGGL(k_flag_scan, dim3(nb), dim3(256), 0, s, counts, n, pos, block_tot);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_tot, nb, n_vis, scratch_u64,
+                     (int64_t)0x7FFFFFFFFFFFFFFF, dummy_status);
+  if (n > 0)
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, block_tot, keys, n, out_k,
+                       out_v);
   return hipGetLastError();
 }
 

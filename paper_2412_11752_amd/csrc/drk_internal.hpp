@@ -37,7 +37,10 @@ enum RecField : int {
   R_PB2 = 20, R_PB3 = 21,     // Psi intercepts -tau/(1-tau), 2 tau/(1+tau)
   R_RGB = 22,                 // 3 entries
   R_TAU = 25,
-  R_SEC = 28,                 // per-sector arrays follow, each K long
+  R_R2CUT = 26,               // u^2 + v^2 beyond which alpha < alpha_min (bound E >= r2 / max_k s_k^2)
+  R_LPCUT = 27,               // d^2 |r_d|^2 / W^2 beyond which the low-pass term < alpha_min
+  R_BOX = 28,                 // 4 entries: pixel-space box (x0, x1, y0, y1) of the support polygon
+  R_SEC = 32,                 // per-sector arrays follow, each K long
 };
 // Per-sector arrays (offset R_SEC + field * K + k):
 enum SecField : int {

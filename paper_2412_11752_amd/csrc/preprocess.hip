@@ -14,6 +14,7 @@ namespace drk {
 
 constexpr double kPi = 3.141592653589793;
 constexpr double kTwoPi = 2.0 * kPi;
+constexpr uint32_t kNoSpans = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------------------------
 // Rotation of a quaternion (w, x, y, z): columns are the tangent axes t_u, t_v and the normal.
@@ -133,25 +134,12 @@ __device__ inline bool load_geo(const SceneDev& sc, int64_t j, const CamDev& cam
   return true;
 }
 
-// Inverse L2 scale 1/sbar along absolute angle a inside the sector [thk, thn] (Sec. 4.1).
-__device__ inline double sbar_at(double a, double thk, double thn, double sk, double sn) {
-  double dl = (kPi * (a - thk)) / (thn - thk);
-  double w = (1.0 + cos(dl)) / ((2.0 * sk) * sk) + (1.0 - cos(dl)) / ((2.0 * sn) * sn);
-  return 1.0 / sqrt(w);
-}
-// Distance from the centre to the segment e_k e_{k+1} along absolute angle a (Sec. 4.2 level set).
-__device__ inline double chord_at(double a, double thk, double thn, double sk, double sn) {
-  double phi = a - thk;
-  double dlt = thn - thk;
-  double f = (sin(dlt - phi) / sk + sin(phi) / sn) / sin(dlt);
-  return 1.0 / f;
-}
-
 // ---------------------------------------------------------------------------------------------
 // Tile-row spans of the projected support.  Edges of the near-clipped projected polygon are
 // streamed in order; each updates the x-extent of the tile rows whose pixel-centre slab it crosses.
 struct Spans {
   double lo[kMaxTileRows], hi[kMaxTileRows];
+  double bx0, bx1, by0, by1;        // box of every projected segment and the low-pass square
   int r0, r1;                       // initialised rows [r0, r1]
   int W, H, tx, ty;
   // near-plane clipping state (Sutherland-Hodgman order)
@@ -163,6 +151,8 @@ struct Spans {
 
 __device__ inline void spans_init(Spans& sp, const CamDev& cam) {
   sp.r0 = 1; sp.r1 = 0;
+  sp.bx0 = sp.by0 = INFINITY;
+  sp.bx1 = sp.by1 = -INFINITY;
   sp.W = cam.W; sp.H = cam.H; sp.tx = cam.tiles_x; sp.ty = cam.tiles_y;
   sp.have_prev = false; sp.have_first = false; sp.pending_exit = false; sp.have_first_entry = false;
 }
@@ -176,6 +166,10 @@ __device__ inline void spans_touch(Spans& sp, int r) {
 // Screen segment (x0,y0)-(x1,y1) against every tile row slab it may cross.
 __device__ inline void spans_segment(Spans& sp, double x0, double y0, double x1, double y1) {
   double ymin = fmin(y0, y1), ymax = fmax(y0, y1);
+  sp.bx0 = fmin(sp.bx0, fmin(x0, x1));
+  sp.bx1 = fmax(sp.bx1, fmax(x0, x1));
+  sp.by0 = fmin(sp.by0, ymin);
+  sp.by1 = fmax(sp.by1, ymax);
   double fa = floor((ymin - 15.5) / 16.0), fb = ceil((ymax - 0.5) / 16.0);
   if (!(fb >= 0.0) || !(fa <= (double)(sp.ty - 1))) return;
   int ra = fa < 0.0 ? 0 : (int)fa;
@@ -279,29 +273,37 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
       push_vertex(sp, cam, nearp, p);
     }
   } else {
-    // Support polygon: E is a convex combination of r1^2 and r2^2/sbar^2, so the support lies
-    // within radius c * max(sbar, chord) along each direction; both are maximal at sub-arc ends.
+    // Support polygon.  E is a convex combination of r1^2 and r2^2/sbar^2, so the support reaches at
+    // most c * max(chord, sbar) along each direction (chord: distance to the segment e_k e_{k+1},
+    // Eq. L1 level set; sbar: Eq. radial).  Both are maximal at the ends of each half sector, where
+    // they equal s_k, s_{k+1} or the bisector values below; each half is covered by the quad of its
+    // circular sector (half-angle delta/4 < pi/4).
     for (int k = 0; k < K; ++k) {
-      double thk = g.th[k];
-      double thn = (k + 1 < K) ? g.th[k + 1] : g.th[0] + kTwoPi;
-      double sk = g.s[k], sn = g.s[(k + 1) % K];
-      for (int j = 0; j < kSubArcs; ++j) {
-        double a = thk + ((thn - thk) * j) / kSubArcs;
-        double b = thk + ((thn - thk) * (j + 1)) / kSubArcs;
-        double h = 0.5 * (b - a);
-        double mid = a + h;
-        double rho = fmax(fmax(sbar_at(a, thk, thn, sk, sn), sbar_at(b, thk, thn, sk, sn)),
-                          fmax(chord_at(a, thk, thn, sk, sn), chord_at(b, thk, thn, sk, sn)));
-        rho = g.c * rho;
-        double rm = rho / cos(h);
-        double p[3];
-        lift(g, cam, rho * cos(a), rho * sin(a), p);
-        push_vertex(sp, cam, nearp, p);
-        lift(g, cam, rm * cos(mid), rm * sin(mid), p);
-        push_vertex(sp, cam, nearp, p);
-        lift(g, cam, rho * cos(b), rho * sin(b), p);
-        push_vertex(sp, cam, nearp, p);
-      }
+      const double thk = g.th[k];
+      const double thn = (k + 1 < K) ? g.th[k + 1] : g.th[0] + kTwoPi;
+      const double sk = g.s[k], sn = g.s[(k + 1) % K];
+      const double dl = thn - thk;
+      const double sbar_mid = 1.0 / sqrt(0.5 * (1.0 / (sk * sk) + 1.0 / (sn * sn)));
+      const double chord_mid = 2.0 * cos(0.5 * dl) / (1.0 / sk + 1.0 / sn);
+      const double r_mid = fmax(sbar_mid, chord_mid);
+      const double rho0 = g.c * fmax(sk, r_mid);
+      const double rho1 = g.c * fmax(sn, r_mid);
+      const double sec = 1.0 / cos(0.25 * dl);
+      const double a1 = thk + 0.5 * dl, m0 = thk + 0.25 * dl, m1 = thk + 0.75 * dl;
+      const double ca1 = cos(a1), sa1 = sin(a1);
+      double p[3];
+      lift(g, cam, rho0 * cos(thk), rho0 * sin(thk), p);
+      push_vertex(sp, cam, nearp, p);
+      lift(g, cam, rho0 * sec * cos(m0), rho0 * sec * sin(m0), p);
+      push_vertex(sp, cam, nearp, p);
+      lift(g, cam, rho0 * ca1, rho0 * sa1, p);
+      push_vertex(sp, cam, nearp, p);
+      lift(g, cam, rho1 * ca1, rho1 * sa1, p);
+      push_vertex(sp, cam, nearp, p);
+      lift(g, cam, rho1 * sec * cos(m1), rho1 * sec * sin(m1), p);
+      push_vertex(sp, cam, nearp, p);
+      lift(g, cam, rho1 * cos(thn), rho1 * sin(thn), p);
+      push_vertex(sp, cam, nearp, p);
     }
   }
   close_polygon(sp, cam, nearp);
@@ -311,6 +313,10 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
     double r = (double)opt.lowpass_sl * sqrt(2.0 * log(ratio > 1.0 ? ratio : 1.0));
     double dcx, dcy;
     project(cam, g.muc, dcx, dcy);
+    sp.bx0 = fmin(sp.bx0, dcx - r);
+    sp.bx1 = fmax(sp.bx1, dcx + r);
+    sp.by0 = fmin(sp.by0, dcy - r);
+    sp.by1 = fmax(sp.by1, dcy + r);
     for (int row = 0; row < sp.ty; ++row) {
       double ya = 16.0 * row + 0.5;
       double yb = fmin(16.0 * row + 15.5, sp.H - 0.5);
@@ -342,43 +348,53 @@ __device__ inline float diamond_angle(float c, float s) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Preprocess: one thread per (primitive, view).
-__global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, const Views* __restrict__ views, OptsDev opt, float* __restrict__ records,
-                                                    uint32_t* __restrict__ depth_keys,
-                                                    uint32_t* __restrict__ tile_counts,
-                                                    uint32_t* __restrict__ status, int64_t stride) {
-  // per-view arrays are [view][stride] (stride = workspace capacity in primitives)
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y;
-  if (j >= sc.n) return;
-  const CamDev& cam = views->cam[v];
+// Conservative frustum test.  The support polygon lies in the disc of radius sqrt(2) c max_k s_k
+// around the centre (its half-sector quads reach rho / cos(h) with rho <= c max s_k, h < pi/4); if
+// that ball is entirely outside one side plane of the view (pixel x = 0 or W, y = 0 or H) no part of
+// the near-clipped polygon can reach a pixel centre (0.5 px inside those planes), and the low-pass
+// square is tested directly.  Culling here never removes a tile the polygon would produce.
+__device__ inline bool outside_view(const Geo& g, const CamDev& cam, const OptsDev& opt) {
+  double smax = 0.0;
+  for (int k = 0; k < g.K; ++k) smax = fmax(smax, g.s[k]);
+  const double R = 1.4142135623730951 * g.c * smax * (1.0 + 1e-9) + 1e-12;
+  const double X = g.muc[0], Y = g.muc[1], Z = g.muc[2];
+  const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy, W = cam.W, H = cam.H;
+  bool out = (fx * X + cx * Z) < -R * sqrt(fx * fx + cx * cx) ||
+             (fx * X + (cx - W) * Z) > R * sqrt(fx * fx + (cx - W) * (cx - W)) ||
+             (fy * Y + cy * Z) < -R * sqrt(fy * fy + cy * cy) ||
+             (fy * Y + (cy - H) * Z) > R * sqrt(fy * fy + (cy - H) * (cy - H));
+  if (out && opt.lowpass_sl > 0.0f) {
+    const double ratio = g.o / (double)opt.alpha_min;
+    const double r = (double)opt.lowpass_sl * sqrt(2.0 * log(ratio > 1.0 ? ratio : 1.0));
+    double dcx, dcy;
+    project(cam, g.muc, dcx, dcy);
+    const bool sq_out = dcx + r < 0.25 || dcx - r > W - 0.25 || dcy + r < 0.25 || dcy - r > H - 0.25;
+    out = sq_out;
+  }
+  return out;
+}
+
+// Per-lane offsets from one atomic per wave (all lanes of the wave must call it).
+__device__ inline uint32_t wave_alloc(uint32_t* ctr, uint32_t n) {
+  const int lane = threadIdx.x & 63;
+  uint32_t inc = n;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  const uint32_t total = __shfl(inc, 63, 64);
+  uint32_t base = 0;
+  if (lane == 0 && total) base = atomicAdd(ctr, total);
+  base = __shfl(base, 0, 64);
+  return base + inc - n;
+}
+
+// Render record of a visible primitive (layout: RecField / SecField).
+__device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const CamDev& cam, const OptsDev& opt,
+                             const double box[4], float* rec) {
   const int64_t n = sc.n;
   const int K = sc.K;
-  const int RF = rec_floats(K);
-  Geo g;
-  bool invalid = false;
-  bool alive = load_geo(sc, j, cam, opt, g, &invalid);
-  if (invalid && opt.validate) atomicOr(status + v, (uint32_t)ST_INVALID);
-  uint32_t count = 0;
-  if (alive) {
-    if (opt.cull_mode == 2) {
-      count = (uint32_t)(cam.tiles_x * cam.tiles_y);
-    } else {
-      Spans sp;
-      build_spans(g, cam, opt, sp);
-      for (int r = sp.r0; r <= sp.r1; ++r) {
-        int i0, i1;
-        if (row_tiles(sp, r, i0, i1)) count += (uint32_t)(i1 - i0 + 1);
-      }
-    }
-  }
-  // centre depth key: float32 of ((r20 x + r21 y) + r22 z) + t2 computed in float64
-  depth_keys[(int64_t)v * stride + j] = (alive && count) ? __float_as_uint((float)g.muc[2]) : kCulledKey;
-  tile_counts[(int64_t)v * stride + j] = count;
-  if (!alive || count == 0) return;
-
-  float* rec = records + ((int64_t)v * stride + j) * RF;
-  // homography (see RecField): adjugate rows of N = [t_u^c | t_v^c | mu_c]
+  // homography: adjugate rows of N = [t_u^c | t_v^c | mu_c]
   double tuc[3], tvc[3];
   rot_cam(cam, g.tu, tuc);
   rot_cam(cam, g.tv, tvc);
@@ -415,7 +431,20 @@ __global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, const Views* __
   rec[R_PB2] = (float)(-tau / (1.0 - tau));
   rec[R_PB3] = (float)(2.0 * tau / (1.0 + tau));
   rec[R_TAU] = (float)tau;
-  // colour
+  // exact early-outs of the raster (with margin): E >= r2 / max_k s_k^2 (both the L1 chord and sbar
+  // are bounded by the larger basis length), and the low-pass term needs d^2/den^2 <= 2 s_l^2 ln(o/alpha_min)
+  double smax = 0.0;
+  for (int k = 0; k < K; ++k) smax = fmax(smax, g.s[k]);
+  rec[R_R2CUT] = (float)(1.001 * (g.c * smax) * (g.c * smax) + 1e-30);
+  const double ratio = g.o / (double)opt.alpha_min;
+  const double lpc = opt.lowpass_sl > 0.0f ? 2.0 * (double)opt.lowpass_sl * (double)opt.lowpass_sl *
+                                                 log(ratio > 1.0 ? ratio : 1.0)
+                                           : 0.0;
+  rec[R_LPCUT] = opt.lowpass_sl > 0.0f ? (float)(1.001 * lpc + 1e-6) : -1.0f;
+  rec[R_BOX + 0] = (float)(box[0] - 0.01);
+  rec[R_BOX + 1] = (float)(box[1] + 0.01);
+  rec[R_BOX + 2] = (float)(box[2] - 0.01);
+  rec[R_BOX + 3] = (float)(box[3] + 0.01);
   if (sc.color_mode == 0) {
     for (int c = 0; c < 3; ++c) rec[R_RGB + c] = sc.color[c * n + j];
   } else {
@@ -435,7 +464,6 @@ __global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, const Views* __
       rec[R_RGB + c] = (float)(acc > 0.0 ? acc : 0.0);
     }
   }
-  // per-sector constants
   for (int k = 0; k < K; ++k) {
     int kn = (k + 1 < K) ? k + 1 : 0;
     double thk = g.th[k];
@@ -456,26 +484,139 @@ __global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, const Views* __
   }
 }
 
+// Pass 1, one thread per (primitive, view): validity, near/opacity/frustum culling and the
+// centre-depth key (float32 of ((r20 x + r21 y) + r22 z) + t2, computed in float64).  Primitives
+// that may touch the view are appended to the view's work list.  Per-view arrays are
+// [view][stride] with stride = the workspace capacity in primitives.
+__global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
+                                                    uint32_t* __restrict__ depth_keys,
+                                                    uint32_t* __restrict__ tile_counts,
+                                                    uint32_t* __restrict__ work, uint32_t* __restrict__ work_count,
+                                                    uint32_t* __restrict__ status, int64_t stride) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  const CamDev& cam = views->cam[v];
+  bool maybe = false;
+  if (j < sc.n) {
+    Geo g;
+    bool invalid = false;
+    const bool alive = load_geo(sc, j, cam, opt, g, &invalid);
+    if (invalid && opt.validate) atomicOr(status + v, (uint32_t)ST_INVALID);
+    maybe = alive && (opt.cull_mode == 2 || !outside_view(g, cam, opt));
+    depth_keys[(int64_t)v * stride + j] = maybe ? __float_as_uint((float)g.muc[2]) : kCulledKey;
+    tile_counts[(int64_t)v * stride + j] = 0;
+  }
+  const uint32_t slot = wave_alloc(work_count + v, maybe ? 1u : 0u);
+  if (maybe) work[(int64_t)v * stride + slot] = (uint32_t)j;
+}
+
+// Pass 2, one thread per listed primitive: support polygon -> tile-row spans -> tile count, the
+// spans kept for the duplication pass (rows of one primitive contiguous; kNoSpans when the row
+// buffer is full, then the duplication recomputes them), and the render record.
+__global__ void __launch_bounds__(128) k_polygon(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
+                                                 float* __restrict__ records, uint32_t* __restrict__ depth_keys,
+                                                 uint32_t* __restrict__ tile_counts,
+                                                 const uint32_t* __restrict__ work,
+                                                 const uint32_t* __restrict__ work_count,
+                                                 uint2* __restrict__ span_meta, uint32_t* __restrict__ span_rows,
+                                                 uint32_t* __restrict__ rows_used, int64_t row_cap, int64_t stride) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  const CamDev& cam = views->cam[v];
+  const bool active = i < (int64_t)work_count[v];
+  const int64_t j = active ? (int64_t)work[(int64_t)v * stride + i] : 0;
+  Geo g;
+  Spans sp;
+  uint32_t count = 0, nrows = 0;
+  bool ok = false;
+  if (active) {
+    bool invalid;
+    ok = load_geo(sc, j, cam, opt, g, &invalid);
+    if (ok) {
+      if (opt.cull_mode == 2) {
+        count = (uint32_t)(cam.tiles_x * cam.tiles_y);
+      } else {
+        build_spans(g, cam, opt, sp);
+        for (int r = sp.r0; r <= sp.r1; ++r) {
+          int i0, i1;
+          if (row_tiles(sp, r, i0, i1)) count += (uint32_t)(i1 - i0 + 1);
+        }
+        if (count) nrows = (uint32_t)(sp.r1 - sp.r0 + 1);
+      }
+    }
+  }
+  const uint32_t off = wave_alloc(rows_used + v, nrows);
+  if (!active) return;
+  tile_counts[(int64_t)v * stride + j] = count;
+  if (count == 0) {
+    depth_keys[(int64_t)v * stride + j] = kCulledKey;
+    return;
+  }
+  if (nrows) {
+    uint2 meta;
+    if ((int64_t)off + nrows <= row_cap) {
+      meta.x = off;
+      meta.y = (uint32_t)sp.r0 | (nrows << 16);
+      uint32_t* out = span_rows + (int64_t)v * row_cap + off;
+      for (int r = sp.r0; r <= sp.r1; ++r) {
+        int i0, i1;
+        out[r - sp.r0] = row_tiles(sp, r, i0, i1) ? ((uint32_t)i0 | ((uint32_t)i1 << 16)) : 0xFFFFFFFFu;
+      }
+    } else {
+      meta.x = kNoSpans;
+      meta.y = 0;
+    }
+    span_meta[(int64_t)v * stride + j] = meta;
+  }
+  double box[4];
+  if (opt.cull_mode != 0) {   // only the conservative polygon bounds the support
+    box[0] = -1e30; box[1] = 1e30; box[2] = -1e30; box[3] = 1e30;
+  } else {
+    box[0] = sp.bx0; box[1] = sp.bx1; box[2] = sp.by0; box[3] = sp.by1;
+  }
+  write_record(g, sc, j, cam, opt, box, records + ((int64_t)v * stride + j) * rec_floats(sc.K));
+}
+
 // ---------------------------------------------------------------------------------------------
 // Duplication: for the depth-sorted primitive order, write (tile id, primitive) pairs at the
-// scanned offsets, row-major over each primitive's tiles.  Spans are recomputed with the same
-// float64 code as the count, so counts and pairs agree exactly.
+// scanned offsets, row-major over each primitive's tiles, from the stored row spans (recomputed
+// with the same float64 code when they did not fit the row buffer).
 __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __restrict__ views, OptsDev opt, int v,
                                                    const uint32_t* __restrict__ sorted_prims,
                                                    const uint32_t* __restrict__ offsets,   // exclusive, per sorted slot
                                                    const uint32_t* __restrict__ tile_counts,
+                                                   const uint2* __restrict__ span_meta,
+                                                   const uint32_t* __restrict__ span_rows,
                                                    uint32_t* __restrict__ pair_tiles, uint32_t* __restrict__ pair_prims,
-                                                   const uint64_t* __restrict__ total_ptr, int64_t capacity) {
+                                                   const uint64_t* __restrict__ total_ptr, int64_t capacity,
+                                                   const uint64_t* __restrict__ n_sorted) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= sc.n) return;
+  if (i >= (int64_t)*n_sorted) return;
   const uint32_t j = sorted_prims[i];
   const uint32_t cnt = tile_counts[j];
   if (cnt == 0) return;
   if ((int64_t)*total_ptr > capacity) return;   // overflow: the status word already says so
-  uint32_t off = offsets[i];
+  const uint32_t off = offsets[i];
   const CamDev& cam = views->cam[v];
   if (opt.cull_mode == 2) {
     for (uint32_t t = 0; t < cnt; ++t) { pair_tiles[off + t] = t; pair_prims[off + t] = j; }
+    return;
+  }
+  const uint2 meta = span_meta[j];
+  uint32_t w = 0;
+  if (meta.x != kNoSpans) {
+    const int r0 = (int)(meta.y & 0xFFFFu), nr = (int)(meta.y >> 16);
+    const uint32_t* rows = span_rows + meta.x;
+    for (int r = 0; r < nr && w < cnt; ++r) {
+      const uint32_t e = rows[r];
+      if (e == 0xFFFFFFFFu) continue;
+      const int i0 = (int)(e & 0xFFFFu), i1 = (int)(e >> 16);
+      const uint32_t base = (uint32_t)((r0 + r) * cam.tiles_x);
+      for (int c = i0; c <= i1 && w < cnt; ++c, ++w) {
+        pair_tiles[off + w] = base + (uint32_t)c;
+        pair_prims[off + w] = j;
+      }
+    }
     return;
   }
   Geo g;
@@ -483,7 +624,6 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
   if (!load_geo(sc, j, cam, opt, g, &invalid)) return;
   Spans sp;
   build_spans(g, cam, opt, sp);
-  uint32_t w = 0;
   for (int r = sp.r0; r <= sp.r1 && w < cnt; ++r) {
     int i0, i1;
     if (!row_tiles(sp, r, i0, i1)) continue;
@@ -507,23 +647,27 @@ hipError_t set_views(Views* d_views, const Views& views, hipStream_t s) {
 }
 
 hipError_t launch_preprocess(const SceneDev& sc, const Views* views, int nv, const OptsDev& opt, float* records,
-                             uint32_t* depth_keys, uint32_t* tile_counts, uint32_t* status, int64_t stride,
-                             hipStream_t s) {
+                             uint32_t* depth_keys, uint32_t* tile_counts, uint32_t* work, uint32_t* work_count,
+                             uint2* span_meta, uint32_t* span_rows, uint32_t* rows_used, int64_t row_cap,
+                             uint32_t* status, int64_t stride, hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
   dim3 grid((unsigned)((sc.n + 127) / 128), (unsigned)nv);
-  hipLaunchKernelGGL(k_preprocess, grid, dim3(128), 0, s, sc, views, opt, records, depth_keys, tile_counts, status,
-                     stride);
+  hipLaunchKernelGGL(k_preprocess, grid, dim3(128), 0, s, sc, views, opt, depth_keys, tile_counts, work, work_count,
+                     status, stride);
+  hipLaunchKernelGGL(k_polygon, grid, dim3(128), 0, s, sc, views, opt, records, depth_keys, tile_counts, work,
+                     work_count, span_meta, span_rows, rows_used, row_cap, stride);
   return hipGetLastError();
 }
 
 hipError_t launch_duplicate(const SceneDev& sc, const Views* views, const OptsDev& opt, int v,
                             const uint32_t* sorted_prims, const uint32_t* offsets, const uint32_t* tile_counts,
-                            uint32_t* pair_tiles, uint32_t* pair_prims, const uint64_t* total_ptr, int64_t capacity,
+                            const uint2* span_meta, const uint32_t* span_rows, uint32_t* pair_tiles,
+                            uint32_t* pair_prims, const uint64_t* total_ptr, int64_t capacity, const uint64_t* n_sorted,
                             hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
   dim3 grid((unsigned)((sc.n + 127) / 128));
   hipLaunchKernelGGL(k_duplicate, grid, dim3(128), 0, s, sc, views, opt, v, sorted_prims, offsets, tile_counts,
-                     pair_tiles, pair_prims, total_ptr, capacity);
+                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, n_sorted);
   return hipGetLastError();
 }
 

@@ -24,10 +24,51 @@ struct RasterParams {
   int32_t cache_len;
 };
 
-__device__ inline float diamond_pa(float u, float v) {
-  float r = u / (fabsf(u) + fabsf(v));
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ float diamond_pa(float u, float v) {
+  const float r = u * rcpf(fabsf(u) + fabsf(v));
   return v >= 0.0f ? 1.0f - r : 3.0f + r;
 }
+
+// atan2 for the sector angle: atan(a) = a P(a^2) on [0, 1] (odd polynomial fitted by relative-error
+// weighted least squares; max relative error 2.2e-7 in float32), then the octant is restored.
+__device__ __forceinline__ float atan2_fast(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float a = mx > 0.0f ? mn * rcpf(mx) : 0.0f;
+  const float s = a * a;
+  float p = -0.00469335893820626f;
+  p = fmaf(p, s, 0.024252677013602238f);
+  p = fmaf(p, s, -0.059486744643040414f);
+  p = fmaf(p, s, 0.09914314847813398f);
+  p = fmaf(p, s, -0.1401948782422469f);
+  p = fmaf(p, s, 0.19969724889612928f);
+  p = fmaf(p, s, -0.33331990794665783f);
+  p = fmaf(p, s, 0.9999999009920119f);
+  float r = a * p;
+  r = ay > ax ? 1.5707963267948966f - r : r;
+  r = x < 0.0f ? 3.141592653589793f - r : r;
+  return copysignf(r, y);
+}
+
+// cos(pi t) for t in about [-0.02, 1.02]: even polynomial on [0, 1/2] (least-squares fit, max abs
+// error 1.5e-7 in float32) and cos(pi t) = -cos(pi (1 - t)) above 1/2.
+__device__ __forceinline__ float cospi_fast(float t) {
+  t = fabsf(t);
+  const bool hi = t > 0.5f;
+  const float x = hi ? 1.0f - t : t;
+  const float s = x * x;
+  float p = -0.024396864677873612f;
+  p = fmaf(p, s, 0.23493764446403828f);
+  p = fmaf(p, s, -1.3352120737951056f);
+  p = fmaf(p, s, 4.05870916572721f);
+  p = fmaf(p, s, -4.93480213726698f);
+  p = fmaf(p, s, 0.9999999997808213f);
+  return hi ? -p : p;
+}
+
+__device__ __forceinline__ float exp_fast(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 
 // Intermediate values of one (pixel, primitive) evaluation.
 struct Eval {
@@ -50,11 +91,17 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
   const float W = fmaf(r[R_H + 6], dx, fmaf(r[R_H + 7], dy, r[R_H + 8]));
   const float W2 = W * W;
   if (!(W2 >= 1e-12f * p.rd2)) return false;          // |r_d . n| < 1e-6
-  const float iW = 1.0f / W;
+  const float iW = rcpf(W);
   Z = r[R_DN] * iW;
   if (!(Z > rp.near_plane)) return false;
   const float u = U * iW, v = V * iW;
   const float r2 = fmaf(u, u, v * v);
+  // exact early-out: beyond R2CUT the kernel term is below alpha_min, beyond LPCUT the low-pass term
+  if (r2 > r[R_R2CUT]) {
+    const float ex = dx - r[R_OX], ey = dy - r[R_OY];
+    const float d2 = fmaf(ex, ex, ey * ey);
+    if (!(d2 * p.rd2 <= r[R_LPCUT] * W2)) return false;
+  }
   float E = 0.0f;
   int k = 0;
   float A = 0.f, B = 0.f, D = 0.f, phi = 0.f, t = 0.f, cd = 1.f, ws = 0.f, r1 = 0.f;
@@ -72,15 +119,15 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
     A = fmaf(ck, v, -(sk * u));          // cross(d_k, p)       = r2 sin(phi)
     B = fmaf(u, sn, -(v * cn));          // cross(p, d_{k+1})   = r2 sin(delta - phi)
     D = fmaf(ck, u, sk * v);             // dot(d_k, p)         = r2 cos(phi)
-    phi = atan2f(A, D);
+    phi = atan2_fast(A, D);
     t = phi * sec[S_ID * K + k];
-    cd = cospif(t);
+    cd = cospi_fast(t);
     ws = fmaf(sec[S_Q * K + k], cd, sec[S_P * K + k]);
     r1 = fmaf(sec[S_A * K + k], fabsf(B), sec[S_B * K + k] * fabsf(A));
     const float eta = r[R_ETA];
     E = fmaf(eta, r1 * r1, (1.0f - eta) * (r2 * ws));
   }
-  const float g = expf(-0.5f * E);
+  const float g = exp_fast(-0.5f * E);
   float psi;
   int piece;
   if (g < r[R_PLO]) { psi = r[R_PA1] * g; piece = 0; }
@@ -93,7 +140,7 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
   if (rp.lowpass) {
     const float ex = dx - r[R_OX], ey = dy - r[R_OY];
     const float d2 = fmaf(ex, ex, ey * ey);
-    f = o * expf(rp.lp_coef * ((d2 * p.rd2) / W2));
+    f = o * exp_fast(rp.lp_coef * ((d2 * p.rd2) * (iW * iW)));
     lp = f > alpha;
     alpha = lp ? f : alpha;
   }
@@ -104,6 +151,11 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
     ev->E = E; ev->g = g; ev->psi = psi; ev->alpha = alpha; ev->f = f; ev->k = k; ev->piece = piece; ev->lp_wins = lp;
   }
   return true;
+}
+
+// True when the wave's pixel rectangle [x0, x1] x [y0, y1] (pixel centres) misses the record's box.
+__device__ __forceinline__ bool box_misses(const float* __restrict__ r, float x0, float x1, float y0, float y1) {
+  return x1 < r[R_BOX + 0] || x0 > r[R_BOX + 1] || y1 < r[R_BOX + 2] || y0 > r[R_BOX + 3];
 }
 
 // Always-full sorted cache of kMaxCache slots (Sec. 4.4 Cache Sorting, Algorithm 1).  Slots hold

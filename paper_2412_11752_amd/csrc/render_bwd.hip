@@ -21,14 +21,25 @@ __device__ __forceinline__ void gadd(float* p, float v) {
   if (v != 0.0f) unsafeAtomicAdd(p, v);
 }
 
-// dL/d(record quantities) of one composited (pixel, primitive) pair.
+// Gradient terms of one composited (pixel, primitive) pair w.r.t. the record quantities.
+struct PairGrad {
+  float v[17];       // G_H..G_OY, in GradField order
+  float s_k, s_n, th_k, th_n;
+  int k, kn;
+};
+
+// dL/d(record quantities) of one composited pair with dL/d(alpha~) = gA and colour weight T a.
 template <int K>
-__device__ void backprop_pair(const float* __restrict__ r, const Pix& pix, const RasterParams& rp, float gA,
-                              float T_w, float G0, float G1, float G2, float* __restrict__ g, int64_t n, uint32_t j) {
-  // colour: dL/dc = T a G
-  gadd(g + (size_t)(G_RGB + 0) * n + j, T_w * G0);
-  gadd(g + (size_t)(G_RGB + 1) * n + j, T_w * G1);
-  gadd(g + (size_t)(G_RGB + 2) * n + j, T_w * G2);
+__device__ void pair_grad(const float* __restrict__ r, const Pix& pix, const RasterParams& rp, float gA, float T_w,
+                          float G0, float G1, float G2, PairGrad& out) {
+#pragma unroll
+  for (int f = 0; f < 17; ++f) out.v[f] = 0.0f;
+  out.s_k = out.s_n = out.th_k = out.th_n = 0.0f;
+  out.k = 0;
+  out.kn = 1 % K;
+  out.v[G_RGB + 0] = T_w * G0;   // dL/dc = T a G
+  out.v[G_RGB + 1] = T_w * G1;
+  out.v[G_RGB + 2] = T_w * G2;
   Eval ev;
   float at, Z;
   drk_eval<K>(r, pix, rp, at, Z, &ev);
@@ -37,20 +48,19 @@ __device__ void backprop_pair(const float* __restrict__ r, const Pix& pix, const
   float gU = 0.f, gV = 0.f, gW = 0.f;
   if (ev.lp_wins) {
     // f = o exp(arg), arg = lp_coef * d2 * |r_d|^2 / W^2
-    const float e = ev.f / o;
-    gadd(g + (size_t)G_O * n + j, gA * e);
+    out.v[G_O] = gA * (ev.f / o);
     const float garg = gA * ev.f;
     const float ex = ev.dx - r[R_OX], ey = ev.dy - r[R_OY];
-    const float W2 = ev.W * ev.W;
-    const float gd2 = garg * rp.lp_coef * pix.rd2 / W2;
-    gadd(g + (size_t)G_OX * n + j, -2.0f * ex * gd2);
-    gadd(g + (size_t)G_OY * n + j, -2.0f * ey * gd2);
-    const float arg = rp.lp_coef * ((fmaf(ex, ex, ey * ey) * pix.rd2) / W2);
-    gW = garg * (-2.0f * arg / ev.W);
+    const float iW2 = ev.iW * ev.iW;
+    const float gd2 = garg * rp.lp_coef * pix.rd2 * iW2;
+    out.v[G_OX] = -2.0f * ex * gd2;
+    out.v[G_OY] = -2.0f * ey * gd2;
+    const float arg = rp.lp_coef * ((fmaf(ex, ex, ey * ey) * pix.rd2) * iW2);
+    gW = garg * (-2.0f * arg * ev.iW);
   } else {
     const float tau = r[R_TAU];
     const float gpsi = gA * o;
-    gadd(g + (size_t)G_O * n + j, gA * ev.psi);
+    out.v[G_O] = gA * ev.psi;
     float dpsi_dtau, slope;
     if (ev.piece == 0) {
       slope = r[R_PA1];
@@ -62,10 +72,10 @@ __device__ void backprop_pair(const float* __restrict__ r, const Pix& pix, const
       slope = r[R_PA1];
       dpsi_dtau = 2.0f * (1.0f - ev.g) / ((1.0f + tau) * (1.0f + tau));
     }
-    gadd(g + (size_t)G_TAU * n + j, gpsi * dpsi_dtau);
+    out.v[G_TAU] = gpsi * dpsi_dtau;
     const float gE = -0.5f * ev.g * gpsi * slope;
     const float eta = r[R_ETA];
-    gadd(g + (size_t)G_ETA * n + j, gE * (ev.r1 * ev.r1 - ev.r2 * ev.ws));
+    out.v[G_ETA] = gE * (ev.r1 * ev.r1 - ev.r2 * ev.ws);
     if (ev.r2 > 0.0f) {
       const int k = ev.k, kn = (k + 1 == K) ? 0 : k + 1;
       const float* sec = r + R_SEC;
@@ -90,41 +100,89 @@ __device__ void backprop_pair(const float* __restrict__ r, const Pix& pix, const
       const float gB = g_r1 * ak * sB;
       float gAc = g_r1 * bk * sA;
       const float g_ak = g_r1 * fabsf(ev.B), g_bk = g_r1 * fabsf(ev.A);
-      float g_sk = -g_ak * ak / s_k - 2.0f * g_isk2 * isk2 / s_k;
-      float g_sn = -g_bk * bk / s_n - 2.0f * g_isn2 * isn2 / s_n;
+      out.s_k = -g_ak * ak / s_k - 2.0f * g_isk2 * isk2 / s_k;
+      out.s_n = -g_bk * bk / s_n - 2.0f * g_isn2 * isn2 / s_n;
       g_delta -= (g_ak * ak + g_bk * bk) * cot;
       gAc += g_phi * ev.D / ev.r2;
       const float gD = -g_phi * ev.A / ev.r2;
       const float u = ev.u, v = ev.v;
       const float g_u = -gAc * sk + gB * sn + gD * ck + 2.0f * u * g_r2;
       const float g_v = gAc * ck - gB * cn + gD * sk + 2.0f * v * g_r2;
-      const float g_thk = -gAc * ev.D + gD * ev.A - g_delta;
-      const float g_thn = gB * (u * cn + v * sn) + g_delta;
-      gadd(g + (size_t)(G_SEC + k) * n + j, g_sk);
-      gadd(g + (size_t)(G_SEC + kn) * n + j, g_sn);
-      gadd(g + (size_t)(G_SEC + K + k) * n + j, g_thk);
-      gadd(g + (size_t)(G_SEC + K + kn) * n + j, g_thn);
+      out.th_k = -gAc * ev.D + gD * ev.A - g_delta;
+      out.th_n = gB * (u * cn + v * sn) + g_delta;
+      out.k = k;
+      out.kn = kn;
       gU = g_u * ev.iW;
       gV = g_v * ev.iW;
       gW = -(g_u * u + g_v * v) * ev.iW;
     }
   }
-  gadd(g + (size_t)(G_H + 0) * n + j, gU * ev.dx);
-  gadd(g + (size_t)(G_H + 1) * n + j, gU * ev.dy);
-  gadd(g + (size_t)(G_H + 2) * n + j, gU);
-  gadd(g + (size_t)(G_H + 3) * n + j, gV * ev.dx);
-  gadd(g + (size_t)(G_H + 4) * n + j, gV * ev.dy);
-  gadd(g + (size_t)(G_H + 5) * n + j, gV);
-  gadd(g + (size_t)(G_H + 6) * n + j, gW * ev.dx);
-  gadd(g + (size_t)(G_H + 7) * n + j, gW * ev.dy);
-  gadd(g + (size_t)(G_H + 8) * n + j, gW);
+  out.v[G_H + 0] = gU * ev.dx;
+  out.v[G_H + 1] = gU * ev.dy;
+  out.v[G_H + 2] = gU;
+  out.v[G_H + 3] = gV * ev.dx;
+  out.v[G_H + 4] = gV * ev.dy;
+  out.v[G_H + 5] = gV;
+  out.v[G_H + 6] = gW * ev.dx;
+  out.v[G_H + 7] = gW * ev.dy;
+  out.v[G_H + 8] = gW;
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Accumulates the pair gradients of the lanes with `on` set.  Must be called by every lane of the
+// wave.  When all those lanes hold the same primitive the terms are summed across the wave first
+// (one atomic per field); otherwise each lane adds its own.
+template <int K>
+__device__ void accumulate(bool on, uint32_t j, const PairGrad& pg, float* __restrict__ g, int64_t n) {
+  const uint64_t m = __ballot(on);
+  if (!m) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  const uint32_t j0 = __shfl(j, leader, 64);
+  const bool uniform = __ballot(on && j != j0) == 0;
+  if (uniform) {
+#pragma unroll
+    for (int f = 0; f < 17; ++f) {
+      const float t = wave_sum(on ? pg.v[f] : 0.0f);
+      if (lane == leader && t != 0.0f) unsafeAtomicAdd(g + (size_t)f * n + j0, t);
+    }
+    const int k0 = __shfl(pg.k, leader, 64);
+    if (__ballot(on && pg.k != k0) == 0) {
+      const int kn0 = (k0 + 1 == K) ? 0 : k0 + 1;
+      const float a = wave_sum(on ? pg.s_k : 0.0f), b = wave_sum(on ? pg.s_n : 0.0f);
+      const float c = wave_sum(on ? pg.th_k : 0.0f), d = wave_sum(on ? pg.th_n : 0.0f);
+      if (lane == leader) {
+        if (a != 0.0f) unsafeAtomicAdd(g + (size_t)(G_SEC + k0) * n + j0, a);
+        if (b != 0.0f) unsafeAtomicAdd(g + (size_t)(G_SEC + kn0) * n + j0, b);
+        if (c != 0.0f) unsafeAtomicAdd(g + (size_t)(G_SEC + K + k0) * n + j0, c);
+        if (d != 0.0f) unsafeAtomicAdd(g + (size_t)(G_SEC + K + kn0) * n + j0, d);
+      }
+      return;
+    }
+  } else if (on) {
+#pragma unroll
+    for (int f = 0; f < 17; ++f)
+      if (pg.v[f] != 0.0f) unsafeAtomicAdd(g + (size_t)f * n + j, pg.v[f]);
+  }
+  if (on) {
+    if (pg.s_k != 0.0f) unsafeAtomicAdd(g + (size_t)(G_SEC + pg.k) * n + j, pg.s_k);
+    if (pg.s_n != 0.0f) unsafeAtomicAdd(g + (size_t)(G_SEC + pg.kn) * n + j, pg.s_n);
+    if (pg.th_k != 0.0f) unsafeAtomicAdd(g + (size_t)(G_SEC + K + pg.k) * n + j, pg.th_k);
+    if (pg.th_n != 0.0f) unsafeAtomicAdd(g + (size_t)(G_SEC + K + pg.kn) * n + j, pg.th_n);
+  }
 }
 
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_render_bwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
-                                                       const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp, OptsDev opt,
-                                                       const float* __restrict__ rgb, const float* __restrict__ dL,
-                                                       float* __restrict__ grad, int64_t n) {
+                                                       const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp,
+                                                       OptsDev opt, const float* __restrict__ rgb,
+                                                       const float* __restrict__ dL, float* __restrict__ grad,
+                                                       int64_t n) {
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
   __shared__ float4 lds[kBatch * RF4];
@@ -138,6 +196,9 @@ __global__ void __launch_bounds__(kBlock) k_render_bwd(const float* __restrict__
   const bool inside = x < cam.W && y < cam.H;
   const RasterParams rp = make_params(opt);
   const Pix pix = make_pix(cam, x, y);
+  // pixel-centre rectangle of this wave (16 x 4 pixels)
+  const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + (float)(kTile - 1);
+  const float wy0 = (float)(ty * kTile + (tid >> 6) * 4) + 0.5f, wy1 = wy0 + 3.0f;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
   const size_t plane = (size_t)cam.W * cam.H;
   const size_t pidx = inside ? (size_t)y * cam.W + x : 0;
@@ -151,21 +212,30 @@ __global__ void __launch_bounds__(kBlock) k_render_bwd(const float* __restrict__
   Cache<2> cache;
   cache.init(rp.cache_len);
 
-  // composites the popped entry (alpha a, primitive j); returns false when the pixel stops
-  auto emit = [&](float a, uint32_t j) -> bool {
-    const float test = T * (1.0f - a);
-    if (test < rp.T_min) return false;
-    const float* rg = records + (size_t)j * RF;
-    const float c0 = rg[R_RGB + 0], c1 = rg[R_RGB + 1], c2 = rg[R_RGB + 2];
-    const float w = a * T;
-    A0 = fmaf(w, c0, A0);
-    A1 = fmaf(w, c1, A1);
-    A2 = fmaf(w, c2, A2);
-    const float rest = (Cf0 - A0) * G0 + (Cf1 - A1) * G1 + (Cf2 - A2) * G2;
-    const float gA = T * (c0 * G0 + c1 * G1 + c2 * G2) - rest / (1.0f - a);
-    backprop_pair<K>(rg, pix, rp, gA, w, G0, G1, G2, grad, n, j);
-    T = test;
-    return true;
+  // Composites the popped entries (alpha a, primitive j) of the lanes with `have` set, exactly as the
+  // forward pass does, and accumulates their gradients.  Called by every lane of the wave.
+  auto emit = [&](bool have, float a, uint32_t j) {
+    PairGrad pg;
+    bool on = false;
+    if (have) {
+      const float test = T * (1.0f - a);
+      if (test < rp.T_min) {
+        done = true;
+      } else {
+        const float* rg = records + (size_t)j * RF;
+        const float c0 = rg[R_RGB + 0], c1 = rg[R_RGB + 1], c2 = rg[R_RGB + 2];
+        const float w = a * T;
+        A0 = fmaf(w, c0, A0);
+        A1 = fmaf(w, c1, A1);
+        A2 = fmaf(w, c2, A2);
+        const float rest = (Cf0 - A0) * G0 + (Cf1 - A1) * G1 + (Cf2 - A2) * G2;
+        const float gA = T * (c0 * G0 + c1 * G1 + c2 * G2) - rest / (1.0f - a);
+        pair_grad<K>(rg, pix, rp, gA, w, G0, G1, G2, pg);
+        T = test;
+        on = true;
+      }
+    }
+    accumulate<K>(on, j, pg, grad, n);
   };
 
   for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
@@ -178,29 +248,34 @@ __global__ void __launch_bounds__(kBlock) k_render_bwd(const float* __restrict__
     }
     if (tid < nb) lidx[tid] = prims[b0 + tid];
     __syncthreads();
-    if (!done) {
-      for (int i = 0; i < nb; ++i) {
-        const float* r = reinterpret_cast<const float*>(lds + i * RF4);
+    for (int i = 0; i < nb; ++i) {
+      if (__ballot(!done) == 0) break;
+      const float* r = reinterpret_cast<const float*>(lds + i * RF4);
+      if (box_misses(r, wx0, wx1, wy0, wy1)) continue;
+      bool have = false;
+      float ea = 0.0f;
+      uint32_t ej = 0;
+      if (!done) {
         float at, Z;
         if (drk_eval<K>(r, pix, rp, at, Z) && at >= rp.alpha_min) {
           const float x2[2] = {at, __uint_as_float(lidx[i])};
           float hk, hp[2];
           cache.push(Z, x2, hk, hp);
-          if (hp[0] > 0.0f && !emit(hp[0], __float_as_uint(hp[1]))) {
-            done = true;
-            break;
+          if (hp[0] > 0.0f) {
+            have = true;
+            ea = hp[0];
+            ej = __float_as_uint(hp[1]);
           }
         }
       }
+      if (__ballot(have)) emit(have, ea, ej);
     }
     __syncthreads();
   }
-  if (!done) {
 #pragma unroll
-    for (int s = 0; s < kMaxCache; ++s) {
-      const float a = cache.pay[0][s];
-      if (!done && a > 0.0f && !emit(a, __float_as_uint(cache.pay[1][s]))) done = true;
-    }
+  for (int s = 0; s < kMaxCache; ++s) {
+    const bool have = !done && cache.pay[0][s] > 0.0f;
+    if (__ballot(have)) emit(have, cache.pay[0][s], __float_as_uint(cache.pay[1][s]));
   }
 }
 

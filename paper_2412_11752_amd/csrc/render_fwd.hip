@@ -16,7 +16,8 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
                                                        float* __restrict__ rgb, float* __restrict__ T_out,
                                                        int32_t* __restrict__ n_emit_out,
                                                        int32_t* __restrict__ consumed_out,
-                                                       int32_t* __restrict__ contrib_out) {
+                                                       int32_t* __restrict__ contrib_out,
+                                                       int32_t* __restrict__ work_out) {
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
   __shared__ float4 lds[kBatch * RF4];
@@ -29,10 +30,13 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   const bool inside = x < cam.W && y < cam.H;
   const RasterParams rp = make_params(opt);
   const Pix pix = make_pix(cam, x, y);
+  // pixel-centre rectangle of this wave (16 x 4 pixels)
+  const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + (float)(kTile - 1);
+  const float wy0 = (float)(ty * kTile + (tid >> 6) * 4) + 0.5f, wy1 = wy0 + 3.0f;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
 
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  int n_emit = 0, n_contrib = 0;
+  int n_emit = 0, n_contrib = 0, n_hit = 0, n_full = 0;
   int consumed = (int)(end - start);
   bool done = !inside;
   Cache<4> cache;
@@ -50,8 +54,12 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
     if (!done) {
       for (int i = 0; i < nb; ++i) {
         const float* r = reinterpret_cast<const float*>(lds + i * RF4);
+        if (box_misses(r, wx0, wx1, wy0, wy1)) continue;
+        ++n_hit;
         float at, Z;
-        if (drk_eval<K>(r, pix, rp, at, Z) && at >= rp.alpha_min) {
+        if (!drk_eval<K>(r, pix, rp, at, Z)) continue;
+        ++n_full;
+        if (at >= rp.alpha_min) {
           ++n_contrib;
           const float x4[4] = {at, r[R_RGB + 0], r[R_RGB + 1], r[R_RGB + 2]};
           float hk, hp[4];
@@ -105,24 +113,26 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
     n_emit_out[pidx] = n_emit;
     consumed_out[pidx] = consumed;
     contrib_out[pidx] = n_contrib;
+    work_out[pidx] = n_hit;                 // entries whose hit was evaluated (wave box passed)
+    work_out[plane + pidx] = n_full;        // entries that went through the full kernel
   }
 }
 
 template <int K>
 static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, const uint32_t* prims, const CamDev* cam,
                                int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
-                               hipStream_t s) {
+                               int32_t* wk, hipStream_t s) {
   hipLaunchKernelGGL(k_render_fwd<K>, dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt, rgb, T, ne,
-                     cons, nc);
+                     cons, nc, wk);
   return hipGetLastError();
 }
 
 hipError_t launch_render_fwd(int K, const float* records, const uint32_t* ranges, const uint32_t* prims,
                              const CamDev* cam, int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
-                             int32_t* nc, hipStream_t s) {
+                             int32_t* nc, int32_t* wk, hipStream_t s) {
   switch (K) {
 #define DRK_CASE(k) \
-  case k: return launch_fwd_k<k>(records, ranges, prims, cam, ntiles, opt, rgb, T, ne, cons, nc, s);
+  case k: return launch_fwd_k<k>(records, ranges, prims, cam, ntiles, opt, rgb, T, ne, cons, nc, wk, s);
     DRK_CASE(3) DRK_CASE(4) DRK_CASE(5) DRK_CASE(6) DRK_CASE(7) DRK_CASE(8) DRK_CASE(9) DRK_CASE(10)
     DRK_CASE(11) DRK_CASE(12) DRK_CASE(13) DRK_CASE(14) DRK_CASE(15) DRK_CASE(16)
 #undef DRK_CASE

@@ -15,8 +15,7 @@ from . import _lib
 from ._lib import DRK_OK, DRK_EOVERFLOW, check, lib
 
 EXPORT = {"depth_keys": 0, "tile_counts": 1, "pair_tiles": 2, "pair_prims": 3, "ranges": 4, "emitted": 5,
-          "consumed": 6, "contributors": 7}
-_INT_EXPORTS = {"emitted", "consumed", "contributors"}
+          "consumed": 6, "contributors": 7, "hits": 8, "kernels": 9}
 
 
 def _stream_handle(device=None) -> int:
