@@ -28,14 +28,17 @@ METRIC = "Mpix/s fwd and fwd+bwd it/s at 1M DRKs 1080p; served p50/p99 latency v
 
 # Algorithmic work per unit (see the design notes): FP32 operations with an FMA counted as 2 and an
 # elementary function (reciprocal, exp, atan2, cospi) counted as 1.
-OPS_HIT = 30                   # ray-plane hit through the homography, depth/grazing tests, radius cut
 
 
-def ops_kernel(K: int) -> int:
-    return 46 + 2 * K          # sector search (2K), kernel, sharpening, low-pass, cutoffs
+def ops_hit(K: int) -> int:
+    # every (pixel, primitive) evaluation behind the wave's box test: homography hit, depth and
+    # grazing tests, low-pass reach, radius cut, pseudo-angle, sector search (2K), cross/dot
+    # products, L1 radius and the energy lower bound with its cut
+    return 62 + 2 * K
 
 
-OPS_CACHE_PER_SLOT = 6         # per contributor: one compare + key/alpha/rgb move per cache slot
+OPS_KERNEL = 22                # past both cuts: atan2, cos(pi t), L2 weight, energy, exp, Psi, low-pass, clamp
+OPS_CACHE = 49                 # per contributor: 7 key compares + 2 selects per slot for key, alpha, index
 OPS_COMPOSITE = 10             # per emitted contribution: transmittance test and colour update
 VALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12   # 78.6: non-packed FP32 FMA issue rate
 HBM_PEAK_GBS = 8000.0
@@ -161,7 +164,7 @@ def main():
         contribs += int(ras.export("contributors").sum().item())
         emits += int(ras.export("emitted").sum().item())
     pairs_last = int(ras.export("pair_tiles").numel())
-    flops = hits * OPS_HIT + kernels * ops_kernel(K) + contribs * 8 * OPS_CACHE_PER_SLOT + emits * OPS_COMPOSITE
+    flops = hits * ops_hit(K) + kernels * OPS_KERNEL + contribs * OPS_CACHE + emits * OPS_COMPOSITE
     fwd = result.get("fwd")
     roofline = None
     if fwd is not None:

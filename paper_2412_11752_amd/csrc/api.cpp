@@ -32,7 +32,7 @@ hipError_t launch_preprocess(const SceneDev&, const Views*, int, const OptsDev&,
                              hipStream_t);
 hipError_t launch_duplicate(const SceneDev&, const Views*, const OptsDev&, int, const uint32_t*, const uint32_t*,
                             const uint32_t*, const uint2*, const uint32_t*, uint32_t*, uint32_t*, const uint64_t*,
-                            int64_t, const uint64_t*, hipStream_t);
+                            int64_t, const uint64_t*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t radix_sort(int, const uint64_t*, uint32_t* const*, uint32_t* const*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t scan_counts(const uint32_t*, const uint32_t*, const uint64_t*, int64_t, uint32_t*, uint64_t*, uint64_t*,
                        uint64_t*, int64_t, uint32_t*, hipStream_t);
@@ -84,6 +84,8 @@ struct drk_ws {
   uint32_t* span_rows = nullptr;  // per view: tile columns i0 | i1 << 16 of each spanned row
   int64_t row_cap = 0;
   float* out_rgb = nullptr;       // internal output image [3][max_h][max_w] (graph-captured renders)
+  uint32_t* dup_big = nullptr;    // sorted slots of the primitives duplicated a workgroup at a time
+  uint32_t* dup_count = nullptr;  // their count
 
   SceneDev scene{};
   Views views{};
@@ -152,6 +154,8 @@ size_t layout(drk_ws* ws, bool assign, char* base) {
   SLOT(span_meta, uint2, V * N)
   SLOT(span_rows, uint32_t, V * (size_t)ws->row_cap)
   SLOT(out_rgb, float, 3 * px)
+  SLOT(dup_big, uint32_t, N)
+  SLOT(dup_count, uint32_t, 4)
 #undef SLOT
   return p.off;
 }
@@ -403,7 +407,7 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
     if ((st = check_hip(launch_duplicate(ws->scene, ws->views_dev, ws->opts, v, sorted, ws->offsets, counts,
                                          ws->span_meta + (size_t)v * ws->max_n,
                                          ws->span_rows + (size_t)v * ws->row_cap, ws->pk_tmp, ws->pv_tmp,
-                                         ws->totals + v, ws->cap, ws->n_prims, s),
+                                         ws->totals + v, ws->cap, ws->n_prims, ws->dup_big, ws->dup_count, s),
                         "duplicate")))
       return st;
     // 4. stable sort of the pairs by tile id -> (tile, depth, index) order

@@ -13,7 +13,6 @@ constexpr int kMaxK = 16;            // radial bases per primitive
 constexpr int kMaxViews = 8;         // views per launch
 constexpr int kMaxTileRows = 136;    // tile rows per view (image height <= 2176)
 constexpr int kMaxCache = 8;         // cache slots (Sec. 4.4 Cache Sorting uses 8)
-constexpr int kSubArcs = 2;          // sub-arcs per sector in the support polygon
 constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
 constexpr double kGrazing = 1e-6;    // |r_d . n| below this is a grazing ray (no hit)
 
@@ -40,7 +39,8 @@ enum RecField : int {
   R_R2CUT = 26,               // u^2 + v^2 beyond which alpha < alpha_min (bound E >= r2 / max_k s_k^2)
   R_LPCUT = 27,               // d^2 |r_d|^2 / W^2 beyond which the low-pass term < alpha_min
   R_BOX = 28,                 // 4 entries: pixel-space box (x0, x1, y0, y1) of the support polygon
-  R_SEC = 32,                 // per-sector arrays follow, each K long
+  R_ETHR = 32,                // energy beyond which alpha < alpha_min, with margin (c^2 (1 + 1e-3) + 1e-2)
+  R_SEC = 36,                 // per-sector arrays follow, each K long (33..35 unused, 16-byte alignment)
 };
 // Per-sector arrays (offset R_SEC + field * K + k):
 enum SecField : int {

@@ -15,6 +15,7 @@ namespace drk {
 constexpr double kPi = 3.141592653589793;
 constexpr double kTwoPi = 2.0 * kPi;
 constexpr uint32_t kNoSpans = 0xFFFFFFFFu;
+constexpr uint32_t kDupSmall = 32;      // primitives with more tiles are duplicated by a whole workgroup
 
 // ---------------------------------------------------------------------------------------------
 // Rotation of a quaternion (w, x, y, z): columns are the tangent axes t_u, t_v and the normal.
@@ -441,6 +442,10 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
                                                  log(ratio > 1.0 ? ratio : 1.0)
                                            : 0.0;
   rec[R_LPCUT] = opt.lowpass_sl > 0.0f ? (float)(1.001 * lpc + 1e-6) : -1.0f;
+  // alpha = o Psi(exp(-E/2)) is decreasing in E and equals alpha_min at E = c^2; the margin keeps
+  // the raster's float32 test conservative against the rounding of exp and Psi
+  rec[R_ETHR] = (float)(g.c * g.c * 1.001 + 1e-2);
+  rec[R_ETHR + 1] = rec[R_ETHR + 2] = rec[R_ETHR + 3] = 0.0f;
   rec[R_BOX + 0] = (float)(box[0] - 0.01);
   rec[R_BOX + 1] = (float)(box[1] + 0.01);
   rec[R_BOX + 2] = (float)(box[2] - 0.01);
@@ -589,7 +594,8 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
                                                    const uint32_t* __restrict__ span_rows,
                                                    uint32_t* __restrict__ pair_tiles, uint32_t* __restrict__ pair_prims,
                                                    const uint64_t* __restrict__ total_ptr, int64_t capacity,
-                                                   const uint64_t* __restrict__ n_sorted) {
+                                                   const uint64_t* __restrict__ n_sorted,
+                                                   uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)*n_sorted) return;
   const uint32_t j = sorted_prims[i];
@@ -598,11 +604,15 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
   if ((int64_t)*total_ptr > capacity) return;   // overflow: the status word already says so
   const uint32_t off = offsets[i];
   const CamDev& cam = views->cam[v];
+  const uint2 meta = opt.cull_mode == 2 ? make_uint2(0u, 0u) : span_meta[j];
+  if (cnt > kDupSmall && (opt.cull_mode == 2 || meta.x != kNoSpans)) {
+    big_list[atomicAdd(big_count, 1u)] = (uint32_t)i;   // written by k_duplicate_big
+    return;
+  }
   if (opt.cull_mode == 2) {
     for (uint32_t t = 0; t < cnt; ++t) { pair_tiles[off + t] = t; pair_prims[off + t] = j; }
     return;
   }
-  const uint2 meta = span_meta[j];
   uint32_t w = 0;
   if (meta.x != kNoSpans) {
     const int r0 = (int)(meta.y & 0xFFFFu), nr = (int)(meta.y >> 16);
@@ -634,6 +644,49 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
   }
 }
 
+// Duplication of the primitives with more than kDupSmall tiles: one workgroup per primitive walks
+// its stored rows; the lanes write the tiles of a row side by side (coalesced).
+__global__ void __launch_bounds__(256) k_duplicate_big(const Views* __restrict__ views, OptsDev opt, int v,
+                                                       const uint32_t* __restrict__ sorted_prims,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ tile_counts,
+                                                       const uint2* __restrict__ span_meta,
+                                                       const uint32_t* __restrict__ span_rows,
+                                                       uint32_t* __restrict__ pair_tiles, uint32_t* __restrict__ pair_prims,
+                                                       const uint64_t* __restrict__ total_ptr, int64_t capacity,
+                                                       const uint32_t* __restrict__ big_list,
+                                                       const uint32_t* __restrict__ big_count) {
+  if ((int64_t)*total_ptr > capacity) return;
+  const uint32_t nbig = *big_count;
+  const CamDev& cam = views->cam[v];
+  for (uint32_t item = blockIdx.x; item < nbig; item += gridDim.x) {
+    const uint32_t i = big_list[item];
+    const uint32_t j = sorted_prims[i];
+    const uint32_t cnt = tile_counts[j];
+    const uint32_t off = offsets[i];
+    if (opt.cull_mode == 2) {
+      for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) { pair_tiles[off + t] = t; pair_prims[off + t] = j; }
+      continue;
+    }
+    const uint2 meta = span_meta[j];
+    const int r0 = (int)(meta.y & 0xFFFFu), nr = (int)(meta.y >> 16);
+    const uint32_t* rows = span_rows + meta.x;
+    uint32_t w = 0;
+    for (int r = 0; r < nr && w < cnt; ++r) {
+      const uint32_t e = rows[r];
+      if (e == 0xFFFFFFFFu) continue;
+      const uint32_t i0 = e & 0xFFFFu, i1 = e >> 16;
+      const uint32_t n_row = min(i1 - i0 + 1u, cnt - w);
+      const uint32_t base = (uint32_t)((r0 + r) * cam.tiles_x) + i0;
+      for (uint32_t t = threadIdx.x; t < n_row; t += blockDim.x) {
+        pair_tiles[off + w + t] = base + t;
+        pair_prims[off + w + t] = j;
+      }
+      w += n_row;
+    }
+  }
+}
+
 }  // namespace drk
 
 // Host launchers ------------------------------------------------------------------------------
@@ -659,15 +712,21 @@ hipError_t launch_preprocess(const SceneDev& sc, const Views* views, int nv, con
   return hipGetLastError();
 }
 
+hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+
 hipError_t launch_duplicate(const SceneDev& sc, const Views* views, const OptsDev& opt, int v,
                             const uint32_t* sorted_prims, const uint32_t* offsets, const uint32_t* tile_counts,
                             const uint2* span_meta, const uint32_t* span_rows, uint32_t* pair_tiles,
                             uint32_t* pair_prims, const uint64_t* total_ptr, int64_t capacity, const uint64_t* n_sorted,
-                            hipStream_t s) {
+                            uint32_t* big_list, uint32_t* big_count, hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
+  hipError_t e = fill_u32(big_count, 0u, 1, s);
+  if (e != hipSuccess) return e;
   dim3 grid((unsigned)((sc.n + 127) / 128));
   hipLaunchKernelGGL(k_duplicate, grid, dim3(128), 0, s, sc, views, opt, v, sorted_prims, offsets, tile_counts,
-                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, n_sorted);
+                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, n_sorted, big_list, big_count);
+  hipLaunchKernelGGL(k_duplicate_big, dim3(1024), dim3(256), 0, s, views, opt, v, sorted_prims, offsets, tile_counts,
+                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, big_list, big_count);
   return hipGetLastError();
 }
 

@@ -79,8 +79,14 @@ struct Eval {
 };
 
 // Evaluates the opacity (after low-pass and clamp) of record r at pixel p.  Returns false when the
-// ray misses (grazing, behind the near plane).  Sec. 3.3 (hit, via the homography), Sec. 4.1-4.3
-// (kernel), Sec. 4.4 (low-pass).
+// ray misses (grazing, behind the near plane) or when the pixel provably cannot contribute.  Sec. 3.3
+// (hit, via the homography), Sec. 4.1-4.3 (kernel), Sec. 4.4 (low-pass).
+//
+// The two early-outs are exact in float32: with w_lo = P - |Q| <= P + Q cos(pi t) (|cos| <= 1 for
+// cospi_fast), every rounding step is monotone, so E >= E_lo = eta r1^2 + (1 - eta) r2 w_lo, and
+// E > R_ETHR (c^2 with a margin) gives o Psi(exp(-E/2)) < alpha_min.  Likewise r2 > R_R2CUT bounds
+// E from below by r2 / max_k s_k^2.  Either test only rejects when the low-pass term is also below
+// alpha_min.
 template <int K>
 __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix& p, const RasterParams& rp, float& at,
                                          float& Z, Eval* ev = nullptr) {
@@ -96,12 +102,11 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
   if (!(Z > rp.near_plane)) return false;
   const float u = U * iW, v = V * iW;
   const float r2 = fmaf(u, u, v * v);
-  // exact early-out: beyond R2CUT the kernel term is below alpha_min, beyond LPCUT the low-pass term
-  if (r2 > r[R_R2CUT]) {
-    const float ex = dx - r[R_OX], ey = dy - r[R_OY];
-    const float d2 = fmaf(ex, ex, ey * ey);
-    if (!(d2 * p.rd2 <= r[R_LPCUT] * W2)) return false;
-  }
+  const float ex = dx - r[R_OX], ey = dy - r[R_OY];
+  const float d2 = fmaf(ex, ex, ey * ey);
+  // the low-pass term can reach alpha_min (R_LPCUT < 0 when the filter is off)
+  const bool lp_in = d2 * p.rd2 <= r[R_LPCUT] * W2;
+  if (r2 > r[R_R2CUT] && !lp_in) return false;
   float E = 0.0f;
   int k = 0;
   float A = 0.f, B = 0.f, D = 0.f, phi = 0.f, t = 0.f, cd = 1.f, ws = 0.f, r1 = 0.f;
@@ -119,13 +124,17 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
     A = fmaf(ck, v, -(sk * u));          // cross(d_k, p)       = r2 sin(phi)
     B = fmaf(u, sn, -(v * cn));          // cross(p, d_{k+1})   = r2 sin(delta - phi)
     D = fmaf(ck, u, sk * v);             // dot(d_k, p)         = r2 cos(phi)
+    r1 = fmaf(sec[S_A * K + k], fabsf(B), sec[S_B * K + k] * fabsf(A));
+    const float eta = r[R_ETA];
+    const float P = sec[S_P * K + k], Q = sec[S_Q * K + k];
+    const float r1sq = r1 * r1, oeta = 1.0f - eta;
+    const float E_lo = fmaf(eta, r1sq, oeta * (r2 * (P - fabsf(Q))));
+    if (E_lo > r[R_ETHR] && !lp_in) return false;
     phi = atan2_fast(A, D);
     t = phi * sec[S_ID * K + k];
     cd = cospi_fast(t);
-    ws = fmaf(sec[S_Q * K + k], cd, sec[S_P * K + k]);
-    r1 = fmaf(sec[S_A * K + k], fabsf(B), sec[S_B * K + k] * fabsf(A));
-    const float eta = r[R_ETA];
-    E = fmaf(eta, r1 * r1, (1.0f - eta) * (r2 * ws));
+    ws = fmaf(Q, cd, P);
+    E = fmaf(eta, r1sq, oeta * (r2 * ws));
   }
   const float g = exp_fast(-0.5f * E);
   float psi;
@@ -138,8 +147,6 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
   float f = 0.0f;
   bool lp = false;
   if (rp.lowpass) {
-    const float ex = dx - r[R_OX], ey = dy - r[R_OY];
-    const float d2 = fmaf(ex, ex, ey * ey);
     f = o * exp_fast(rp.lp_coef * ((d2 * p.rd2) * (iW * iW)));
     lp = f > alpha;
     alpha = lp ? f : alpha;
@@ -158,10 +165,21 @@ __device__ __forceinline__ bool box_misses(const float* __restrict__ r, float x0
   return x1 < r[R_BOX + 0] || x0 > r[R_BOX + 1] || y1 < r[R_BOX + 2] || y0 > r[R_BOX + 3];
 }
 
+// Bit i set when staged record i (i < nb) may touch the wave's pixel rectangle.  Lane i tests record
+// i; called by every lane of the wave.
+template <int RF4>
+__device__ __forceinline__ uint64_t batch_box_mask(const float4* lds, int nb, float x0, float x1, float y0, float y1) {
+  const int lane = threadIdx.x & 63;
+  bool hit = false;
+  if (lane < nb) hit = !box_misses(reinterpret_cast<const float*>(lds + lane * RF4), x0, x1, y0, y1);
+  return __ballot(hit);
+}
+
 // Always-full sorted cache of kMaxCache slots (Sec. 4.4 Cache Sorting, Algorithm 1).  Slots hold
 // (key, payload...).  Unused capacity holds -inf sentinels (popped first, emit nothing) and, for
 // cache_len < kMaxCache, +inf sentinels that never reach the head.  An arriving contributor pops
-// the head (emitted if real) and is inserted after all entries with key <= its key.
+// the head (the caller reads and emits it first) and is inserted after all entries with key <= its
+// key.
 template <int NP>
 struct Cache {
   float key[kMaxCache];
@@ -175,23 +193,24 @@ struct Cache {
       for (int q = 0; q < NP; ++q) pay[q][s] = 0.0f;
     }
   }
-  // Pops slot 0 into (hk, hp) and inserts (z, x).
-  __device__ __forceinline__ void push(float z, const float (&x)[NP], float& hk, float (&hp)[NP]) {
-    hk = key[0];
+  // Drops slot 0 and inserts (z, x).  With b_j = key[j+1] <= z (monotone in j), slot j takes
+  // key[j+1] while b_j holds, z at the first j where it fails, and keeps its entry after that.
+  __device__ __forceinline__ void pop_insert(float z, const float (&x)[NP]) {
+    bool b[kMaxCache - 1];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) hp[q] = pay[q][0];
-    int p = 0;
+    for (int j = 0; j < kMaxCache - 1; ++j) b[j] = key[j + 1] <= z;
+    key[0] = b[0] ? key[1] : z;
 #pragma unroll
-    for (int i = 1; i < kMaxCache; ++i) p += (key[i] <= z) ? 1 : 0;
+    for (int q = 0; q < NP; ++q) pay[q][0] = b[0] ? pay[q][1] : x[q];
 #pragma unroll
-    for (int j = 0; j < kMaxCache; ++j) {
-      const bool before = j < p;
-      const bool here = j == p;
-      const int jn = (j + 1 < kMaxCache) ? j + 1 : j;
-      key[j] = before ? key[jn] : (here ? z : key[j]);
+    for (int j = 1; j < kMaxCache - 1; ++j) {
+      key[j] = b[j] ? key[j + 1] : (b[j - 1] ? z : key[j]);
 #pragma unroll
-      for (int q = 0; q < NP; ++q) pay[q][j] = before ? pay[q][jn] : (here ? x[q] : pay[q][j]);
+      for (int q = 0; q < NP; ++q) pay[q][j] = b[j] ? pay[q][j + 1] : (b[j - 1] ? x[q] : pay[q][j]);
     }
+    key[kMaxCache - 1] = b[kMaxCache - 2] ? z : key[kMaxCache - 1];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) pay[q][kMaxCache - 1] = b[kMaxCache - 2] ? x[q] : pay[q][kMaxCache - 1];
   }
 };
 

@@ -42,7 +42,9 @@ __device__ void pair_grad(const float* __restrict__ r, const Pix& pix, const Ras
   out.v[G_RGB + 2] = T_w * G2;
   Eval ev;
   float at, Z;
-  drk_eval<K>(r, pix, rp, at, Z, &ev);
+  // an emitted pair re-evaluates exactly as when it entered the cache; a miss here would mean
+  // inconsistent inputs, and contributes nothing rather than reading undefined state
+  if (!drk_eval<K>(r, pix, rp, at, Z, &ev)) return;
   if (ev.alpha > rp.alpha_max || gA == 0.0f) return;   // clamped: constant opacity
   const float o = r[R_O];
   float gU = 0.f, gV = 0.f, gW = 0.f;
@@ -248,27 +250,21 @@ __global__ void __launch_bounds__(kBlock) k_render_bwd(const float* __restrict__
     }
     if (tid < nb) lidx[tid] = prims[b0 + tid];
     __syncthreads();
-    for (int i = 0; i < nb; ++i) {
+    const uint64_t mask = batch_box_mask<RF4>(lds, nb, wx0, wx1, wy0, wy1);
+    for (uint64_t m = mask; m; m &= m - 1) {
       if (__ballot(!done) == 0) break;
+      const int i = __builtin_ctzll(m);
       const float* r = reinterpret_cast<const float*>(lds + i * RF4);
-      if (box_misses(r, wx0, wx1, wy0, wy1)) continue;
-      bool have = false;
-      float ea = 0.0f;
-      uint32_t ej = 0;
-      if (!done) {
-        float at, Z;
-        if (drk_eval<K>(r, pix, rp, at, Z) && at >= rp.alpha_min) {
-          const float x2[2] = {at, __uint_as_float(lidx[i])};
-          float hk, hp[2];
-          cache.push(Z, x2, hk, hp);
-          if (hp[0] > 0.0f) {
-            have = true;
-            ea = hp[0];
-            ej = __float_as_uint(hp[1]);
-          }
-        }
+      bool contrib = false;
+      float at = 0.0f, Z = 0.0f;
+      if (!done) contrib = drk_eval<K>(r, pix, rp, at, Z) && at >= rp.alpha_min;
+      // a contributor pops the head (emitted when real), then is inserted
+      const bool have = contrib && cache.pay[0][0] > 0.0f;
+      if (__ballot(have)) emit(have, cache.pay[0][0], __float_as_uint(cache.pay[1][0]));
+      if (contrib) {
+        const float x2[2] = {at, __uint_as_float(lidx[i])};
+        cache.pop_insert(Z, x2);
       }
-      if (__ballot(have)) emit(have, ea, ej);
     }
     __syncthreads();
   }
@@ -347,7 +343,7 @@ __device__ inline void real_sh_grad(int deg, double x, double y, double z, doubl
   }
 }
 
-__global__ void __launch_bounds__(128) k_preprocess_bwd(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) k_preprocess_bwd(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
                                                         const uint32_t* __restrict__ tile_counts,
                                                         const float* __restrict__ grec, int64_t stride,
                                                         drk_scene_grad out) {

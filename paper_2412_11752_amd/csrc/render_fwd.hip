@@ -21,6 +21,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
   __shared__ float4 lds[kBatch * RF4];
+  __shared__ uint32_t lidx[kBatch];
   const CamDev& cam = *camp;
   const int tile = blockIdx.x;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -39,7 +40,8 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   int n_emit = 0, n_contrib = 0, n_hit = 0, n_full = 0;
   int consumed = (int)(end - start);
   bool done = !inside;
-  Cache<4> cache;
+  // cache payload: (alpha, primitive index); the colour is gathered from the record at emission
+  Cache<2> cache;
   cache.init(rp.cache_len);
 
   for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
@@ -50,21 +52,21 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
       const uint32_t j = prims[b0 + ri];
       lds[q] = reinterpret_cast<const float4*>(records + (size_t)j * RF)[c];
     }
+    if (tid < nb) lidx[tid] = prims[b0 + tid];
     __syncthreads();
+    const uint64_t mask = batch_box_mask<RF4>(lds, nb, wx0, wx1, wy0, wy1);
     if (!done) {
-      for (int i = 0; i < nb; ++i) {
+      for (uint64_t m = mask; m; m &= m - 1) {
+        const int i = __builtin_ctzll(m);
         const float* r = reinterpret_cast<const float*>(lds + i * RF4);
-        if (box_misses(r, wx0, wx1, wy0, wy1)) continue;
         ++n_hit;
         float at, Z;
         if (!drk_eval<K>(r, pix, rp, at, Z)) continue;
         ++n_full;
         if (at >= rp.alpha_min) {
           ++n_contrib;
-          const float x4[4] = {at, r[R_RGB + 0], r[R_RGB + 1], r[R_RGB + 2]};
-          float hk, hp[4];
-          cache.push(Z, x4, hk, hp);
-          const float a = hp[0];
+          // pop the head (emit it), then insert the newcomer
+          const float a = cache.pay[0][0];
           if (a > 0.0f) {
             const float test = T * (1.0f - a);
             if (test < rp.T_min) {
@@ -72,13 +74,16 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
               consumed = (int)(b0 - start) + i + 1;
               break;
             }
+            const float* c = records + (size_t)__float_as_uint(cache.pay[1][0]) * RF + R_RGB;
             const float w = a * T;
-            C0 = fmaf(w, hp[1], C0);
-            C1 = fmaf(w, hp[2], C1);
-            C2 = fmaf(w, hp[3], C2);
+            C0 = fmaf(w, c[0], C0);
+            C1 = fmaf(w, c[1], C1);
+            C2 = fmaf(w, c[2], C2);
             T = test;
             ++n_emit;
           }
+          const float x2[2] = {at, __uint_as_float(lidx[i])};
+          cache.pop_insert(Z, x2);
         }
       }
     }
@@ -93,10 +98,11 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
         if (test < rp.T_min) {
           done = true;
         } else {
+          const float* c = records + (size_t)__float_as_uint(cache.pay[1][s]) * RF + R_RGB;
           const float w = a * T;
-          C0 = fmaf(w, cache.pay[1][s], C0);
-          C1 = fmaf(w, cache.pay[2][s], C1);
-          C2 = fmaf(w, cache.pay[3][s], C2);
+          C0 = fmaf(w, c[0], C0);
+          C1 = fmaf(w, c[1], C1);
+          C2 = fmaf(w, c[2], C2);
           T = test;
           ++n_emit;
         }
