@@ -138,8 +138,12 @@ __device__ inline bool load_geo(const SceneDev& sc, int64_t j, const CamDev& cam
 // ---------------------------------------------------------------------------------------------
 // Tile-row spans of the projected support.  Edges of the near-clipped projected polygon are
 // streamed in order; each updates the x-extent of the tile rows whose pixel-centre slab it crosses.
+// lo/hi are indexed by the row relative to the primitive's centre row (wrapping), so that the
+// lanes of a wave, whose primitives mostly cover a row or two around their centres, touch the same
+// private-memory slots instead of slots spread over every tile row of the view.
 struct Spans {
   double lo[kMaxTileRows], hi[kMaxTileRows];
+  int base;                         // tile row stored in slot 0
   double bx0, bx1, by0, by1;        // box of every projected segment and the low-pass square
   int r0, r1;                       // initialised rows [r0, r1]
   int W, H, tx, ty;
@@ -158,10 +162,15 @@ __device__ inline void spans_init(Spans& sp, const CamDev& cam) {
   sp.have_prev = false; sp.have_first = false; sp.pending_exit = false; sp.have_first_entry = false;
 }
 
+__device__ inline int slot(const Spans& sp, int r) {
+  int x = r - sp.base;
+  return x < 0 ? x + kMaxTileRows : x;
+}
+
 __device__ inline void spans_touch(Spans& sp, int r) {
-  if (sp.r0 > sp.r1) { sp.r0 = sp.r1 = r; sp.lo[r] = INFINITY; sp.hi[r] = -INFINITY; return; }
-  while (r < sp.r0) { --sp.r0; sp.lo[sp.r0] = INFINITY; sp.hi[sp.r0] = -INFINITY; }
-  while (r > sp.r1) { ++sp.r1; sp.lo[sp.r1] = INFINITY; sp.hi[sp.r1] = -INFINITY; }
+  if (sp.r0 > sp.r1) { sp.r0 = sp.r1 = r; sp.lo[slot(sp, r)] = INFINITY; sp.hi[slot(sp, r)] = -INFINITY; return; }
+  while (r < sp.r0) { --sp.r0; sp.lo[slot(sp, sp.r0)] = INFINITY; sp.hi[slot(sp, sp.r0)] = -INFINITY; }
+  while (r > sp.r1) { ++sp.r1; sp.lo[slot(sp, sp.r1)] = INFINITY; sp.hi[slot(sp, sp.r1)] = -INFINITY; }
 }
 
 // Screen segment (x0,y0)-(x1,y1) against every tile row slab it may cross.
@@ -191,8 +200,9 @@ __device__ inline void spans_segment(Spans& sp, double x0, double y0, double x1,
       xb = x0 + thi * (x1 - x0);
     }
     spans_touch(sp, r);
-    sp.lo[r] = fmin(sp.lo[r], fmin(xa, xb));
-    sp.hi[r] = fmax(sp.hi[r], fmax(xa, xb));
+    const int q = slot(sp, r);
+    sp.lo[q] = fmin(sp.lo[q], fmin(xa, xb));
+    sp.hi[q] = fmax(sp.hi[q], fmax(xa, xb));
   }
 }
 
@@ -260,6 +270,10 @@ __device__ inline void lift(const Geo& g, const CamDev& cam, double x, double y,
 // 1: the paper's endpoint polygon; 2 handled by the caller).
 __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt, Spans& sp) {
   spans_init(sp, cam);
+  {
+    const double pyc = fmin(fmax((double)cam.fy * g.muc[1] / g.muc[2] + (double)cam.cy, -1e7), 1e7);
+    sp.base = min(max((int)floor(pyc / 16.0), 0), sp.ty - 1);
+  }
   const double nearp = (double)opt.near_plane;
   const int K = g.K;
   if (opt.cull_mode == 1) {
@@ -323,8 +337,9 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
       double yb = fmin(16.0 * row + 15.5, sp.H - 0.5);
       if (dcy + r >= ya && dcy - r <= yb) {
         spans_touch(sp, row);
-        sp.lo[row] = fmin(sp.lo[row], dcx - r);
-        sp.hi[row] = fmax(sp.hi[row], dcx + r);
+        const int q = slot(sp, row);
+        sp.lo[q] = fmin(sp.lo[q], dcx - r);
+        sp.hi[q] = fmax(sp.hi[q], dcx + r);
       }
     }
   }
@@ -332,8 +347,8 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
 
 // Tile columns [i0, i1] of row r (false when none).
 __device__ inline bool row_tiles(const Spans& sp, int r, int& i0, int& i1) {
-  double lo = fmax(sp.lo[r], 0.5);
-  double hi = fmin(sp.hi[r], sp.W - 0.5);
+  double lo = fmax(sp.lo[slot(sp, r)], 0.5);
+  double hi = fmin(sp.hi[slot(sp, r)], sp.W - 0.5);
   if (lo > hi) return false;
   double a = ceil((lo - 15.5) / 16.0);
   double b = floor((hi - 0.5) / 16.0);
