@@ -44,6 +44,26 @@ VALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12   # 78.6: non-packed FP32 FMA iss
 HBM_PEAK_GBS = 8000.0
 
 
+def raster_traffic():
+    """HBM bytes per raster launch measured with rocprofv3 counters (profiles/), or None when the
+    raster sources have changed since that measurement."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, "profiles", "render_fwd_c3_1080p_traffic.md")).read()
+    except OSError:
+        return None
+    m_t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    m_h = re.search(r"raster_sources_sha256: ([0-9a-f]+)", text)
+    h = hashlib.sha256()
+    for name in ("render_fwd.hip", "raster_common.hpp", "drk_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2412_11752_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if not (m_t and m_h) or m_h.group(1) != h.hexdigest():
+        return None
+    return int(m_t.group(1))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -171,7 +191,7 @@ def main():
         raster_s = fwd["ms"][:, 2].sum() / 1e3
         achieved = flops / raster_s / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
-                    "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": raster_traffic(),
                     "kernel": "k_render_fwd", "avg_launch_ms": round(float(fwd["ms"][:, 2].mean()), 4),
                     "listed_pairs_per_launch": listed // args.steps,
                     "hit_evaluations_per_launch": hits // args.steps,
