@@ -232,8 +232,14 @@ class Cam:
                    _f64(c.R).reshape(3, 3), _f64(c.t).reshape(3), _f64(c.bg).reshape(3))
 
     @property
+    def Rinv(self) -> torch.Tensor:
+        """Camera-to-world rotation: the exact inverse of the world-to-camera R (X_c = R X_w + t).
+        R is given in float32, so its transpose is only approximately its inverse."""
+        return torch.linalg.inv(self.R)
+
+    @property
     def position(self) -> torch.Tensor:
-        return -(self.R.T @ self.t)
+        return -(self.Rinv @ self.t)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -290,7 +296,7 @@ def pixel_rays(cam: Cam, px: torch.Tensor, py: torch.Tensor):
     """Unit world-space ray directions through pixel centres (px + 0.5, py + 0.5)."""
     dc = torch.stack([(px.to(F64) + 0.5 - cam.cx) / cam.fx, (py.to(F64) + 0.5 - cam.cy) / cam.fy,
                       torch.ones_like(px, dtype=F64)], -1)
-    rd = dc @ cam.R          # R^T dc for each row
+    rd = dc @ cam.Rinv.T     # R^-1 dc for each row
     return rd / torch.linalg.vector_norm(rd, dim=-1, keepdim=True)
 
 

@@ -182,10 +182,13 @@ def test_hit_against_linear_solve():
     py = torch.as_tensor(rng.integers(0, H, n))
     res = O.eval_pairs(P, cam, O.Opts(lowpass_sl=0.0), px, py, P.color)
     Rq = O.quat_to_rotmat(_t(q)).numpy()
-    ro = cam.position.numpy()
+    # camera model X_c = R X_w + t: the centre solves R r_o + t = 0 and a pixel's ray direction solves
+    # R r_d = K^-1 (px, py, 1) (R is float32, so R^T is not exactly its inverse)
+    Rc = cam.R.numpy()
+    ro = np.linalg.solve(Rc, -cam.t.numpy())
     for i in range(n):
         dcam = np.array([(px[i].item() + 0.5 - cam.cx) / cam.fx, (py[i].item() + 0.5 - cam.cy) / cam.fy, 1.0])
-        rd = cam.R.numpy().T @ dcam
+        rd = np.linalg.solve(Rc, dcam)
         rd /= np.linalg.norm(rd)
         A = np.stack([rd, -Rq[i][:, 0], -Rq[i][:, 1]], 1)
         tt, uu, vv = np.linalg.solve(A, mu[i].astype(np.float64) - ro)
