@@ -34,10 +34,10 @@ def ops_hit(K: int) -> int:
     # every (pixel, primitive) evaluation behind the wave's box test: homography hit, depth and
     # grazing tests, low-pass reach, radius cut, pseudo-angle, sector search (2K), cross/dot
     # products, L1 radius and the energy lower bound with its cut
-    return 62 + 2 * K
+    return 63 + 2 * K
 
 
-OPS_KERNEL = 22                # past both cuts: atan2, cos(pi t), L2 weight, energy, exp, Psi, low-pass, clamp
+OPS_KERNEL = 27                # past both cuts: atan2, sin/cos(pi t/2), L2 weight, energy, exp, Psi, low-pass, clamp
 OPS_CACHE = 49                 # per contributor: 7 key compares + 2 selects per slot for key, alpha, index
 OPS_COMPOSITE = 10             # per emitted contribution: transmittance test and colour update
 VALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12   # 78.6: non-packed FP32 FMA issue rate

@@ -208,10 +208,18 @@ drk_status ws_set_cameras(drk_ws* ws, const drk_camera* cams, int32_t n_views, h
     d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
     for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
     for (int i = 0; i < 3; ++i) { d.t[i] = c.t[i]; d.bg[i] = c.bg[i]; }
-    for (int i = 0; i < 3; ++i) {
-      double a = 0.0;
-      for (int k = 0; k < 3; ++k) a -= (double)c.R[3 * k + i] * (double)c.t[k];
-      d.campos[i] = (float)a;
+    // camera centre: the exact inverse of the float32 R (its transpose is only approximately it)
+    {
+      double m[9];
+      for (int i = 0; i < 9; ++i) m[i] = (double)c.R[i];
+      const double c0 = m[4] * m[8] - m[5] * m[7], c1 = m[5] * m[6] - m[3] * m[8], c2 = m[3] * m[7] - m[4] * m[6];
+      const double det = m[0] * c0 + m[1] * c1 + m[2] * c2;
+      if (!(fabs(det) > 1e-6)) { set_error("camera %d rotation is singular", v); return DRK_EINVAL; }
+      const double inv[9] = {c0 / det, (m[2] * m[7] - m[1] * m[8]) / det, (m[1] * m[5] - m[2] * m[4]) / det,
+                             c1 / det, (m[0] * m[8] - m[2] * m[6]) / det, (m[2] * m[3] - m[0] * m[5]) / det,
+                             c2 / det, (m[1] * m[6] - m[0] * m[7]) / det, (m[0] * m[4] - m[1] * m[3]) / det};
+      for (int i = 0; i < 3; ++i)
+        d.campos[i] = -(inv[3 * i] * (double)c.t[0] + inv[3 * i + 1] * (double)c.t[1] + inv[3 * i + 2] * (double)c.t[2]);
     }
   }
   drk_status st = check_hip(set_views(ws->views_dev, views, s), "set cameras");

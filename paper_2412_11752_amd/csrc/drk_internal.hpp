@@ -50,8 +50,8 @@ enum SecField : int {
   S_ID = 3,    // 1 / delta_k, delta_k = theta_{k+1} - theta_k (wrapping)
   S_A = 4,     // 1 / (s_k sin delta_k)
   S_B = 5,     // 1 / (s_{k+1} sin delta_k)
-  S_P = 6,     // (1/s_k^2 + 1/s_{k+1}^2) / 2
-  S_Q = 7,     // (1/s_k^2 - 1/s_{k+1}^2) / 2
+  S_IK2 = 6,   // 1 / s_k^2
+  S_IN2 = 7,   // 1 / s_{k+1}^2
   S_NFIELDS = 8
 };
 __host__ __device__ inline int rec_floats(int K) { return (R_SEC + S_NFIELDS * K + 3) & ~3; }
@@ -63,7 +63,7 @@ struct CamDev {
   float R[9];
   float t[3];
   float bg[3];
-  float campos[3];   // -R^T t, float64-exact rounding not needed (used for SH direction only in f64)
+  double campos[3];  // camera centre -R^-1 t (float64; the SH view direction)
 };
 
 struct Views {

@@ -470,8 +470,7 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
   } else {
     double cp[3];
     for (int i = 0; i < 3; ++i)
-      cp[i] = -(((double)cam.R[i] * (double)cam.t[0] + (double)cam.R[3 + i] * (double)cam.t[1]) +
-                (double)cam.R[6 + i] * (double)cam.t[2]);
+      cp[i] = cam.campos[i];
     double d[3] = {g.mu[0] - cp[0], g.mu[1] - cp[1], g.mu[2] - cp[2]};
     double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     double Y[16];
@@ -498,9 +497,8 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
     double sd = sin(dl);
     rec[R_SEC + S_A * K + k] = (float)(1.0 / (sk * sd));
     rec[R_SEC + S_B * K + k] = (float)(1.0 / (sn * sd));
-    double ik2 = 1.0 / (sk * sk), in2 = 1.0 / (sn * sn);
-    rec[R_SEC + S_P * K + k] = (float)(0.5 * (ik2 + in2));
-    rec[R_SEC + S_Q * K + k] = (float)(0.5 * (ik2 - in2));
+    rec[R_SEC + S_IK2 * K + k] = (float)(1.0 / (sk * sk));
+    rec[R_SEC + S_IN2 * K + k] = (float)(1.0 / (sn * sn));
   }
 }
 

@@ -52,20 +52,17 @@ __device__ __forceinline__ float atan2_fast(float y, float x) {
   return copysignf(r, y);
 }
 
-// cos(pi t) for t in about [-0.02, 1.02]: even polynomial on [0, 1/2] (least-squares fit, max abs
-// error 1.5e-7 in float32) and cos(pi t) = -cos(pi (1 - t)) above 1/2.
-__device__ __forceinline__ float cospi_fast(float t) {
-  t = fabsf(t);
-  const bool hi = t > 0.5f;
-  const float x = hi ? 1.0f - t : t;
+// sin(pi x / 2) for x in about [-0.02, 1.02]: odd polynomial (least squares weighted by the relative
+// error; max relative error 1.9e-7 in float32).  The L2 weight uses cos^2(pi t/2) = sinhalf(1-t)^2
+// and sin^2(pi t/2) = sinhalf(t)^2, both accurate relative to their size.
+__device__ __forceinline__ float sinhalf_fast(float x) {
   const float s = x * x;
-  float p = -0.024396864677873612f;
-  p = fmaf(p, s, 0.23493764446403828f);
-  p = fmaf(p, s, -1.3352120737951056f);
-  p = fmaf(p, s, 4.05870916572721f);
-  p = fmaf(p, s, -4.93480213726698f);
-  p = fmaf(p, s, 0.9999999997808213f);
-  return hi ? -p : p;
+  float p = 0.00015193128256064164f;
+  p = fmaf(p, s, -0.004674595124423347f);
+  p = fmaf(p, s, 0.07969015617822843f);
+  p = fmaf(p, s, -0.6459637978745842f);
+  p = fmaf(p, s, 1.570796320926877f);
+  return x * p;
 }
 
 __device__ __forceinline__ float exp_fast(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
@@ -73,7 +70,7 @@ __device__ __forceinline__ float exp_fast(float x) { return __builtin_amdgcn_exp
 // Intermediate values of one (pixel, primitive) evaluation.
 struct Eval {
   float dx, dy, U, V, W, iW, u, v;
-  float A, B, D, phi, t, cd, ws, r1, r2, E, g, psi, alpha, f;
+  float A, B, D, phi, t, ch, sh, ws, r1, r2, E, g, psi, alpha, f;
   int k, piece;
   bool lp_wins;
 };
@@ -82,11 +79,15 @@ struct Eval {
 // ray misses (grazing, behind the near plane) or when the pixel provably cannot contribute.  Sec. 3.3
 // (hit, via the homography), Sec. 4.1-4.3 (kernel), Sec. 4.4 (low-pass).
 //
-// The two early-outs are exact in float32: with w_lo = P - |Q| <= P + Q cos(pi t) (|cos| <= 1 for
-// cospi_fast), every rounding step is monotone, so E >= E_lo = eta r1^2 + (1 - eta) r2 w_lo, and
-// E > R_ETHR (c^2 with a margin) gives o Psi(exp(-E/2)) < alpha_min.  Likewise r2 > R_R2CUT bounds
-// E from below by r2 / max_k s_k^2.  Either test only rejects when the low-pass term is also below
-// alpha_min.
+// The L2 weight 1/sbar^2 = (1 + cos pi t)/(2 s_k^2) + (1 - cos pi t)/(2 s_{k+1}^2) (Sec. 4.1) is
+// evaluated as cos^2(pi t/2)/s_k^2 + sin^2(pi t/2)/s_{k+1}^2: two positive terms, so that very
+// different lengths in one sector do not cancel.
+//
+// The two early-outs are exact in float32.  cos^2 + sin^2 of the polynomial stays within 1.1e-6 of 1,
+// so w_lo = min(1/s_k^2, 1/s_{k+1}^2) * 0.99999 is below the weight after rounding; every other
+// rounding step is monotone, so E >= E_lo = eta r1^2 + (1 - eta) r2 w_lo, and E > R_ETHR (c^2 with a
+// margin) gives o Psi(exp(-E/2)) < alpha_min.  Likewise r2 > R_R2CUT bounds E from below by
+// r2 / max_k s_k^2.  Either test only rejects when the low-pass term is also below alpha_min.
 template <int K>
 __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix& p, const RasterParams& rp, float& at,
                                          float& Z, Eval* ev = nullptr) {
@@ -109,7 +110,7 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
   if (r2 > r[R_R2CUT] && !lp_in) return false;
   float E = 0.0f;
   int k = 0;
-  float A = 0.f, B = 0.f, D = 0.f, phi = 0.f, t = 0.f, cd = 1.f, ws = 0.f, r1 = 0.f;
+  float A = 0.f, B = 0.f, D = 0.f, phi = 0.f, t = 0.f, ch = 1.f, sh = 0.f, ws = 0.f, r1 = 0.f;
   if (r2 > 0.0f) {
     // sector: largest k with pa_k < pa (wrapping to K-1)
     const float pa = diamond_pa(u, v);
@@ -126,14 +127,15 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
     D = fmaf(ck, u, sk * v);             // dot(d_k, p)         = r2 cos(phi)
     r1 = fmaf(sec[S_A * K + k], fabsf(B), sec[S_B * K + k] * fabsf(A));
     const float eta = r[R_ETA];
-    const float P = sec[S_P * K + k], Q = sec[S_Q * K + k];
+    const float ik2 = sec[S_IK2 * K + k], in2 = sec[S_IN2 * K + k];
     const float r1sq = r1 * r1, oeta = 1.0f - eta;
-    const float E_lo = fmaf(eta, r1sq, oeta * (r2 * (P - fabsf(Q))));
+    const float E_lo = fmaf(eta, r1sq, oeta * (r2 * (fminf(ik2, in2) * 0.99999f)));
     if (E_lo > r[R_ETHR] && !lp_in) return false;
     phi = atan2_fast(A, D);
     t = phi * sec[S_ID * K + k];
-    cd = cospi_fast(t);
-    ws = fmaf(Q, cd, P);
+    sh = sinhalf_fast(t);
+    ch = sinhalf_fast(1.0f - t);
+    ws = fmaf(ch * ch, ik2, (sh * sh) * in2);
     E = fmaf(eta, r1sq, oeta * (r2 * ws));
   }
   const float g = exp_fast(-0.5f * E);
@@ -154,7 +156,8 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
   at = fminf(alpha, rp.alpha_max);
   if (ev) {
     ev->dx = dx; ev->dy = dy; ev->U = U; ev->V = V; ev->W = W; ev->iW = iW; ev->u = u; ev->v = v;
-    ev->A = A; ev->B = B; ev->D = D; ev->phi = phi; ev->t = t; ev->cd = cd; ev->ws = ws; ev->r1 = r1; ev->r2 = r2;
+    ev->A = A; ev->B = B; ev->D = D; ev->phi = phi; ev->t = t; ev->ch = ch; ev->sh = sh; ev->ws = ws; ev->r1 = r1;
+    ev->r2 = r2;
     ev->E = E; ev->g = g; ev->psi = psi; ev->alpha = alpha; ev->f = f; ev->k = k; ev->piece = piece; ev->lp_wins = lp;
   }
   return true;

@@ -84,17 +84,16 @@ __device__ void pair_grad(const float* __restrict__ r, const Pix& pix, const Ras
       const float ck = sec[S_C * K + k], sk = sec[S_S * K + k];
       const float cn = sec[S_C * K + kn], sn = sec[S_S * K + kn];
       const float id = sec[S_ID * K + k], ak = sec[S_A * K + k], bk = sec[S_B * K + k];
-      const float P = sec[S_P * K + k], Q = sec[S_Q * K + k];
-      const float isk2 = P + Q, isn2 = P - Q;
+      const float isk2 = sec[S_IK2 * K + k], isn2 = sec[S_IN2 * K + k];
       const float s_k = 1.0f / sqrtf(isk2), s_n = 1.0f / sqrtf(isn2);
       const float cot = (ck * cn + sk * sn) * (ak * s_k);       // cos(delta) / sin(delta)
       const float g_r1 = gE * 2.0f * eta * ev.r1;
       const float g_ws = gE * (1.0f - eta) * ev.r2;
       const float g_r2 = gE * (1.0f - eta) * ev.ws;
-      const float g_cd = g_ws * Q;
-      const float g_isk2 = g_ws * 0.5f * (1.0f + ev.cd);
-      const float g_isn2 = g_ws * 0.5f * (1.0f - ev.cd);
-      const float g_t = -3.14159265358979f * sinpif(ev.t) * g_cd;
+      // ws = ch^2 isk2 + sh^2 isn2 with ch = cos(pi t/2), sh = sin(pi t/2)
+      const float g_isk2 = g_ws * (ev.ch * ev.ch);
+      const float g_isn2 = g_ws * (ev.sh * ev.sh);
+      const float g_t = 3.14159265358979f * (ev.ch * ev.sh) * (isn2 - isk2) * g_ws;
       const float g_phi = g_t * id;
       float g_delta = -g_t * ev.phi * id * id;
       const float sB = ev.B > 0.f ? 1.f : (ev.B < 0.f ? -1.f : 0.f);
@@ -427,8 +426,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) k
     } else {
       double cp[3];
       for (int i = 0; i < 3; ++i)
-        cp[i] = -(((double)cam.R[i] * (double)cam.t[0] + (double)cam.R[3 + i] * (double)cam.t[1]) +
-                  (double)cam.R[6 + i] * (double)cam.t[2]);
+        cp[i] = cam.campos[i];
       double d[3] = {mu[0] - cp[0], mu[1] - cp[1], mu[2] - cp[2]};
       const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       const double dh[3] = {d[0] / dn, d[1] / dn, d[2] / dn};

@@ -1,0 +1,181 @@
+"""Forward parity beyond the 64x64 case: other K, several views in one call, primitives that cross
+the near plane, and the 1M-DRK 1080p and 3M-DRK eight-view workloads at full size (sampled pixels
+against the FP64 oracle, sampled primitives' tile sets and depth keys bit-exact)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from drk_synth import (Camera, Scene, camera_lookat, config_c3, config_c5, draw_angles, intrinsics_hfov,
+                       scene_uniform_box)
+from oracle import drk_oracle as O
+from tests._gpu_util import IMG_TOL, compare_image, gpu_opts, log, need_gpu, oracle_opts
+
+pytestmark = pytest.mark.gpu
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32).astype(np.int64)
+
+
+def _rasterizer(scene, cams, cap):
+    from paper_2412_11752_amd import Rasterizer
+    return Rasterizer(scene.n, scene.K, max(c.width for c in cams), max(c.height for c in cams),
+                      max_views=len(cams), pair_capacity=cap)
+
+
+def _views(rgb_flat, cams):
+    out, off = [], 0
+    g = rgb_flat.reshape(-1).cpu().numpy()
+    for c in cams:
+        n = c.width * c.height
+        out.append(g[3 * off:3 * (off + n)].reshape(3, c.height, c.width))
+        off += n
+    return out
+
+
+@pytest.mark.parametrize("K", [3, 5, 16])
+def test_other_basis_counts_match_oracle(K):
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene = scene_uniform_box(40 + K, 1500, K=K)
+    cam = camera_lookat((0.3, -0.2, -3.2), (0, 0, 0), (0, 1, 0), 96, 80, 60.0, bg=(0.1, 0.2, 0.3))
+    ras = _rasterizer(scene, [cam], 1 << 20)
+    rgb, _ = ras.forward(DRKScene.from_host(scene), [cam], gpu_opts())
+    orc = O.render_image(scene, cam, oracle_opts())
+    worst, nk, _, _ = compare_image(rgb[0].cpu().numpy(), orc, cam.height, cam.width)
+    log(f"K={K}: max err {worst:.2e}, knife {nk}")
+    assert worst <= IMG_TOL and nk <= 8
+
+
+def test_views_of_different_sizes_in_one_call():
+    """Three views of different sizes share one preprocess/bin/raster call; each matches the oracle
+    and the tile lists of each view are sorted by (tile, depth key, index)."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene = scene_uniform_box(9, 2500, K=8)
+    cams = [camera_lookat((0, 0, -3.0), (0, 0, 0), (0, 1, 0), 64, 48, 60.0),
+            camera_lookat((2.5, 0.5, -1.5), (0, 0, 0), (0, 1, 0), 50, 70, 70.0, bg=(0.2, 0.2, 0.2)),
+            camera_lookat((-1.0, 2.8, 0.5), (0, 0, 0), (0, 0, 1), 33, 17, 50.0)]
+    ras = _rasterizer(scene, cams, 1 << 20)
+    rgb, _ = ras.forward(DRKScene.from_host(scene), cams, gpu_opts())
+    for v, (g, cam) in enumerate(zip(_views(rgb, cams), cams)):
+        orc = O.render_image(scene, cam, oracle_opts())
+        worst, nk, _, _ = compare_image(g, orc, cam.height, cam.width)
+        log(f"view {v} {cam.width}x{cam.height}: max err {worst:.2e}, knife {nk}")
+        assert worst <= IMG_TOL and nk <= 4
+        gt, gp = _u32(ras.export("pair_tiles", v)), _u32(ras.export("pair_prims", v))
+        keys = _u32(ras.export("depth_keys", v))
+        assert np.array_equal(np.lexsort((gp, keys[gp], gt)), np.arange(gt.size))
+        tiles, _, _ = O.tile_lists(scene, cam, oracle_opts())
+        ot, op = [], []
+        for t in sorted(tiles):
+            for _, j in tiles[t]:
+                ot.append(t)
+                op.append(j)
+        assert np.array_equal(gt, np.array(ot)) and np.array_equal(gp, np.array(op))
+
+
+def _near_scene():
+    rng = np.random.default_rng(13)
+    n, K = 12, 8
+    mu = rng.uniform(-0.5, 0.5, (3, n)).astype(np.float32)
+    q = rng.normal(size=(4, n)).astype(np.float32)
+    th = draw_angles(rng, K, n)
+    s = np.exp(rng.uniform(math.log(0.15), math.log(0.6), (K, n))).astype(np.float32)
+    col = rng.normal(0, 0.1, (48, n)).astype(np.float32)
+    col[:3] = rng.uniform(0, 1, (3, n))
+    return Scene(mu, q, s, th, rng.uniform(0, 1, n).astype(np.float32), rng.uniform(0, 0.9, n).astype(np.float32),
+                 rng.uniform(0.3, 0.95, n).astype(np.float32), col, 3)
+
+
+@pytest.mark.parametrize("lowpass", [False, True])
+def test_primitives_crossing_the_near_plane(lowpass):
+    """Large DRKs whose support crosses z = near: the clipped polygon, the hits behind the camera and
+    the near cut must all agree with the oracle."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene = _near_scene()
+    cams = []
+    for z, W, H in ((2.5, 24, 24), (0.9, 80, 64), (0.45, 96, 96)):
+        fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+        cams.append(Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.array([0, 0, z], np.float32),
+                           np.array([0.2, 0.1, 0.0], np.float32)))
+    for cam in cams:
+        ras = _rasterizer(scene, [cam], 1 << 16)
+        rgb, _ = ras.forward(DRKScene.from_host(scene), [cam], gpu_opts(lowpass=lowpass))
+        orc = O.render_image(scene, cam, oracle_opts(lowpass=lowpass))
+        worst, nk, _, _ = compare_image(rgb[0].cpu().numpy(), orc, cam.height, cam.width)
+        log(f"near-plane scene, camera z={cam.t[2]:.2f} {cam.width}x{cam.height}: max err {worst:.2e}, knife {nk}")
+        assert worst <= IMG_TOL and nk <= 4
+        gc = _u32(ras.export("tile_counts"))
+        oc = np.array([len(O.primitive_tiles(scene, cam, oracle_opts(lowpass=lowpass), j)) for j in range(scene.n)])
+        assert np.array_equal(gc, oc)
+
+
+def _sampled_check(scene, cam, g, prims, n_px, seed, label):
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(cam.width * cam.height, n_px, replace=False)
+    # plus the ragged last tile row and column
+    idx = np.concatenate([idx, [cam.width * cam.height - 1, (cam.height - 1) * cam.width, cam.width - 1]])
+    px, py = idx % cam.width, idx // cam.width
+    orc = O.render_pixels(scene, cam, oracle_opts(), px, py, prims=prims)
+    err = np.abs(g[:, py, px].T.astype(np.float64) - orc.rgb).max(axis=1)
+    worst = float(err[~orc.knife].max())
+    log(f"{label}: {idx.size} px, max err {worst:.3e}, knife {int(orc.knife.sum())}, mean emitted {orc.n_emit.mean():.1f}")
+    assert worst <= IMG_TOL
+    assert orc.knife.sum() <= max(2, idx.size // 100)
+
+
+def _tile_sample(ras, scene, cam, view, n, seed):
+    gt, gp = _u32(ras.export("pair_tiles", view)), _u32(ras.export("pair_prims", view))
+    keys = _u32(ras.export("depth_keys", view))
+    assert np.array_equal(np.lexsort((gp, keys[gp], gt)), np.arange(gt.size))
+    okey = O.centre_depth_f32(scene.mu, cam).view(np.uint32)
+    listed = np.unique(gp)
+    rng = np.random.default_rng(seed)
+    for j in rng.choice(listed, min(n, listed.size), replace=False):
+        ot = O.primitive_tiles(scene, cam, oracle_opts(), int(j))
+        assert np.array_equal(np.sort(gt[gp == j]), np.array(ot, np.int64)), j
+        assert keys[j] == okey[j]
+
+
+@pytest.mark.timeout(300)
+def test_headline_1m_1080p_sampled():
+    """1M DRKs (K=8, SH3) at 1920x1080 from inside the cluster box, in the launch configuration the
+    benchmark times: 256 seeded pixels (and the image corners) against the oracle, 60 listed DRKs'
+    tile sets and keys bit-exact."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene, cams = config_c3()
+    cam = cams[3]
+    ras = _rasterizer(scene, [cam], 6_000_000)
+    rgb, _ = ras.forward(DRKScene.from_host(scene), [cam], gpu_opts())
+    g = rgb[0].cpu().numpy()
+    log("1M 1080p rendered")
+    prims = O.Prims.from_scene(scene)
+    _sampled_check(scene, cam, g, prims, 256, 31, "1M 1080p")
+    _tile_sample(ras, scene, cam, 0, 60, 32)
+
+
+@pytest.mark.timeout(400)
+def test_eight_views_3m_k16_sampled():
+    """3M DRKs (K=16, SH3) in a 40-unit box, eight 1920x1080 views rendered in one call with
+    per-view sort buffers: 24 seeded pixels in each of four views against the oracle, and 10 listed
+    DRKs' tile sets in two views."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene, cams = config_c5()
+    log("3M K=16 scene generated")
+    ras = _rasterizer(scene, cams, 12_000_000)
+    rgb, _ = ras.forward(DRKScene.from_host(scene), cams, gpu_opts())
+    views = _views(rgb, cams)
+    log(f"8 views rendered, pair capacity {ras.pair_capacity}")
+    prims = O.Prims.from_scene(scene)
+    for v in (0, 2, 5, 7):
+        _sampled_check(scene, cams[v], views[v], prims, 24, 50 + v, f"3M K=16 view {v}")
+    for v in (0, 5):
+        _tile_sample(ras, scene, cams[v], v, 10, 60 + v)
+    log(f"peak device memory {torch.cuda.max_memory_allocated() / 2**30:.2f} GiB (torch) + workspace "
+        f"{ras.size_query(scene.n, scene.K, 1920, 1080, 8, ras.pair_capacity) / 2**30:.2f} GiB")
