@@ -68,6 +68,110 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def sized_rasterizer(ds, frames, W, H, opts):
+    """A rasterizer whose pair buffer fits every frame of the list (sized in an untimed pass)."""
+    from paper_2412_11752_amd import Rasterizer
+    ras = Rasterizer(ds.n, ds.K, W, H, pair_capacity=1 << 26)
+    need = 0
+    for cam in frames:
+        ras.preprocess(ds, [cam], opts)
+        ras.bin_sort()
+        _, nd = ras.status()
+        need = max(need, nd)
+    cap = int(need * 1.05) + 4096
+    ras.close()
+    return Rasterizer(ds.n, ds.K, W, H, pair_capacity=cap), cap, need
+
+
+def timed(ras, ds, frames, opts, args, rgb, T, bwd=False):
+    """Times args.steps frames (after args.warmup untimed ones); per-stage HIP events on the stream
+    the library runs on.  Returns (wall seconds, [steps][4] ms: preprocess, bin/sort, fwd, bwd)."""
+    import torch
+    from paper_2412_11752_amd._lib import DRK_OK, DrkError
+    stream = torch.cuda.current_stream()
+    g_up = torch.full_like(rgb, 0.01) if bwd else None
+    for i in range(args.warmup):
+        ras.preprocess(ds, [frames[i]], opts)
+        ras.bin_sort()
+        ras.render_fwd(rgb, T)
+        if bwd:
+            ras.render_bwd(rgb, g_up)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        cam = frames[args.warmup + s]
+        e = ev[s]
+        e[0].record(stream)
+        ras.preprocess(ds, [cam], opts)
+        e[1].record(stream)
+        ras.bin_sort()
+        e[2].record(stream)
+        ras.render_fwd(rgb, T)
+        e[3].record(stream)
+        if bwd:
+            ras.render_bwd(rgb, g_up)
+        e[4].record(stream)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
+                    e[3].elapsed_time(e[4])] for e in ev])
+    code, _ = ras.status()
+    if code != DRK_OK:
+        raise DrkError(code, "timed loop")
+    return t_total, ms
+
+
+def raster_work(ras, ds, frames, opts, args, rgb, T):
+    """Work units of the forward raster per launch, averaged over the timed frames (re-rendered:
+    the pipeline is deterministic), counted by the kernel itself."""
+    tot = dict(listed=0, hits=0, kernels=0, contributors=0, emitted=0)
+    names = dict(listed="consumed", hits="hits", kernels="kernels", contributors="contributors", emitted="emitted")
+    for s in range(args.steps):
+        ras.preprocess(ds, [frames[args.warmup + s]], opts)
+        ras.bin_sort()
+        ras.render_fwd(rgb, T)
+        for k, e in names.items():
+            tot[k] += int(ras.export(e).sum().item())
+    out = {k: v // args.steps for k, v in tot.items()}
+    out["flops"] = (tot["hits"] * ops_hit(ds.K) + tot["kernels"] * OPS_KERNEL + tot["contributors"] * OPS_CACHE
+                    + tot["emitted"] * OPS_COMPOSITE) / args.steps
+    return out
+
+
+def ksweep_phase(args, opts, W, H):
+    """Rendering cost against the number of radial bases K (the cost side of the K ablation): the
+    same cluster centres and orientations, scales and angles drawn for each K, same camera path."""
+    import torch
+    from drk_synth import c3_camera_path, scene_clusters
+    from paper_2412_11752_amd import DRKScene
+    out = {}
+    cams = c3_camera_path(202, 100, W, H, half=10.0)
+    frames = [cams[i % len(cams)] for i in range(args.warmup + args.steps)]
+    for K in [int(k) for k in args.ksweep.split(",")]:
+        t0 = time.time()
+        host = scene_clusters(2, args.n, K=K, half=10.0)
+        ds = DRKScene.from_host(host, device="cuda")
+        ras, cap, need = sized_rasterizer(ds, frames, W, H, opts)
+        rgb = torch.empty(3 * W * H, device="cuda")
+        T = torch.empty(W * H, device="cuda")
+        t_total, ms = timed(ras, ds, frames, opts, args, rgb, T)
+        work = raster_work(ras, ds, frames, opts, args, rgb, T)
+        raster_ms = float(ms[:, 2].mean())
+        row = {"mpix_s": round(args.steps * W * H / t_total / 1e6, 2),
+               "ms_preprocess": round(float(ms[:, 0].mean()), 4), "ms_bin_sort": round(float(ms[:, 1].mean()), 4),
+               "ms_raster": round(raster_ms, 4), "pairs_max": need,
+               "hits": work["hits"], "kernels": work["kernels"], "contributors": work["contributors"],
+               "emitted": work["emitted"], "raster_tflops": round(work["flops"] / raster_ms / 1e9, 3),
+               "ns_per_hit": round(raster_ms * 1e6 / max(work["hits"], 1), 4)}
+        log(f"ksweep K={K}: {row} (scene gen + sizing {time.time() - t0:.1f}s)")
+        out[str(K)] = row
+        ras.close()
+        del ds
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,7 +180,8 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
-    ap.add_argument("--phases", default="fwd,serve", help="fwd, fwdbwd (backward switched off), serve")
+    ap.add_argument("--phases", default="fwd,serve", help="fwd, fwdbwd (backward switched off), serve, ksweep")
+    ap.add_argument("--ksweep", default="3,5,8,16", help="radial basis counts of the ksweep phase")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the Poisson arrival trace")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget (0 = skip)")
@@ -89,8 +194,8 @@ def main():
 
     import torch
     from drk_synth import config_c3
-    from paper_2412_11752_amd import DRKScene, Rasterizer, make_opts
-    from paper_2412_11752_amd._lib import DRK_OK, DrkError
+    from paper_2412_11752_amd import DRKScene, make_opts
+    from paper_2412_11752_amd._lib import DrkError
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -104,103 +209,45 @@ def main():
     n_frames = args.warmup + args.steps
     frames = [cams[i % len(cams)] for i in range(n_frames)]
 
-    # size the pair buffer for every frame used (untimed)
-    ras = Rasterizer(scene.n, K, W, H, pair_capacity=1 << 26)
-    need = 0
-    for cam in frames:
-        ras.preprocess(ds, [cam], opts)
-        ras.bin_sort()
-        code, nd = ras.status()
-        need = max(need, nd)
-    cap = int(need * 1.05) + 4096
-    ras.close()
-    ras = Rasterizer(scene.n, K, W, H, pair_capacity=cap)
+    ras, cap, need = sized_rasterizer(ds, frames, W, H, opts)
     log(f"pairs per view (max over frames): {need}  capacity {cap}")
-
     rgb = torch.empty(3 * W * H, device=dev)
     T = torch.empty(W * H, device=dev)
-    stream = torch.cuda.current_stream()
     result = {}
-
-    def timed(phase):
-        bwd = phase == "fwdbwd"
-        g_up = torch.ones(3 * W * H, device=dev) * 0.01 if bwd else None
-        for i in range(args.warmup):
-            ras.preprocess(ds, [frames[i]], opts)
-            ras.bin_sort()
-            ras.render_fwd(rgb, T)
-            if bwd:
-                ras.render_bwd(rgb, g_up)
-        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for s in range(args.steps):
-            cam = frames[args.warmup + s]
-            e = ev[s]
-            e[0].record(stream)
-            ras.preprocess(ds, [cam], opts)
-            e[1].record(stream)
-            ras.bin_sort()
-            e[2].record(stream)
-            ras.render_fwd(rgb, T)
-            e[3].record(stream)
-            if bwd:
-                ras.render_bwd(rgb, g_up)
-            e[4].record(stream)
-        torch.cuda.synchronize()
-        t_total = time.perf_counter() - t_start
-        ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
-                        e[3].elapsed_time(e[4])] for e in ev])
-        code, _ = ras.status()
-        if code != DRK_OK:
-            raise DrkError(code, "timed loop")
-        return t_total, ms
 
     phases = [p for p in args.phases.split(",") if p]
     if "fwd" in phases:
-        t_total, ms = timed("fwd")
+        t_total, ms = timed(ras, ds, frames, opts, args, rgb, T, bwd=False)
         mpix = args.steps * W * H / t_total / 1e6
         log(f"fwd: {t_total * 1e3 / args.steps:.3f} ms/step, {mpix:.1f} Mpix/s; "
             f"preprocess {ms[:, 0].mean():.3f} ms, bin/sort {ms[:, 1].mean():.3f} ms, raster {ms[:, 2].mean():.3f} ms")
         result["fwd"] = dict(t_total=t_total, ms=ms, mpix=mpix)
     if "fwdbwd" in phases:
         try:
-            t_total, ms = timed("fwdbwd")
+            t_total, ms = timed(ras, ds, frames, opts, args, rgb, T, bwd=True)
             its = args.steps / t_total
             log(f"fwd+bwd: {t_total * 1e3 / args.steps:.3f} ms/step, {its:.2f} it/s; bwd {ms[:, 3].mean():.3f} ms")
             result["fwdbwd"] = dict(t_total=t_total, ms=ms, its=its)
         except DrkError as e:
             log(f"fwd+bwd unavailable: {e}")
 
-    # algorithmic work of the forward raster over the timed frames (same frames, deterministic)
-    listed = hits = kernels = contribs = emits = 0
-    for s in range(args.steps):
-        ras.preprocess(ds, [frames[args.warmup + s]], opts)
-        ras.bin_sort()
-        ras.render_fwd(rgb, T)
-        listed += int(ras.export("consumed").sum().item())
-        hits += int(ras.export("hits").sum().item())
-        kernels += int(ras.export("kernels").sum().item())
-        contribs += int(ras.export("contributors").sum().item())
-        emits += int(ras.export("emitted").sum().item())
+    work = raster_work(ras, ds, frames, opts, args, rgb, T)
     pairs_last = int(ras.export("pair_tiles").numel())
-    flops = hits * ops_hit(K) + kernels * OPS_KERNEL + contribs * OPS_CACHE + emits * OPS_COMPOSITE
     fwd = result.get("fwd")
     roofline = None
     if fwd is not None:
-        raster_s = fwd["ms"][:, 2].sum() / 1e3
-        achieved = flops / raster_s / 1e12
+        achieved = work["flops"] / (fwd["ms"][:, 2].sum() / 1e3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
                     "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": raster_traffic(),
                     "kernel": "k_render_fwd", "avg_launch_ms": round(float(fwd["ms"][:, 2].mean()), 4),
-                    "listed_pairs_per_launch": listed // args.steps,
-                    "hit_evaluations_per_launch": hits // args.steps,
-                    "kernel_evaluations_per_launch": kernels // args.steps,
-                    "contributors_per_launch": contribs // args.steps,
-                    "emitted_per_launch": emits // args.steps}
-        log(f"raster work: {listed / args.steps / 1e6:.1f}M listed, {hits / args.steps / 1e6:.1f}M hits, "
-            f"{kernels / args.steps / 1e6:.1f}M kernel evaluations, {contribs / args.steps / 1e6:.1f}M "
-            f"contributors, {emits / args.steps / 1e6:.1f}M emitted per view -> {achieved:.2f} TFLOP/s")
+                    "listed_pairs_per_launch": work["listed"],
+                    "hit_evaluations_per_launch": work["hits"],
+                    "kernel_evaluations_per_launch": work["kernels"],
+                    "contributors_per_launch": work["contributors"],
+                    "emitted_per_launch": work["emitted"]}
+        log(f"raster work: {work['listed'] / 1e6:.1f}M listed, {work['hits'] / 1e6:.1f}M hits, "
+            f"{work['kernels'] / 1e6:.1f}M kernel evaluations, {work['contributors'] / 1e6:.1f}M "
+            f"contributors, {work['emitted'] / 1e6:.1f}M emitted per view -> {achieved:.2f} TFLOP/s")
 
     # CPU oracle on a bounded sample of the same workload (first timed frame)
     cpu = None
@@ -234,10 +281,13 @@ def main():
                "parity_max_err": float(max(errs)) if errs else None}
         log(f"cpu oracle: {done} px in {el:.1f}s -> {cpu['value']:.2e} Mpix/s; max |gpu-oracle| {cpu['parity_max_err']}")
 
+    ras.close()
+    torch.cuda.empty_cache()
+    ksweep = None
+    if "ksweep" in phases:
+        ksweep = ksweep_phase(args, opts, W, H)
     serve = None
     if "serve" in phases and not args.profile:
-        ras.close()
-        torch.cuda.empty_cache()
         serve = serve_phase(args, opts)
 
     ms_step = fwd["t_total"] * 1e3 / args.steps if fwd else None
@@ -259,6 +309,8 @@ def main():
         "cpu_baseline": cpu,
         "serve": serve,
     }
+    if ksweep is not None:
+        line["ksweep"] = ksweep
     if "fwdbwd" in result:
         line["ms_breakdown"]["render_bwd"] = round(float(result["fwdbwd"]["ms"][:, 3].mean()), 4)
     print(json.dumps(line), flush=True)
