@@ -24,8 +24,9 @@ listed below (and in the design notes):
     contributors enter a cache of L slots kept sorted by r_t (a newcomer goes
     after equal keys); when the cache is full its head is emitted BEFORE the
     newcomer is inserted; at the end of the list the cache drains from the
-    head.  The arrival order is the global pre-sort by (float32 view-space
-    depth of the centre, primitive index);
+    head.  The arrival order is the pre-sort by (float32 key, primitive
+    index), the key being the view-space depth of the centre, or one of the
+    per-tile keys of ``tile_key`` (supplement, cache-sorting evaluation);
   * colour: real spherical harmonics of degree <= 3 at the direction from the
     camera to the centre, plus 0.5, clamped at 0 (3D-GS convention); a plain
     RGB colour is used as is;
@@ -57,12 +58,13 @@ class Opts:
     lowpass_sl: float = math.sqrt(0.5)   # 0 disables the low-pass filter
     cache_len: int = 8                   # >= 1<<30 means exact per-pixel sort
     cull_mode: int = 0                   # 0 conservative polygon, 1 paper polygon, 2 all tiles
+    key_mode: int = 0                    # pre-sort key: 0 centre depth, 1 most centric, 2 nearest (per tile)
 
     def f32(self) -> "Opts":
         """The same options rounded to float32, as the C ABI carries them."""
         r = lambda x: float(np.float32(x))
         return Opts(r(self.alpha_min), r(self.alpha_max), r(self.T_min), r(self.near), r(self.lowpass_sl),
-                    self.cache_len, self.cull_mode)
+                    self.cache_len, self.cull_mode, self.key_mode)
 
 
 EXACT = 1 << 30
@@ -432,6 +434,7 @@ class PixelResult:
     knife: np.ndarray        # (P,) bool: some decision within 1e-6 (relative) of its threshold
     emitted: List[List[int]]  # per pixel, primitive indices actually composited, in order
     weights: List[List[float]]
+    emitted_z: List[List[float]]  # per pixel, view depth of the hit of each composited contribution
 
 
 def render_pixels(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, chunk: int = 64,
@@ -442,7 +445,7 @@ def render_pixels(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, chu
     primitives binned to the pixel's tile are considered, to show that binning changes nothing."""
     P = prims if prims is not None else Prims.from_scene(scene)
     cam = Cam.from_camera(camera)
-    key = centre_depth_f32(scene.mu, camera).view(np.uint32)
+    akey = arrival_keys(scene, camera, opts, np.asarray(px), np.asarray(py))
     with torch.no_grad():
         box, cull = screen_bounds(P, cam, opts)
         colors = prim_colors(P, cam)
@@ -458,6 +461,7 @@ def render_pixels(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, chu
         knife = np.zeros(npix, bool)
         emitted: List[List[int]] = [[] for _ in range(npix)]
         weights: List[List[float]] = [[] for _ in range(npix)]
+        emitted_z: List[List[float]] = [[] for _ in range(npix)]
         bg = cam.bg.numpy()
         for c0 in range(0, npix, chunk):
             cx_ = px_t[c0:c0 + chunk].to(F64)[:, None] + 0.5
@@ -480,17 +484,17 @@ def render_pixels(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, chu
             pj = alive[ml]
             pidx = pl + c0
             res = eval_pairs(P.index(pj), cam, opts, px_t[pidx], py_t[pidx], colors[pj])
-            _finish_pixels(res, pidx, pj, key, opts, bg, out_rgb, out_T, out_n, out_nc, knife, emitted, weights,
-                           c0, min(chunk, npix - c0))
-    return PixelResult(out_rgb, out_T, out_n, out_nc, knife, emitted, weights)
+            _finish_pixels(res, pidx, pj, akey, opts, bg, out_rgb, out_T, out_n, out_nc, knife, emitted, weights,
+                           emitted_z, c0, min(chunk, npix - c0))
+    return PixelResult(out_rgb, out_T, out_n, out_nc, knife, emitted, weights, emitted_z)
 
 
 def _near(x, thr, rel=1e-6):
     return np.abs(x - thr) <= rel * abs(thr)
 
 
-def _finish_pixels(res, pidx, pj, key, opts, bg, out_rgb, out_T, out_n, out_nc, knife, emitted, weights,
-                   c0, cnt):
+def _finish_pixels(res, pidx, pj, akey, opts, bg, out_rgb, out_T, out_n, out_nc, knife, emitted, weights,
+                   emitted_z, c0, cnt):
     contrib = res["contrib"].numpy()
     ok = res["ok"].numpy()
     at = res["alpha"].numpy()
@@ -520,7 +524,7 @@ def _finish_pixels(res, pidx, pj, key, opts, bg, out_rgb, out_T, out_n, out_nc, 
             emit_at = list(range(1, len(em) + 1))
             gaps = [math.inf] + [abs(em[i][0] - em[i - 1][0]) / abs(em[i][0]) for i in range(1, len(em))]
         else:
-            arrival = sorted(sel, key=lambda s: (int(key[pj[s]]), int(pj[s])))
+            arrival = sorted(sel, key=lambda s: (akey(p, int(pj[s])), int(pj[s])))
             em, emit_at, gaps = cache_trace([(float(rt[s]), int(pj[s])) for s in arrival], opts.cache_len)
         lut = {int(pj[s]): s for s in sel}
         em_s = [lut[j] for _, j in em]
@@ -540,6 +544,7 @@ def _finish_pixels(res, pidx, pj, key, opts, bg, out_rgb, out_T, out_n, out_nc, 
         out_T[p] = T
         out_n[p] = n
         emitted[p] = [int(pj[s]) for s in em_s[:n]]
+        emitted_z[p] = [float(zc[s]) for s in em_s[:n]]
         weights[p] = w
 
 
@@ -776,10 +781,28 @@ def primitive_tiles(scene, camera, opts: Opts, j: int) -> List[int]:
     with the conservative polygon of ``support_polygon``).  float64, operations in written order."""
     W, H = camera.width, camera.height
     tx = (W + TILE - 1) // TILE
-    ty = (H + TILE - 1) // TILE
-    f = lambda a: float(np.float32(a))
     if not primitive_valid(scene, j):
         return []
+    sup = support_screen(scene, camera, opts, j)
+    if sup is None:
+        return []
+    if opts.cull_mode == 2:
+        return list(range(tx * ((H + TILE - 1) // TILE)))
+    scr, disk = sup
+    spans = row_spans(scr, disk, W, H)
+    out = []
+    for row in sorted(spans):
+        i0, i1 = spans[row]
+        out.extend(row * tx + i for i in range(i0, i1 + 1))
+    return out
+
+
+def support_screen(scene, camera, opts: Opts, j: int):
+    """Projected support of primitive j: the near-clipped support polygon in pixel coordinates (P, 2)
+    and, with the low-pass filter, the square (centre x, centre y, half-width) of the low-pass term.
+    None when the centre is at or behind the near plane or the opacity is below alpha_min; with
+    cull_mode 2, (None, None).  float64, operations in written order."""
+    f = lambda a: float(np.float32(a))
     Rc = [[f(camera.R[i][k]) for k in range(3)] for i in range(3)]
     tc = [f(camera.t[i]) for i in range(3)]
     fx, fy, cx, cy = f(camera.fx), f(camera.fy), f(camera.cx), f(camera.cy)
@@ -787,9 +810,9 @@ def primitive_tiles(scene, camera, opts: Opts, j: int) -> List[int]:
     mc = _to_cam(Rc, tc, mu)
     o, tau = f(scene.opacity[j]), f(scene.tau[j])
     if not mc[2] > opts.near or o < opts.alpha_min:
-        return []
+        return None
     if opts.cull_mode == 2:
-        return list(range(tx * ty))
+        return None, None
     R = _rot_cols([scene.q[i, j] for i in range(4)])
     tu = [R[0][0], R[1][0], R[2][0]]
     tv = [R[0][1], R[1][1], R[2][1]]
@@ -811,17 +834,13 @@ def primitive_tiles(scene, camera, opts: Opts, j: int) -> List[int]:
     if opts.lowpass_sl > 0:
         r = opts.lowpass_sl * math.sqrt(2.0 * math.log(max(o / opts.alpha_min, 1.0)))
         disk = ((fx * mc[0]) / mc[2] + cx, (fy * mc[1]) / mc[2] + cy, r)
-    spans = row_spans(scr, disk, W, H)
-    out = []
-    for row in sorted(spans):
-        i0, i1 = spans[row]
-        out.extend(row * tx + i for i in range(i0, i1 + 1))
-    return out
+    return scr, disk
 
 
 def tile_lists(scene, camera, opts: Opts, prim_ids: Optional[Sequence[int]] = None):
-    """Reference binning: for every tile, the primitives binned to it ordered by (depth key, index).
-    Returns (tiles dict -> list of (key, j)), per-primitive tile lists, and the depth keys (uint32)."""
+    """Reference binning: for every tile, the primitives binned to it ordered by (pre-sort key, index),
+    the key being the centre depth or, with ``opts.key_mode``, the per-tile key.  Returns (tiles dict
+    -> list of (key, j)), per-primitive tile lists, and the centre-depth keys (uint32)."""
     ids = range(scene.n) if prim_ids is None else prim_ids
     key = centre_depth_f32(scene.mu, camera).view(np.uint32)
     per_prim = {}
@@ -829,8 +848,166 @@ def tile_lists(scene, camera, opts: Opts, prim_ids: Optional[Sequence[int]] = No
     for j in ids:
         tl = primitive_tiles(scene, camera, opts, int(j))
         per_prim[int(j)] = tl
+        kp = key_plane(scene, camera, opts, int(j)) if (opts.key_mode != 0 and tl) else None
         for t in tl:
-            tiles.setdefault(t, []).append((int(key[j]), int(j)))
+            k = int(key[j]) if kp is None else tile_key(kp, camera, opts, t)
+            tiles.setdefault(t, []).append((k, int(j)))
     for t in tiles:
         tiles[t].sort()
     return tiles, per_prim, key
+
+
+# ---------------------------------------------------------------------------------------------
+# Pre-sort key variants and the sorting-accuracy measures (supplement, cache-sorting evaluation:
+# tile-kernel pairs pre-sorted by the nearest distance between kernel and tile, or by the most
+# centric point, before the per-pixel cache; accuracy, Kendall's tau and MAE of the depths composited
+# front to back).  Readings: the distance is the view depth; "most centric" is the depth where the
+# ray through the centre of the rectangle below meets the kernel's plane; "nearest" is
+# the smallest such depth over the rectangle's four corner rays, which bounds the plane's depth over
+# the whole rectangle from below because 1/depth is affine in the pixel coordinates.  Both are held
+# to the depth range of the kernel's support disc (radius sqrt(2) c max_k s_k, which contains the
+# support polygon).  Every value is float64 in the order written and rounded to float32 once, so the
+# keys are reproducible bit for bit.  The rectangle is the tile's pixel-centre rectangle cut to the
+# pixel box of the kernel's projected support (conservative polygon and low-pass square), so that
+# both keys look at the part of the tile the kernel can cover.
+
+KEY_CENTRE, KEY_CENTRIC, KEY_NEAREST = 0, 1, 2
+
+
+@dataclasses.dataclass
+class KeyPlane:
+    a: Tuple[float, float, float]   # camera-frame plane normal t_u^c x t_v^c (not normalised)
+    dN: float                       # a . mu_c
+    zc: float                       # view depth of the centre
+    zlo: float                      # depth range of the support disc, zlo >= near
+    zhi: float
+    box: Optional[Tuple[float, float, float, float]]   # pixel box (x0, x1, y0, y1) of the projected support
+
+
+def key_plane(scene, camera, opts: Opts, j: int) -> KeyPlane:
+    """Camera-frame plane and support depth range of DRK j for the per-tile keys."""
+    f = lambda a: float(np.float32(a))
+    Rc = [[f(camera.R[i][k]) for k in range(3)] for i in range(3)]
+    tc = [f(camera.t[i]) for i in range(3)]
+    mu = [f(scene.mu[i, j]) for i in range(3)]
+    mc = _to_cam(Rc, tc, mu)
+    R = _rot_cols([scene.q[i, j] for i in range(4)])
+    tu = [R[0][0], R[1][0], R[2][0]]
+    tv = [R[0][1], R[1][1], R[2][1]]
+    tuc = [(Rc[i][0] * tu[0] + Rc[i][1] * tu[1]) + Rc[i][2] * tu[2] for i in range(3)]
+    tvc = [(Rc[i][0] * tv[0] + Rc[i][1] * tv[1]) + Rc[i][2] * tv[2] for i in range(3)]
+    a = (tuc[1] * tvc[2] - tuc[2] * tvc[1], tuc[2] * tvc[0] - tuc[0] * tvc[2], tuc[0] * tvc[1] - tuc[1] * tvc[0])
+    dN = (a[0] * mc[0] + a[1] * mc[1]) + a[2] * mc[2]
+    o, tau = f(scene.opacity[j]), f(scene.tau[j])
+    c = math.sqrt(-2.0 * math.log(_psi_inv_scalar(opts.alpha_min / o, tau)))
+    smax = max(f(scene.scale[k, j]) for k in range(scene.K))
+    zr = (math.sqrt(2.0) * (c * smax)) * math.sqrt(tuc[2] * tuc[2] + tvc[2] * tvc[2])
+    box = None
+    if opts.cull_mode == 0:
+        scr, disk = support_screen(scene, camera, opts, j)
+        xs, ys = list(scr[:, 0]), list(scr[:, 1])
+        if disk is not None:
+            xs += [disk[0] - disk[2], disk[0] + disk[2]]
+            ys += [disk[1] - disk[2], disk[1] + disk[2]]
+        box = (min(xs), max(xs), min(ys), max(ys))
+    return KeyPlane(a, dN, mc[2], max(mc[2] - zr, opts.near), mc[2] + zr, box)
+
+
+def plane_depth(kp: KeyPlane, camera, opts: Opts, x: float, y: float) -> Optional[float]:
+    """View depth where the ray through pixel point (x, y) meets the plane, or None when it meets it
+    at or behind the near plane (or not at all)."""
+    f = lambda a: float(np.float32(a))
+    fx, fy, cx, cy = f(camera.fx), f(camera.fy), f(camera.cx), f(camera.cy)
+    wd = (kp.a[0] * ((x - cx) / fx) + kp.a[1] * ((y - cy) / fy)) + kp.a[2]
+    if wd == 0.0:
+        return None
+    z = kp.dN / wd
+    return z if (z > opts.near and z < math.inf) else None
+
+
+def tile_rect(camera, tile: int) -> Tuple[float, float, float, float]:
+    """Pixel-centre rectangle (xa, xb, ya, yb) of a tile, cut at the image border."""
+    tx = (camera.width + TILE - 1) // TILE
+    x0, y0 = TILE * (tile % tx), TILE * (tile // tx)
+    return (x0 + 0.5, min(x0 + TILE - 0.5, camera.width - 0.5), y0 + 0.5, min(y0 + TILE - 0.5, camera.height - 0.5))
+
+
+def key_rect(kp: KeyPlane, camera, tile: int) -> Tuple[float, float, float, float]:
+    """The part of a tile's pixel-centre rectangle that the kernel's projected support box covers
+    (the whole rectangle when they do not overlap or no box is known)."""
+    xa, xb, ya, yb = tile_rect(camera, tile)
+    if kp.box is None:
+        return xa, xb, ya, yb
+    x0, x1, y0, y1 = max(xa, kp.box[0]), min(xb, kp.box[1]), max(ya, kp.box[2]), min(yb, kp.box[3])
+    if x0 > x1 or y0 > y1:
+        return xa, xb, ya, yb
+    return x0, x1, y0, y1
+
+
+def tile_key_value(kp: KeyPlane, camera, opts: Opts, tile: int, mode: int) -> float:
+    """Per-tile pre-sort key (float64, before rounding) of the kernel with plane ``kp``."""
+    xa, xb, ya, yb = key_rect(kp, camera, tile)
+    if mode == KEY_CENTRIC:
+        z = plane_depth(kp, camera, opts, 0.5 * (xa + xb), 0.5 * (ya + yb))
+        z = kp.zc if z is None else z
+    elif mode == KEY_NEAREST:
+        zs = [d for d in (plane_depth(kp, camera, opts, x, y) for x, y in ((xa, ya), (xb, ya), (xa, yb), (xb, yb)))
+              if d is not None]
+        z = min(zs) if zs else kp.zlo
+    else:
+        raise ValueError(mode)
+    return min(max(z, kp.zlo), kp.zhi)
+
+
+def tile_key(kp: KeyPlane, camera, opts: Opts, tile: int) -> int:
+    """uint32 bits of the float32 per-tile key (opts.key_mode 1 or 2); positive, so the bits sort
+    like the values."""
+    return int(np.float32(tile_key_value(kp, camera, opts, tile, opts.key_mode)).view(np.uint32))
+
+
+def arrival_keys(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray):
+    """Callable (pixel slot p, primitive j) -> uint32 pre-sort key that orders pixel p's arrivals."""
+    if opts.key_mode == KEY_CENTRE:
+        key = centre_depth_f32(scene.mu, camera).view(np.uint32)
+        return lambda p, j: int(key[j])
+    tx = (camera.width + TILE - 1) // TILE
+    planes: Dict[int, KeyPlane] = {}
+    memo: Dict[Tuple[int, int], int] = {}
+
+    def akey(p, j):
+        t = (int(py[p]) // TILE) * tx + int(px[p]) // TILE
+        k = memo.get((t, j))
+        if k is None:
+            if j not in planes:
+                planes[j] = key_plane(scene, camera, opts, j)
+            k = memo[(t, j)] = tile_key(planes[j], camera, opts, t)
+        return k
+    return akey
+
+
+def sort_metrics(seqs: Sequence[Sequence[float]], cap: Optional[int] = None) -> Dict[str, float]:
+    """Disorder of front-to-back composited depth sequences (one per pixel, first ``cap`` entries):
+    accuracy = share of positions holding the depth that the sorted sequence holds there;
+    Kendall's tau = per-pixel (concordant - discordant) / (m (m - 1) / 2) between composite order and
+    depth (ties count as neither), averaged over pixels with m >= 2;
+    MAE = mean |depth at a position - sorted depth at that position|."""
+    n_el = n_ok = 0
+    err = 0.0
+    taus = []
+    for seq in seqs:
+        z = np.asarray(list(seq)[:cap] if cap else list(seq), dtype=np.float64)
+        m = z.size
+        if m == 0:
+            continue
+        zs = np.sort(z, kind="stable")
+        n_el += m
+        n_ok += int((z == zs).sum())
+        err += float(np.abs(z - zs).sum())
+        if m >= 2:
+            later = np.triu(np.ones((m, m), bool), 1)
+            d = z[None, :] - z[:, None]          # d[i, k] = z_k - z_i
+            cd = int((d[later] > 0).sum()) - int((d[later] < 0).sum())
+            taus.append(cd / (m * (m - 1) / 2))
+    return dict(accuracy=n_ok / n_el if n_el else float("nan"),
+                kendall_tau=float(np.mean(taus)) if taus else float("nan"),
+                mae=err / n_el if n_el else float("nan"), n=n_el, pixels=len(taus))

@@ -478,3 +478,163 @@ def test_p9_support_polygon_adversarial():
         pts = np.stack([rad * np.cos(ang), rad * np.sin(ang)], -1)
         supp = _alpha(pts[:, 0], pts[:, 1], s, th, eta, tau, o) >= 1 / 255
         assert _inside(poly, pts[supp]).all(), trial
+
+
+# ---- Pre-sort key variants and sorting-accuracy measures (supplement, cache-sorting evaluation)
+def test_sort_metrics_hand_examples():
+    m = O.sort_metrics([[1.0, 2.0, 3.0]])
+    assert (m["accuracy"], m["kendall_tau"], m["mae"]) == (1.0, 1.0, 0.0)
+    m = O.sort_metrics([[3.0, 2.0, 1.0]])
+    assert m["accuracy"] == pytest.approx(1 / 3) and m["kendall_tau"] == -1.0 and m["mae"] == pytest.approx(4 / 3)
+    # ties count as neither concordant nor discordant; equal depths at a position count as correct
+    m = O.sort_metrics([[2.0, 1.0, 3.0, 3.0]])
+    assert m["accuracy"] == 0.5 and m["kendall_tau"] == 0.5 and m["mae"] == 0.5
+    # pooled over pixels: accuracy and MAE per element, tau per pixel; single-element pixels carry no tau
+    m = O.sort_metrics([[1.0, 2.0], [2.0, 1.0], [5.0]], cap=None)
+    assert m["accuracy"] == pytest.approx(3 / 5) and m["kendall_tau"] == 0.0 and m["pixels"] == 2
+    assert O.sort_metrics([[3.0, 2.0, 1.0, 0.0]], cap=2)["kendall_tau"] == -1.0
+
+
+def test_kendall_tau_matches_scipy():
+    scipy_stats = pytest.importorskip("scipy.stats")
+    rng = np.random.default_rng(41)
+    for m in (2, 3, 7, 40):
+        for _ in range(5):
+            z = rng.permutation(m).astype(np.float64) + rng.uniform(0, 0.5, m)
+            ref = scipy_stats.kendalltau(np.arange(m), z).statistic
+            assert O.sort_metrics([z])["kendall_tau"] == pytest.approx(ref, abs=1e-12)
+
+
+def _tilted_scene(seed, n=40, K=8):
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-0.6, 0.6, (3, n)).astype(np.float32)
+    q = rng.normal(size=(4, n)).astype(np.float32)
+    th = np.sort(rng.uniform(0, 2 * math.pi, (n, K)), 1)
+    th[:, :] = (np.arange(K)[None, :] + rng.uniform(0.1, 0.9, (n, K))) * (2 * math.pi / K)
+    s = np.exp(rng.uniform(math.log(0.1), math.log(0.6), (K, n))).astype(np.float32)
+    return Scene(mu, q, s, th.T.astype(np.float32), rng.uniform(0, 1, n).astype(np.float32),
+                 rng.uniform(0, 0.9, n).astype(np.float32), rng.uniform(0.3, 0.95, n).astype(np.float32),
+                 rng.uniform(0, 1, (3, n)).astype(np.float32), -1)
+
+
+def _cam_tilted(W=96, H=80):
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+    a = 0.35
+    R = np.array([[math.cos(a), 0, -math.sin(a)], [0, 1, 0], [math.sin(a), 0, math.cos(a)]], np.float32)
+    return Camera(W, H, fx, fy, cx, cy, R, np.array([0.1, -0.05, 2.6], np.float32), np.zeros(3, np.float32))
+
+
+def _depth_world(scene, cam, j, x, y):
+    """View depth where the rays through pixel points (x, y) (arrays) meet DRK j's plane, from the
+    world-space ray-plane intersection of Sec. 3.3 (independent of the camera-frame form the keys
+    use)."""
+    Rc = np.asarray(cam.R, np.float32).astype(np.float64)
+    t = np.asarray(cam.t, np.float32).astype(np.float64)
+    ro = -np.linalg.solve(Rc, t)
+    f64 = lambda a: np.float64(np.float32(a))
+    x, y = np.atleast_1d(np.asarray(x, np.float64)), np.atleast_1d(np.asarray(y, np.float64))
+    dcam = np.stack([(x - f64(cam.cx)) / f64(cam.fx), (y - f64(cam.cy)) / f64(cam.fy), np.ones_like(x)])
+    d = np.linalg.solve(Rc, dcam)                      # (3, P) world directions
+    q = scene.q[:, j].astype(np.float64)
+    n = O.quat_to_rotmat(torch.as_tensor(q))[:, 2].numpy()
+    mu = scene.mu[:, j].astype(np.float64)
+    rt = ((mu - ro) @ n) / (n @ d)
+    return rt * (Rc[2] @ d)
+
+
+def test_tile_keys_fronto_parallel_equal_centre_depth():
+    """A DRK parallel to the image plane has one depth everywhere: both per-tile keys equal the
+    centre-depth key."""
+    sc = _tilted_scene(5)
+    sc.q[:] = np.array([[1.0], [0.0], [0.0], [0.0]], np.float32)
+    fx, fy, cx, cy = intrinsics_hfov(64, 48, 60.0)
+    cam = Camera(64, 48, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.array([0, 0, 3.0], np.float32),
+                 np.zeros(3, np.float32))
+    centre = O.centre_depth_f32(sc.mu, cam)
+    for mode in (O.KEY_CENTRIC, O.KEY_NEAREST):
+        opts = O.Opts(key_mode=mode).f32()
+        for j in range(sc.n):
+            kp = O.key_plane(sc, cam, opts, j)
+            for t in O.primitive_tiles(sc, cam, opts, j):
+                k = np.uint32(O.tile_key(kp, cam, opts, t)).view(np.float32)
+                assert abs(float(k) - float(centre[j])) <= 2e-7 * float(centre[j]), (mode, j, t)
+
+
+def test_nearest_key_is_the_minimum_over_the_tile_brute_force():
+    """The nearest key is the smallest plane depth over the kernel's part of the tile (checked on a
+    33 x 33 grid of that rectangle with the world-space intersection), and the centric key is the
+    depth at the rectangle's centre; both then held to the support's depth range."""
+    sc, cam = _tilted_scene(6), _cam_tilted()
+    checked = 0
+    for mode in (O.KEY_CENTRIC, O.KEY_NEAREST):
+        opts = O.Opts(key_mode=mode).f32()
+        for j in range(sc.n):
+            kp = O.key_plane(sc, cam, opts, j)
+            for t in O.primitive_tiles(sc, cam, opts, j):
+                xa, xb, ya, yb = O.key_rect(kp, cam, t)
+                gx, gy = np.meshgrid(np.linspace(xa, xb, 33), np.linspace(ya, yb, 33))
+                z = _depth_world(sc, cam, j, gx.ravel(), gy.ravel())
+                if not (z > opts.near).all():
+                    continue      # the plane turns away inside the rectangle: fallbacks apply
+                ref = z.min() if mode == O.KEY_NEAREST else \
+                    _depth_world(sc, cam, j, 0.5 * (xa + xb), 0.5 * (ya + yb))[0]
+                ref = min(max(ref, kp.zlo), kp.zhi)
+                assert O.tile_key_value(kp, cam, opts, t, mode) == pytest.approx(ref, rel=1e-9), (mode, j, t)
+                checked += 1
+    assert checked > 100
+
+
+def test_nearest_key_never_after_centric_key():
+    sc, cam = _tilted_scene(7), _cam_tilted()
+    o1, o2 = O.Opts(key_mode=O.KEY_CENTRIC).f32(), O.Opts(key_mode=O.KEY_NEAREST).f32()
+    n = 0
+    for j in range(sc.n):
+        kp = O.key_plane(sc, cam, o1, j)
+        for t in O.primitive_tiles(sc, cam, o1, j):
+            xa, xb, ya, yb = O.key_rect(kp, cam, t)
+            if all(O.plane_depth(kp, cam, o1, x, y) is not None for x in (xa, xb) for y in (ya, yb)):
+                assert O.tile_key_value(kp, cam, o2, t, O.KEY_NEAREST) <= O.tile_key_value(kp, cam, o1, t,
+                                                                                         O.KEY_CENTRIC)
+                n += 1
+    assert n > 100
+
+
+def test_support_depth_range_contains_polygon():
+    """Every vertex of the support polygon lifted to the camera frame has a view depth within the
+    support disc's range [zlo, zhi] (zlo before its clamp at the near plane)."""
+    sc, cam = _tilted_scene(8), _cam_tilted()
+    opts = O.Opts().f32()
+    Rc = np.asarray(cam.R, np.float32).astype(np.float64)
+    t = np.asarray(cam.t, np.float32).astype(np.float64)
+    for j in range(sc.n):
+        kp = O.key_plane(sc, cam, opts, j)
+        o, tau = float(sc.opacity[j]), float(sc.tau[j])
+        c = float(O.calibrated_radius(torch.tensor(o, dtype=F64), torch.tensor(tau, dtype=F64), opts.alpha_min))
+        poly = O.support_polygon(sc.scale[:, j].astype(np.float64), sc.theta[:, j].astype(np.float64), c)
+        R = O.quat_to_rotmat(torch.as_tensor(sc.q[:, j].astype(np.float64))).numpy()
+        w = sc.mu[:, j].astype(np.float64)[None, :] + poly[:, :1] * R[:, 0] + poly[:, 1:] * R[:, 1]
+        z = (w @ Rc.T + t)[:, 2]
+        zr = kp.zhi - kp.zc
+        assert z.max() <= kp.zhi + 1e-12 and z.min() >= kp.zc - zr - 1e-12
+
+
+def test_per_tile_keys_change_order_not_images_of_separated_layers():
+    """With well separated depth layers every pre-sort key gives the exact front-to-back order,
+    so the three key modes give the same image as the exact sort."""
+    rng = np.random.default_rng(9)
+    n, K = 12, 8
+    # one DRK per layer, tilted by about 0.1 rad: each spans at most +-0.09 in depth, 0.25 apart
+    mu = np.stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.3, 0.3, n), rng.permutation(n) * 0.25])
+    q = np.tile(np.array([[1.0], [0.05], [0.0], [0.0]]), (1, n))
+    th = (np.arange(K)[:, None] + 0.5) * (2 * math.pi / K) + np.zeros((1, n))
+    sc = Scene(mu.astype(np.float32), q.astype(np.float32), np.full((K, n), 0.2, np.float32), th.astype(np.float32),
+               np.full(n, 0.5, np.float32), np.zeros(n, np.float32), np.full(n, 0.6, np.float32),
+               rng.uniform(0, 1, (3, n)).astype(np.float32), -1)
+    fx, fy, cx, cy = intrinsics_hfov(32, 32, 60.0)
+    cam = Camera(32, 32, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.array([0, 0, 3.0], np.float32),
+                 np.zeros(3, np.float32))
+    ref = O.render_image(sc, cam, O.Opts(cache_len=O.EXACT))
+    for mode in (0, 1, 2):
+        r = O.render_image(sc, cam, O.Opts(cache_len=1, key_mode=mode))
+        np.testing.assert_allclose(r.rgb, ref.rgb, atol=1e-12)
+        assert O.sort_metrics(r.emitted_z)["accuracy"] == 1.0
