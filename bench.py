@@ -172,6 +172,43 @@ def ksweep_phase(args, opts, W, H):
     return out
 
 
+def sortacc_phase(args, ras, ds, frames, W, H, rgb, T):
+    """Sorting accuracy of the pre-sort keys (supplement, cache-sorting evaluation): randomly placed
+    and oriented kernels (1500 DRKs, K = 8, scales 0.05-0.5 in a 2-unit box) rendered at 512x512
+    with each key and cache length, traced front to back and measured by drk_trace_metrics; plus
+    the cost of each key on the headline workload (same frames as the fwd phase)."""
+    import torch
+    from drk_synth import camera_lookat, scene_uniform_box
+    from paper_2412_11752_amd import DRKScene, Rasterizer, make_opts, trace_metrics
+    out = {"scene": "1500 DRKs (K=8) uniform in [-1,1]^3, scales log-uniform in [0.05, 0.5], random orientations, "
+                    "512x512 view from distance 3", "cap": 64, "metrics": {}, "cost": {}}
+    host = scene_uniform_box(77, 1500, K=8, half=1.0, s_lo=0.05, s_hi=0.5)
+    cam = camera_lookat((0.4, -0.3, -3.0), (0, 0, 0), (0, 1, 0), 512, 512, 60.0, bg=(0.1, 0.1, 0.1))
+    sd = DRKScene.from_host(host, device="cuda")
+    r2 = Rasterizer(host.n, host.K, 512, 512, pair_capacity=1 << 22)
+    names = {0: "centre", 1: "centric", 2: "nearest"}
+    for mode in (0, 1, 2):
+        row = {}
+        for L in (1, 2, 4, 8):
+            r2.preprocess(sd, [cam], make_opts(cache_len=L, key_mode=mode))
+            r2.bin_sort()
+            _, _, tn, ti, tz = r2.render_trace(64)
+            m = trace_metrics(tn, tz, 64)
+            row[str(L)] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in m.items()}
+        out["metrics"][names[mode]] = row
+        log(f"sortacc {names[mode]}: " + ", ".join(f"L={L} acc {v['accuracy']:.3f} tau {v['kendall_tau']:.3f} "
+                                                  f"mae {v['mae']:.4f}" for L, v in row.items()))
+    r2.close()
+    for mode in (0, 1, 2):
+        t_total, ms = timed(ras, ds, frames, make_opts(key_mode=mode), args, rgb, T)
+        out["cost"][names[mode]] = {"mpix_s": round(args.steps * W * H / t_total / 1e6, 2),
+                                    "ms_preprocess": round(float(ms[:, 0].mean()), 4),
+                                    "ms_bin_sort": round(float(ms[:, 1].mean()), 4),
+                                    "ms_raster": round(float(ms[:, 2].mean()), 4)}
+        log(f"sortacc cost {names[mode]}: {out['cost'][names[mode]]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,7 +217,8 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
-    ap.add_argument("--phases", default="fwd,serve", help="fwd, fwdbwd (backward switched off), serve, ksweep")
+    ap.add_argument("--phases", default="fwd,serve",
+                    help="fwd, fwdbwd (backward switched off), serve, ksweep, sortacc")
     ap.add_argument("--ksweep", default="3,5,8,16", help="radial basis counts of the ksweep phase")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the Poisson arrival trace")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
@@ -236,7 +274,7 @@ def main():
     fwd = result.get("fwd")
     roofline = None
     if fwd is not None:
-        achieved = work["flops"] / (fwd["ms"][:, 2].sum() / 1e3) / 1e12
+        achieved = work["flops"] / (float(fwd["ms"][:, 2].mean()) / 1e3) / 1e12   # per-launch work / launch time
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
                     "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": raster_traffic(),
                     "kernel": "k_render_fwd", "avg_launch_ms": round(float(fwd["ms"][:, 2].mean()), 4),
@@ -281,6 +319,9 @@ def main():
                "parity_max_err": float(max(errs)) if errs else None}
         log(f"cpu oracle: {done} px in {el:.1f}s -> {cpu['value']:.2e} Mpix/s; max |gpu-oracle| {cpu['parity_max_err']}")
 
+    sortacc = None
+    if "sortacc" in phases:
+        sortacc = sortacc_phase(args, ras, ds, frames, W, H, rgb, T)
     ras.close()
     torch.cuda.empty_cache()
     ksweep = None
@@ -311,6 +352,8 @@ def main():
     }
     if ksweep is not None:
         line["ksweep"] = ksweep
+    if sortacc is not None:
+        line["sortacc"] = sortacc
     if "fwdbwd" in result:
         line["ms_breakdown"]["render_bwd"] = round(float(result["fwdbwd"]["ms"][:, 3].mean()), 4)
     print(json.dumps(line), flush=True)

@@ -93,12 +93,21 @@ typedef struct drk_camera {
 
 /* Rasterization options.  Defaults (drk_opts_default): alpha_min 1/255, alpha_max 0.99,
  * T_min 1e-4, near 0.2, lowpass_sl sqrt(2)/2 px (Sec. 4.4 low-pass; 0 disables it),
- * cache_len 8 (Sec. 4.4 cache sorting; 1..8, 1 = global centre-depth order),
+ * cache_len 8 (Sec. 4.4 cache sorting; 1..8, 1 = pre-sort order only),
  * cull_mode 0 (0 = conservative support polygon, 1 = the paper's endpoint polygon (lossy),
- * 2 = every tile), validate 0 (1 = return DRK_EINVAL for invalid primitives).               */
+ * 2 = every tile), validate 0 (1 = return DRK_EINVAL for invalid primitives),
+ * key_mode 0: the pre-sort key of the tile lists (supplement, cache-sorting evaluation):
+ *   0 = view depth of the primitive's centre (one key per primitive),
+ *   1 = "most centric": per (tile, primitive), the depth at which the ray through the centre of
+ *       the tile's pixel-centre rectangle, cut to the primitive's projected support box, meets
+ *       the primitive's plane (the centre depth when that ray meets it at or behind the near plane),
+ *   2 = "nearest": per (tile, primitive), the smallest such depth over the four corner rays of that
+ *       rectangle (the support's nearest depth when none meets the plane in front);
+ *   keys 1 and 2 are held to the depth range of the support disc (radius sqrt(2) c max_k s_k),
+ *   computed in float64 in a fixed order and rounded to float32; ties go to the lower index.    */
 typedef struct drk_opts {
   float alpha_min, alpha_max, T_min, near_plane, lowpass_sl;
-  int32_t cache_len, cull_mode, validate;
+  int32_t cache_len, cull_mode, validate, key_mode;
 } drk_opts;
 
 typedef struct drk_ws drk_ws;
@@ -126,11 +135,13 @@ drk_status drk_ws_size_query(int64_t max_n, int32_t K, int32_t max_views, int32_
 drk_status drk_preprocess(drk_ws* ws, const drk_scene* scene, const drk_camera* cams, int32_t n_views,
                           const drk_opts* opts, void* stream);
 
-/* Step 2 (Sec. 4.4 Kernel Culling + Cache Sorting pre-sort).  Per view: stable radix sort of
- * primitives by centre depth, duplication into (tile, primitive) pairs in that order, stable
- * radix sort of the pairs by tile id, and per-tile [start, end) ranges.  The resulting per-tile
- * lists are ordered by (tile, depth key, primitive index).  If a view needs more pairs than
- * pair_capacity the overflow is recorded (see drk_ws_status) and that view renders nothing. */
+/* Step 2 (Sec. 4.4 Kernel Culling + Cache Sorting pre-sort).  Per view, key_mode 0: stable
+ * radix sort of primitives by centre depth, duplication into (tile, primitive) pairs in that
+ * order, stable radix sort of the pairs by tile id.  key_mode 1 or 2: duplication in primitive
+ * order with the per-pair key, stable radix sort of the pairs by key, then by tile id.  Then
+ * per-tile [start, end) ranges.  The resulting per-tile lists are ordered by (tile, key,
+ * primitive index).  If a view needs more pairs than pair_capacity the overflow is recorded
+ * (see drk_ws_status) and that view renders nothing.                                         */
 drk_status drk_bin_sort(drk_ws* ws, void* stream);
 
 /* Step 3 (Eq. 1; Sec. 3.3; Sec. 4.1-4.4; Algorithm 1).  Per pixel: ray-plane hit through each
@@ -139,6 +150,26 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream);
  *   rgb     [V][3][H][W] float32 output (H, W of each view's camera; views packed back to back)
  *   T_final [V][H][W]    float32 output: final transmittance (may be NULL)                   */
 drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream);
+
+/* drk_render_fwd that also records, per pixel, the composited contributions in front-to-back
+ * order (supplement, cache-sorting evaluation: the depths processed front to back):
+ *   trace_n   [V][H][W]       int32 output: contributions composited at the pixel (not capped)
+ *   trace_idx [V][H][W][cap]  int32 output: primitive index of the first min(n, cap) of them
+ *   trace_z   [V][H][W][cap]  float32 output: view depth of their hit (the cache key)
+ * Entries past min(n, cap) are left untouched.  1 <= cap <= 1024, else DRK_EINVAL.            */
+drk_status drk_render_trace(drk_ws* ws, float* rgb, float* T_final, int32_t cap, int32_t* trace_n,
+                            int32_t* trace_idx, float* trace_z, void* stream);
+
+/* Sorting-accuracy measures of recorded traces (device arrays as written by drk_render_trace,
+ * npx pixels, the first m = min(trace_n, cap) depths of each; cap <= 64).  out: 6 doubles
+ * (device), overwritten: [0] sum of m, [1] positions holding the depth the sorted sequence holds
+ * there, [2] sum over pixels with m >= 2 of Kendall's tau between composite order and depth
+ * (ties count as neither concordant nor discordant), [3] pixels with m >= 2, [4] sum of
+ * |depth - sorted depth| per position, [5] pixels with trace_n > cap.  Accuracy = [1]/[0],
+ * mean tau = [2]/[3], MAE = [4]/[0].  The sums use float atomics (the order of additions, and
+ * so the last bits, may vary between calls).                                                  */
+drk_status drk_trace_metrics(const int32_t* trace_n, const float* trace_z, int64_t npx, int32_t cap, double* out,
+                             void* stream);
 
 /* Step 4 (supplement S4: backward front to back, consistent with cache sorting).  Recomputes
  * each pixel's emission sequence and accumulates dL/dparameter for every primitive:
@@ -167,7 +198,8 @@ drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed);
  *   6 consumed     int32  [H*W] (list entries read per pixel before it terminated)
  *   7 contributors int32  [H*W] (entries with alpha >= alpha_min that entered the cache)
  *   8 hits         int32  [H*W] (entries whose ray-plane hit was evaluated)
- *   9 kernels      int32  [H*W] (entries that went through the full kernel evaluation)      */
+ *   9 kernels      int32  [H*W] (entries that went through the full kernel evaluation)
+ *  10 pair keys    uint32 [P]   (pre-sort key of each sorted pair: float32 bits)               */
 drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int64_t bytes, int64_t* out_count,
                          void* stream);
 

@@ -5,7 +5,8 @@ torch binding around it.  Importing the package does not load the library; the f
 and fails loudly if it has not been built.
 """
 from .rasterizer import (  # noqa: F401
-    DRKScene, Rasterizer, DRKRenderFunction, render, camera_struct, make_opts, EXPORT,
+    DRKScene, Rasterizer, DRKRenderFunction, render, camera_struct, make_opts, EXPORT, KEY_MODES, trace_metrics,
 )
 
-__all__ = ["DRKScene", "Rasterizer", "DRKRenderFunction", "render", "camera_struct", "make_opts", "EXPORT"]
+__all__ = ["DRKScene", "Rasterizer", "DRKRenderFunction", "render", "camera_struct", "make_opts", "EXPORT",
+           "KEY_MODES", "trace_metrics"]

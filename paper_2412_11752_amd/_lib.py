@@ -13,7 +13,8 @@ STATUS_NAMES = {0: "DRK_OK", 1: "DRK_EINVAL", 2: "DRK_ENOMEM", 3: "DRK_EOVERFLOW
 
 EXPORTED = [
     "drk_opts_default", "drk_last_error", "drk_version", "drk_ws_create", "drk_ws_destroy", "drk_ws_size_query",
-    "drk_preprocess", "drk_bin_sort", "drk_render_fwd", "drk_render_bwd", "drk_ws_status", "drk_ws_export",
+    "drk_preprocess", "drk_bin_sort", "drk_render_fwd", "drk_render_trace", "drk_trace_metrics", "drk_render_bwd",
+    "drk_ws_status", "drk_ws_export",
     "drk_serve_create", "drk_serve_destroy", "drk_serve_add_scene", "drk_serve_submit", "drk_serve_poll",
 ]
 
@@ -39,7 +40,7 @@ class Camera(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("T_min", C.c_float),
                 ("near_plane", C.c_float), ("lowpass_sl", C.c_float), ("cache_len", C.c_int32),
-                ("cull_mode", C.c_int32), ("validate", C.c_int32)]
+                ("cull_mode", C.c_int32), ("validate", C.c_int32), ("key_mode", C.c_int32)]
 
 
 class ServeCfg(C.Structure):
@@ -81,6 +82,8 @@ def lib() -> C.CDLL:
         "drk_preprocess": [vp, C.POINTER(Scene), C.POINTER(Camera), i32, C.POINTER(Opts), vp],
         "drk_bin_sort": [vp, vp],
         "drk_render_fwd": [vp, vp, vp, vp],
+        "drk_render_trace": [vp, vp, vp, i32, vp, vp, vp, vp],
+        "drk_trace_metrics": [vp, vp, i64, i32, vp, vp],
         "drk_render_bwd": [vp, C.POINTER(Scene), vp, vp, C.POINTER(SceneGrad), vp],
         "drk_ws_status": [vp, vp, C.POINTER(i64)],
         "drk_ws_export": [vp, i32, i32, vp, i64, C.POINTER(i64), vp],

@@ -27,7 +27,8 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"),
     "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["api.cpp", "preprocess.hip", "binning.hip", "render_fwd.hip", "render_bwd.hip", "serve.cpp"]
+SOURCES = ["api.cpp", "preprocess.hip", "binning.hip", "render_fwd.hip", "render_bwd.hip", "trace_metrics.hip",
+           "serve.cpp"]
 
 
 def hipcc() -> str:

@@ -29,10 +29,15 @@ void set_error(const char* fmt, ...) {
 hipError_t set_views(Views*, const Views&, hipStream_t);
 hipError_t launch_preprocess(const SceneDev&, const Views*, int, const OptsDev&, float*, uint32_t*, uint32_t*,
                              uint32_t*, uint32_t*, uint2*, uint32_t*, uint32_t*, int64_t, uint32_t*, int64_t,
-                             hipStream_t);
+                             double*, hipStream_t);
 hipError_t launch_duplicate(const SceneDev&, const Views*, const OptsDev&, int, const uint32_t*, const uint32_t*,
                             const uint32_t*, const uint2*, const uint32_t*, uint32_t*, uint32_t*, const uint64_t*,
-                            int64_t, const uint64_t*, uint32_t*, uint32_t*, hipStream_t);
+                            int64_t, const uint64_t*, uint32_t*, uint32_t*, const double*, uint32_t*, hipStream_t);
+hipError_t launch_pair_keys(const Views*, const OptsDev&, int, const uint32_t*, const uint32_t*, int64_t,
+                            const uint32_t*, const double*, uint32_t*, hipStream_t);
+hipError_t gather_pairs(const uint32_t*, const uint32_t*, const uint32_t*, const uint64_t*, uint32_t*, uint32_t*,
+                        hipStream_t);
+hipError_t launch_trace_metrics(const int32_t*, const float*, int64_t, int, double*, hipStream_t);
 hipError_t radix_sort(int, const uint64_t*, uint32_t* const*, uint32_t* const*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t scan_counts(const uint32_t*, const uint32_t*, const uint64_t*, int64_t, uint32_t*, uint64_t*, uint64_t*,
                        uint64_t*, int64_t, uint32_t*, hipStream_t);
@@ -42,7 +47,8 @@ hipError_t tile_ranges(const uint32_t*, const uint64_t*, uint32_t*, int, hipStre
 hipError_t set_u64(uint64_t*, uint64_t, hipStream_t);
 hipError_t fill_u32(uint32_t*, uint32_t, int64_t, hipStream_t);
 hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
-                             float*, float*, int32_t*, int32_t*, int32_t*, int32_t*, hipStream_t);
+                             float*, float*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, float*, int,
+                             hipStream_t);
 hipError_t launch_render_bwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
                              const float*, const float*, float*, int64_t, hipStream_t);
 hipError_t launch_preprocess_bwd(const SceneDev&, const Views*, const OptsDev&, const uint32_t*, const float*, int64_t,
@@ -86,6 +92,7 @@ struct drk_ws {
   float* out_rgb = nullptr;       // internal output image [3][max_h][max_w] (graph-captured renders)
   uint32_t* dup_big = nullptr;    // sorted slots of the primitives duplicated a workgroup at a time
   uint32_t* dup_count = nullptr;  // their count
+  double* keygeo = nullptr;       // per view and primitive: float64 data of the per-tile keys (KG_N)
 
   SceneDev scene{};
   Views views{};
@@ -156,6 +163,7 @@ size_t layout(drk_ws* ws, bool assign, char* base) {
   SLOT(out_rgb, float, 3 * px)
   SLOT(dup_big, uint32_t, N)
   SLOT(dup_count, uint32_t, 4)
+  SLOT(keygeo, double, V * N * KG_N)
 #undef SLOT
   return p.off;
 }
@@ -242,8 +250,9 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   }
   if (!(opts->alpha_min > 0.0f && opts->alpha_min < 1.0f) || !(opts->alpha_max > 0.0f && opts->alpha_max < 1.0f) ||
       !(opts->T_min > 0.0f && opts->T_min < 1.0f) || !(opts->near_plane > 0.0f) || !(opts->lowpass_sl >= 0.0f) ||
-      opts->cache_len < 1 || opts->cache_len > kMaxCache || opts->cull_mode < 0 || opts->cull_mode > 2) {
-    set_error("invalid drk_opts (cache_len must be in [1, %d])", kMaxCache);
+      opts->cache_len < 1 || opts->cache_len > kMaxCache || opts->cull_mode < 0 || opts->cull_mode > 2 ||
+      opts->key_mode < 0 || opts->key_mode > 2) {
+    set_error("invalid drk_opts (cache_len must be in [1, %d], key_mode in [0, 2])", kMaxCache);
     return DRK_EINVAL;
   }
   SceneDev sc;
@@ -255,14 +264,14 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   OptsDev od;
   od.alpha_min = opts->alpha_min; od.alpha_max = opts->alpha_max; od.T_min = opts->T_min;
   od.near_plane = opts->near_plane; od.lowpass_sl = opts->lowpass_sl; od.cache_len = opts->cache_len;
-  od.cull_mode = opts->cull_mode; od.validate = opts->validate;
+  od.cull_mode = opts->cull_mode; od.validate = opts->validate; od.key_mode = opts->key_mode;
   drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
   if (st) return st;
   if ((st = check_hip(fill_u32(ws->counters, 0u, 2 * ws->max_views, s), "clear counters"))) return st;
   const int V = ws->max_views;
   st = check_hip(launch_preprocess(sc, ws->views_dev, ws->views.nv, od, ws->records, ws->depth_keys, ws->tile_counts,
                                    ws->work, ws->counters, ws->span_meta, ws->span_rows, ws->counters + V,
-                                   ws->row_cap, ws->status, ws->max_n, s),
+                                   ws->row_cap, ws->status, ws->max_n, ws->keygeo, s),
                  "preprocess launch");
   if (st) return st;
   ws->scene = sc;
@@ -321,6 +330,7 @@ drk_opts drk_opts_default(void) {
   o.cache_len = 8;
   o.cull_mode = 0;
   o.validate = 0;
+  o.key_mode = 0;
   return o;
 }
 
@@ -398,29 +408,48 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
                                         ws->n_prims, ws->n_prims + 1, ws->ck, ws->cv, ws->status + v, s),
                         "compact")))
       return st;
-    uint32_t* kb[5] = {ws->ck, ws->dk_a, ws->dk_b, ws->dk_a, ws->dk_b};
-    uint32_t* vb[5] = {ws->cv, ws->dv_a, ws->dv_b, ws->dv_a, ws->dv_b};
-    if ((st = check_hip(radix_sort(32, ws->n_prims, kb, vb, ws->hist, ws->tot, s), "depth sort"))) return st;
-    const uint32_t* sorted = ws->dv_b;
-    // 2. offsets of each primitive's pairs in depth order
-    if ((st = check_hip(scan_counts(sorted, counts, ws->n_prims, N, ws->offsets, ws->block_tot, ws->totals + v,
+    const bool tile_keys = ws->opts.key_mode != 0;
+    const uint32_t* order = ws->cv;      // visible primitives in index order
+    if (!tile_keys) {
+      uint32_t* kb[5] = {ws->ck, ws->dk_a, ws->dk_b, ws->dk_a, ws->dk_b};
+      uint32_t* vb[5] = {ws->cv, ws->dv_a, ws->dv_b, ws->dv_a, ws->dv_b};
+      if ((st = check_hip(radix_sort(32, ws->n_prims, kb, vb, ws->hist, ws->tot, s), "depth sort"))) return st;
+      order = ws->dv_b;
+    }
+    // 2. offsets of each primitive's pairs in that order
+    if ((st = check_hip(scan_counts(order, counts, ws->n_prims, N, ws->offsets, ws->block_tot, ws->totals + v,
                                     ws->n_eff + v, ws->cap, ws->status + v, s), "count scan")))
       return st;
-    // 3. duplicate into (tile, primitive) pairs
+    // 3. duplicate into (tile, primitive) pairs (with per-tile keys: into the final arrays, which
+    //    the key sort then uses as scratch, with the keys in pk_tmp)
     int bits = 1;
     while ((1 << bits) < ntiles) ++bits;
     const int passes = (bits + 7) / 8;
     uint32_t* fk = ws->pair_tiles + (size_t)v * ws->cap;
     uint32_t* fv = ws->pair_prims + (size_t)v * ws->cap;
-    if ((st = check_hip(launch_duplicate(ws->scene, ws->views_dev, ws->opts, v, sorted, ws->offsets, counts,
+    if ((st = check_hip(launch_duplicate(ws->scene, ws->views_dev, ws->opts, v, order, ws->offsets, counts,
                                          ws->span_meta + (size_t)v * ws->max_n,
-                                         ws->span_rows + (size_t)v * ws->row_cap, ws->pk_tmp, ws->pv_tmp,
-                                         ws->totals + v, ws->cap, ws->n_prims, ws->dup_big, ws->dup_count, s),
+                                         ws->span_rows + (size_t)v * ws->row_cap, tile_keys ? fk : ws->pk_tmp,
+                                         tile_keys ? fv : ws->pv_tmp, ws->totals + v, ws->cap, ws->n_prims,
+                                         ws->dup_big, ws->dup_count, ws->keygeo + (size_t)v * ws->max_n * KG_N,
+                                         tile_keys ? ws->pk_tmp : nullptr, s),
                         "duplicate")))
       return st;
-    // 4. stable sort of the pairs by tile id -> (tile, depth, index) order
-    uint32_t* pk[3] = {ws->pk_tmp, passes == 2 ? ws->pk_tmp2 : fk, fk};
-    uint32_t* pv[3] = {ws->pv_tmp, passes == 2 ? ws->pv_tmp2 : fv, fv};
+    if (tile_keys) {
+      // 3b. stable sort of the pair keys (values: pair ids), then tile and primitive in key order
+      uint32_t* kk[5] = {ws->pk_tmp, ws->pk_tmp2, ws->pk_tmp, ws->pk_tmp2, ws->pk_tmp};
+      uint32_t* kv[5] = {nullptr, ws->pv_tmp2, ws->pv_tmp, ws->pv_tmp2, ws->pv_tmp};
+      if ((st = check_hip(radix_sort(32, ws->n_eff + v, kk, kv, ws->hist, ws->tot, s), "key sort"))) return st;
+      if ((st = check_hip(gather_pairs(ws->pv_tmp, fk, fv, ws->n_eff + v, ws->pk_tmp2, ws->pv_tmp2, s), "gather")))
+        return st;
+    }
+    // 4. stable sort of the pairs by tile id -> (tile, key, index) order
+    uint32_t* src_k = tile_keys ? ws->pk_tmp2 : ws->pk_tmp;
+    uint32_t* src_v = tile_keys ? ws->pv_tmp2 : ws->pv_tmp;
+    uint32_t* mid_k = tile_keys ? ws->pk_tmp : ws->pk_tmp2;
+    uint32_t* mid_v = tile_keys ? ws->pv_tmp : ws->pv_tmp2;
+    uint32_t* pk[3] = {src_k, passes == 2 ? mid_k : fk, fk};
+    uint32_t* pv[3] = {src_v, passes == 2 ? mid_v : fv, fv};
     if ((st = check_hip(radix_sort(bits, ws->n_eff + v, pk, pv, ws->hist, ws->tot, s), "tile sort"))) return st;
     // 5. ranges
     if ((st = check_hip(tile_ranges(fk, ws->n_eff + v, ws->ranges + (size_t)v * 2 * ws->max_tiles, ntiles, s),
@@ -431,10 +460,10 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
   return DRK_OK;
 }
 
-drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream) {
-  if (!ws || !rgb) { set_error("null argument"); return DRK_EINVAL; }
-  if (!ws->have_bins) { set_error("drk_render_fwd before drk_bin_sort"); return DRK_EINVAL; }
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+namespace {
+
+drk_status render_views(drk_ws* ws, float* rgb, float* T_final, int32_t cap, int32_t* trace_n, int32_t* trace_idx,
+                        float* trace_z, hipStream_t s) {
   size_t off = 0;
   const size_t px_max = (size_t)ws->max_w * ws->max_h;
   for (int v = 0; v < ws->views.nv; ++v) {
@@ -445,12 +474,38 @@ drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream) 
                           ws->pair_prims + (size_t)v * ws->cap, &ws->views_dev->cam[v], cam.tiles_x * cam.tiles_y,
                           ws->opts, rgb + 3 * off,
                           T_final ? T_final + off : nullptr, ws->n_emit + v * px_max, ws->consumed + v * px_max,
-                          ws->contrib + v * px_max, ws->work_px + 2 * v * px_max, s),
-        "render_fwd");
+                          ws->contrib + v * px_max, ws->work_px + 2 * v * px_max,
+                          trace_n ? trace_n + off : nullptr, trace_n ? trace_idx + off * cap : nullptr,
+                          trace_n ? trace_z + off * cap : nullptr, cap, s),
+        trace_n ? "render_trace" : "render_fwd");
     if (st) return st;
     off += npx;
   }
   return DRK_OK;
+}
+
+}  // namespace
+
+drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream) {
+  if (!ws || !rgb) { set_error("null argument"); return DRK_EINVAL; }
+  if (!ws->have_bins) { set_error("drk_render_fwd before drk_bin_sort"); return DRK_EINVAL; }
+  return render_views(ws, rgb, T_final, 0, nullptr, nullptr, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+drk_status drk_render_trace(drk_ws* ws, float* rgb, float* T_final, int32_t cap, int32_t* trace_n,
+                            int32_t* trace_idx, float* trace_z, void* stream) {
+  if (!ws || !rgb || !trace_n || !trace_idx || !trace_z) { set_error("null argument"); return DRK_EINVAL; }
+  if (!ws->have_bins) { set_error("drk_render_trace before drk_bin_sort"); return DRK_EINVAL; }
+  if (cap < 1 || cap > 1024) { set_error("trace cap %d outside [1, 1024]", cap); return DRK_EINVAL; }
+  return render_views(ws, rgb, T_final, cap, trace_n, trace_idx, trace_z, reinterpret_cast<hipStream_t>(stream));
+}
+
+drk_status drk_trace_metrics(const int32_t* trace_n, const float* trace_z, int64_t npx, int32_t cap, double* out,
+                             void* stream) {
+  if (!trace_n || !trace_z || !out) { set_error("null argument"); return DRK_EINVAL; }
+  if (npx < 0 || cap < 1 || cap > 64) { set_error("npx must be >= 0 and cap in [1, 64]"); return DRK_EINVAL; }
+  return check_hip(launch_trace_metrics(trace_n, trace_z, npx, cap, out, reinterpret_cast<hipStream_t>(stream)),
+                   "trace metrics");
 }
 
 drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, const float* dL_drgb,
@@ -536,6 +591,21 @@ drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int6
     case 7: src = ws->contrib + view * px_max; count = (int64_t)cam.W * cam.H; break;
     case 8: src = ws->work_px + 2 * view * px_max; count = (int64_t)cam.W * cam.H; break;
     case 9: src = ws->work_px + 2 * view * px_max + (size_t)cam.W * cam.H; count = (int64_t)cam.W * cam.H; break;
+    case 10: {
+      if (!ws->have_bins) { set_error("no bins yet"); return DRK_EINVAL; }
+      uint64_t ne = 0;
+      drk_status st = check_hip(hipStreamSynchronize(s), "sync");
+      if (st) return st;
+      if ((st = check_hip(hipMemcpy(&ne, ws->n_eff + view, 8, hipMemcpyDeviceToHost), "read n"))) return st;
+      *out_count = (int64_t)ne;
+      if (!dst) return DRK_OK;
+      const int64_t n = std::min<int64_t>((int64_t)ne, bytes / 4);
+      return check_hip(launch_pair_keys(ws->views_dev, ws->opts, view, ws->pair_tiles + (size_t)view * ws->cap,
+                                        ws->pair_prims + (size_t)view * ws->cap, n,
+                                        ws->depth_keys + (size_t)view * ws->max_n,
+                                        ws->keygeo + (size_t)view * ws->max_n * KG_N, static_cast<uint32_t*>(dst), s),
+                       "pair keys");
+    }
     default: set_error("unknown export %d", what); return DRK_EINVAL;
   }
   *out_count = count;

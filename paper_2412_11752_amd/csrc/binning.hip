@@ -309,6 +309,25 @@ hipError_t tile_ranges(const uint32_t* tiles, const uint64_t* d_n, uint32_t* ran
   return hipGetLastError();
 }
 
+// After the stable sort of pair keys (values = pair ids): tile and primitive of each pair in key
+// order, ready for the stable sort by tile.
+__global__ void __launch_bounds__(256) k_gather_pairs(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ tiles,
+                                                      const uint32_t* __restrict__ prims, const uint64_t* __restrict__ d_n,
+                                                      uint32_t* __restrict__ tiles_out, uint32_t* __restrict__ prims_out) {
+  const uint64_t n = *d_n;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    const uint32_t id = ids[i];
+    tiles_out[i] = tiles[id];
+    prims_out[i] = prims[id];
+  }
+}
+
+hipError_t gather_pairs(const uint32_t* ids, const uint32_t* tiles, const uint32_t* prims, const uint64_t* d_n,
+                        uint32_t* tiles_out, uint32_t* prims_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_pairs, dim3(2048), dim3(256), 0, s, ids, tiles, prims, d_n, tiles_out, prims_out);
+  return hipGetLastError();
+}
+
 __global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
 
 __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {

@@ -73,8 +73,14 @@ struct Views {
 
 struct OptsDev {
   float alpha_min, alpha_max, T_min, near_plane, lowpass_sl;
-  int32_t cache_len, cull_mode, validate;
+  int32_t cache_len, cull_mode, validate, key_mode;
 };
+
+// Per (view, primitive) float64 data of the per-tile pre-sort keys (key_mode 1, 2), written by the
+// preprocess with the record: the camera-frame plane a . X = dN (a = t_u^c x t_v^c), the centre
+// depth, the depth range [zlo, zhi] of the support disc (radius sqrt(2) c max_k s_k; zlo >= near)
+// and the pixel box (x0, x1, y0, y1) of the projected support (+-1e30 when cull_mode != 0).
+enum KeyGeoField : int { KG_A = 0, KG_DN = 3, KG_ZC = 4, KG_ZLO = 5, KG_ZHI = 6, KG_BOX = 7, KG_N = 12 };
 
 struct SceneDev {
   int64_t n;

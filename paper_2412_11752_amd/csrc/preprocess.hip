@@ -407,7 +407,7 @@ __device__ inline uint32_t wave_alloc(uint32_t* ctr, uint32_t n) {
 
 // Render record of a visible primitive (layout: RecField / SecField).
 __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const CamDev& cam, const OptsDev& opt,
-                             const double box[4], float* rec) {
+                             const double box[4], float* rec, double* kg) {
   const int64_t n = sc.n;
   const int K = sc.K;
   // homography: adjugate rows of N = [t_u^c | t_v^c | mu_c]
@@ -420,6 +420,20 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
   double a2[3] = {tuc[1] * tvc[2] - tuc[2] * tvc[1], tuc[2] * tvc[0] - tuc[0] * tvc[2],
                   tuc[0] * tvc[1] - tuc[1] * tvc[0]};
   double dN = a2[0] * m[0] + a2[1] * m[1] + a2[2] * m[2];
+  double smax = 0.0;
+  for (int k = 0; k < K; ++k) smax = fmax(smax, g.s[k]);
+  if (kg) {
+    // per-tile key data: the plane, and the depth range of the disc of radius sqrt(2) c max_k s_k
+    // around the centre, which holds the support polygon (its half-sector quads reach rho / cos(h)
+    // with rho <= c max_k s_k and h < pi/4)
+    const double zr = (1.4142135623730951 * (g.c * smax)) * sqrt(tuc[2] * tuc[2] + tvc[2] * tvc[2]);
+    for (int i = 0; i < 3; ++i) kg[KG_A + i] = a2[i];
+    kg[KG_DN] = dN;
+    kg[KG_ZC] = m[2];
+    kg[KG_ZLO] = fmax(m[2] - zr, (double)opt.near_plane);
+    kg[KG_ZHI] = m[2] + zr;
+    for (int i = 0; i < 4; ++i) kg[KG_BOX + i] = box[i];
+  }
   double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
   double pxc = (fx * m[0]) / m[2] + cx, pyc = (fy * m[1]) / m[2] + cy;
   double axc = fmin(fmax(pxc, -2.0 * cam.W), 3.0 * cam.W);
@@ -449,8 +463,6 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
   rec[R_TAU] = (float)tau;
   // exact early-outs of the raster (with margin): E >= r2 / max_k s_k^2 (both the L1 chord and sbar
   // are bounded by the larger basis length), and the low-pass term needs d^2/den^2 <= 2 s_l^2 ln(o/alpha_min)
-  double smax = 0.0;
-  for (int k = 0; k < K; ++k) smax = fmax(smax, g.s[k]);
   rec[R_R2CUT] = (float)(1.001 * (g.c * smax) * (g.c * smax) + 1e-30);
   const double ratio = g.o / (double)opt.alpha_min;
   const double lpc = opt.lowpass_sl > 0.0f ? 2.0 * (double)opt.lowpass_sl * (double)opt.lowpass_sl *
@@ -537,7 +549,8 @@ __global__ void __launch_bounds__(128) k_polygon(SceneDev sc, const Views* __res
                                                  const uint32_t* __restrict__ work,
                                                  const uint32_t* __restrict__ work_count,
                                                  uint2* __restrict__ span_meta, uint32_t* __restrict__ span_rows,
-                                                 uint32_t* __restrict__ rows_used, int64_t row_cap, int64_t stride) {
+                                                 uint32_t* __restrict__ rows_used, int64_t row_cap, int64_t stride,
+                                                 double* __restrict__ keygeo) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
   const CamDev& cam = views->cam[v];
@@ -592,13 +605,53 @@ __global__ void __launch_bounds__(128) k_polygon(SceneDev sc, const Views* __res
   } else {
     box[0] = sp.bx0; box[1] = sp.bx1; box[2] = sp.by0; box[3] = sp.by1;
   }
-  write_record(g, sc, j, cam, opt, box, records + ((int64_t)v * stride + j) * rec_floats(sc.K));
+  write_record(g, sc, j, cam, opt, box, records + ((int64_t)v * stride + j) * rec_floats(sc.K),
+               opt.key_mode != 0 ? keygeo + ((int64_t)v * stride + j) * KG_N : nullptr);
 }
 
 // ---------------------------------------------------------------------------------------------
-// Duplication: for the depth-sorted primitive order, write (tile id, primitive) pairs at the
-// scanned offsets, row-major over each primitive's tiles, from the stored row spans (recomputed
-// with the same float64 code when they did not fit the row buffer).
+// Per-tile pre-sort keys (supplement, cache-sorting evaluation), float64 in the order written.
+// View depth where the ray through pixel point (x, y) meets the plane; false when it meets it at
+// or behind the near plane (or not at all).
+__device__ inline bool plane_depth(const double* kg, const CamDev& cam, double nearp, double x, double y, double& z) {
+  const double wd = (kg[KG_A] * ((x - (double)cam.cx) / (double)cam.fx) +
+                     kg[KG_A + 1] * ((y - (double)cam.cy) / (double)cam.fy)) + kg[KG_A + 2];
+  if (wd == 0.0) return false;
+  z = kg[KG_DN] / wd;
+  return z > nearp && z < INFINITY;
+}
+
+// float32 bits of the key of the primitive with key data kg in tile `tile` (key_mode 1: depth on
+// the ray through the centre of the tile's pixel-centre rectangle cut to the support box; 2: the
+// smallest depth over that rectangle's corner rays), held to [zlo, zhi].
+__device__ inline uint32_t tile_key(const double* kg, const CamDev& cam, const OptsDev& opt, uint32_t tile) {
+  const int tx = (int)(tile % (uint32_t)cam.tiles_x), ty = (int)(tile / (uint32_t)cam.tiles_x);
+  double xa = 16.0 * tx + 0.5, xb = fmin(16.0 * tx + 15.5, cam.W - 0.5);
+  double ya = 16.0 * ty + 0.5, yb = fmin(16.0 * ty + 15.5, cam.H - 0.5);
+  const double x0 = fmax(xa, kg[KG_BOX + 0]), x1 = fmin(xb, kg[KG_BOX + 1]);
+  const double y0 = fmax(ya, kg[KG_BOX + 2]), y1 = fmin(yb, kg[KG_BOX + 3]);
+  if (!(x0 > x1) && !(y0 > y1)) { xa = x0; xb = x1; ya = y0; yb = y1; }
+  const double nearp = (double)opt.near_plane;
+  double z;
+  if (opt.key_mode == 1) {
+    if (!plane_depth(kg, cam, nearp, 0.5 * (xa + xb), 0.5 * (ya + yb), z)) z = kg[KG_ZC];
+  } else {
+    z = INFINITY;
+    double d;
+    if (plane_depth(kg, cam, nearp, xa, ya, d)) z = fmin(z, d);
+    if (plane_depth(kg, cam, nearp, xb, ya, d)) z = fmin(z, d);
+    if (plane_depth(kg, cam, nearp, xa, yb, d)) z = fmin(z, d);
+    if (plane_depth(kg, cam, nearp, xb, yb, d)) z = fmin(z, d);
+    if (z == INFINITY) z = kg[KG_ZLO];
+  }
+  return __float_as_uint((float)fmin(fmax(z, kg[KG_ZLO]), kg[KG_ZHI]));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Duplication: for the given primitive order (depth-sorted, or index order with per-tile keys),
+// write (tile id, primitive) pairs at the scanned offsets, row-major over each primitive's tiles,
+// from the stored row spans (recomputed with the same float64 code when they did not fit the row
+// buffer), and with key_mode 1 or 2 each pair's key.
 __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __restrict__ views, OptsDev opt, int v,
                                                    const uint32_t* __restrict__ sorted_prims,
                                                    const uint32_t* __restrict__ offsets,   // exclusive, per sorted slot
@@ -608,7 +661,8 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
                                                    uint32_t* __restrict__ pair_tiles, uint32_t* __restrict__ pair_prims,
                                                    const uint64_t* __restrict__ total_ptr, int64_t capacity,
                                                    const uint64_t* __restrict__ n_sorted,
-                                                   uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count) {
+                                                   uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count,
+                                                   const double* __restrict__ keygeo, uint32_t* __restrict__ pair_keys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)*n_sorted) return;
   const uint32_t j = sorted_prims[i];
@@ -622,8 +676,13 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
     big_list[atomicAdd(big_count, 1u)] = (uint32_t)i;   // written by k_duplicate_big
     return;
   }
+  const double* kg = pair_keys ? keygeo + (int64_t)j * KG_N : nullptr;
   if (opt.cull_mode == 2) {
-    for (uint32_t t = 0; t < cnt; ++t) { pair_tiles[off + t] = t; pair_prims[off + t] = j; }
+    for (uint32_t t = 0; t < cnt; ++t) {
+      pair_tiles[off + t] = t;
+      pair_prims[off + t] = j;
+      if (kg) pair_keys[off + t] = tile_key(kg, cam, opt, t);
+    }
     return;
   }
   uint32_t w = 0;
@@ -638,6 +697,7 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
       for (int c = i0; c <= i1 && w < cnt; ++c, ++w) {
         pair_tiles[off + w] = base + (uint32_t)c;
         pair_prims[off + w] = j;
+        if (kg) pair_keys[off + w] = tile_key(kg, cam, opt, base + (uint32_t)c);
       }
     }
     return;
@@ -653,6 +713,7 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
     for (int c = i0; c <= i1 && w < cnt; ++c, ++w) {
       pair_tiles[off + w] = (uint32_t)(r * cam.tiles_x + c);
       pair_prims[off + w] = j;
+      if (kg) pair_keys[off + w] = tile_key(kg, cam, opt, (uint32_t)(r * cam.tiles_x + c));
     }
   }
 }
@@ -668,7 +729,9 @@ __global__ void __launch_bounds__(256) k_duplicate_big(const Views* __restrict__
                                                        uint32_t* __restrict__ pair_tiles, uint32_t* __restrict__ pair_prims,
                                                        const uint64_t* __restrict__ total_ptr, int64_t capacity,
                                                        const uint32_t* __restrict__ big_list,
-                                                       const uint32_t* __restrict__ big_count) {
+                                                       const uint32_t* __restrict__ big_count,
+                                                       const double* __restrict__ keygeo,
+                                                       uint32_t* __restrict__ pair_keys) {
   if ((int64_t)*total_ptr > capacity) return;
   const uint32_t nbig = *big_count;
   const CamDev& cam = views->cam[v];
@@ -677,8 +740,13 @@ __global__ void __launch_bounds__(256) k_duplicate_big(const Views* __restrict__
     const uint32_t j = sorted_prims[i];
     const uint32_t cnt = tile_counts[j];
     const uint32_t off = offsets[i];
+    const double* kg = pair_keys ? keygeo + (int64_t)j * KG_N : nullptr;
     if (opt.cull_mode == 2) {
-      for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) { pair_tiles[off + t] = t; pair_prims[off + t] = j; }
+      for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+        pair_tiles[off + t] = t;
+        pair_prims[off + t] = j;
+        if (kg) pair_keys[off + t] = tile_key(kg, cam, opt, t);
+      }
       continue;
     }
     const uint2 meta = span_meta[j];
@@ -694,10 +762,23 @@ __global__ void __launch_bounds__(256) k_duplicate_big(const Views* __restrict__
       for (uint32_t t = threadIdx.x; t < n_row; t += blockDim.x) {
         pair_tiles[off + w + t] = base + t;
         pair_prims[off + w + t] = j;
+        if (kg) pair_keys[off + w + t] = tile_key(kg, cam, opt, base + t);
       }
       w += n_row;
     }
   }
+}
+
+// Pre-sort key of each sorted pair (inspection): the centre-depth key of its primitive, or the
+// per-tile key recomputed from the key data.
+__global__ void __launch_bounds__(256) k_pair_keys(const Views* __restrict__ views, OptsDev opt, int v,
+                                                   const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ prims,
+                                                   int64_t n, const uint32_t* __restrict__ depth_keys,
+                                                   const double* __restrict__ keygeo, uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t j = prims[i];
+  out[i] = opt.key_mode == 0 ? depth_keys[j] : tile_key(keygeo + (int64_t)j * KG_N, views->cam[v], opt, tiles[i]);
 }
 
 }  // namespace drk
@@ -715,13 +796,13 @@ hipError_t set_views(Views* d_views, const Views& views, hipStream_t s) {
 hipError_t launch_preprocess(const SceneDev& sc, const Views* views, int nv, const OptsDev& opt, float* records,
                              uint32_t* depth_keys, uint32_t* tile_counts, uint32_t* work, uint32_t* work_count,
                              uint2* span_meta, uint32_t* span_rows, uint32_t* rows_used, int64_t row_cap,
-                             uint32_t* status, int64_t stride, hipStream_t s) {
+                             uint32_t* status, int64_t stride, double* keygeo, hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
   dim3 grid((unsigned)((sc.n + 127) / 128), (unsigned)nv);
   hipLaunchKernelGGL(k_preprocess, grid, dim3(128), 0, s, sc, views, opt, depth_keys, tile_counts, work, work_count,
                      status, stride);
   hipLaunchKernelGGL(k_polygon, grid, dim3(128), 0, s, sc, views, opt, records, depth_keys, tile_counts, work,
-                     work_count, span_meta, span_rows, rows_used, row_cap, stride);
+                     work_count, span_meta, span_rows, rows_used, row_cap, stride, keygeo);
   return hipGetLastError();
 }
 
@@ -731,15 +812,26 @@ hipError_t launch_duplicate(const SceneDev& sc, const Views* views, const OptsDe
                             const uint32_t* sorted_prims, const uint32_t* offsets, const uint32_t* tile_counts,
                             const uint2* span_meta, const uint32_t* span_rows, uint32_t* pair_tiles,
                             uint32_t* pair_prims, const uint64_t* total_ptr, int64_t capacity, const uint64_t* n_sorted,
-                            uint32_t* big_list, uint32_t* big_count, hipStream_t s) {
+                            uint32_t* big_list, uint32_t* big_count, const double* keygeo, uint32_t* pair_keys,
+                            hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
   hipError_t e = fill_u32(big_count, 0u, 1, s);
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)((sc.n + 127) / 128));
   hipLaunchKernelGGL(k_duplicate, grid, dim3(128), 0, s, sc, views, opt, v, sorted_prims, offsets, tile_counts,
-                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, n_sorted, big_list, big_count);
+                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, n_sorted, big_list, big_count,
+                     keygeo, pair_keys);
   hipLaunchKernelGGL(k_duplicate_big, dim3(1024), dim3(256), 0, s, views, opt, v, sorted_prims, offsets, tile_counts,
-                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, big_list, big_count);
+                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, big_list, big_count, keygeo,
+                     pair_keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_keys(const Views* views, const OptsDev& opt, int v, const uint32_t* tiles, const uint32_t* prims,
+                            int64_t n, const uint32_t* depth_keys, const double* keygeo, uint32_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, views, opt, v, tiles, prims, n,
+                     depth_keys, keygeo, out);
   return hipGetLastError();
 }
 

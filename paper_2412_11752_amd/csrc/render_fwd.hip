@@ -10,14 +10,18 @@
 
 namespace drk {
 
-template <int K>
+// With TRACE the kernel also records, per pixel, the primitive index and hit depth of its first
+// trace_cap composited contributions (and their count), for the sorting-accuracy measures.
+template <int K, bool TRACE>
 __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp, OptsDev opt,
                                                        float* __restrict__ rgb, float* __restrict__ T_out,
                                                        int32_t* __restrict__ n_emit_out,
                                                        int32_t* __restrict__ consumed_out,
                                                        int32_t* __restrict__ contrib_out,
-                                                       int32_t* __restrict__ work_out) {
+                                                       int32_t* __restrict__ work_out,
+                                                       int32_t* __restrict__ trace_n, int32_t* __restrict__ trace_idx,
+                                                       float* __restrict__ trace_z, int trace_cap) {
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
   __shared__ float4 lds[kBatch * RF4];
@@ -35,6 +39,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + (float)(kTile - 1);
   const float wy0 = (float)(ty * kTile + (tid >> 6) * 4) + 0.5f, wy1 = wy0 + 3.0f;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  const size_t trace_base = TRACE && inside ? ((size_t)y * cam.W + x) * (size_t)trace_cap : 0;
 
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int n_emit = 0, n_contrib = 0, n_hit = 0, n_full = 0;
@@ -80,6 +85,12 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
             C1 = fmaf(w, c[1], C1);
             C2 = fmaf(w, c[2], C2);
             T = test;
+            if constexpr (TRACE) {
+              if (n_emit < trace_cap) {
+                trace_idx[trace_base + n_emit] = (int32_t)__float_as_uint(cache.pay[1][0]);
+                trace_z[trace_base + n_emit] = cache.key[0];
+              }
+            }
             ++n_emit;
           }
           const float x2[2] = {at, __uint_as_float(lidx[i])};
@@ -104,6 +115,12 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
           C1 = fmaf(w, c[1], C1);
           C2 = fmaf(w, c[2], C2);
           T = test;
+          if constexpr (TRACE) {
+            if (n_emit < trace_cap) {
+              trace_idx[trace_base + n_emit] = (int32_t)__float_as_uint(cache.pay[1][s]);
+              trace_z[trace_base + n_emit] = cache.key[s];
+            }
+          }
           ++n_emit;
         }
       }
@@ -121,24 +138,30 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
     contrib_out[pidx] = n_contrib;
     work_out[pidx] = n_hit;                 // entries whose hit was evaluated (wave box passed)
     work_out[plane + pidx] = n_full;        // entries that went through the full kernel
+    if constexpr (TRACE) trace_n[pidx] = n_emit;
   }
 }
 
 template <int K>
 static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, const uint32_t* prims, const CamDev* cam,
                                int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
-                               int32_t* wk, hipStream_t s) {
-  hipLaunchKernelGGL(k_render_fwd<K>, dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt, rgb, T, ne,
-                     cons, nc, wk);
+                               int32_t* wk, int32_t* tn, int32_t* ti, float* tz, int cap, hipStream_t s) {
+  if (tn)
+    hipLaunchKernelGGL((k_render_fwd<K, true>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt, rgb, T,
+                       ne, cons, nc, wk, tn, ti, tz, cap);
+  else
+    hipLaunchKernelGGL((k_render_fwd<K, false>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt, rgb,
+                       T, ne, cons, nc, wk, nullptr, nullptr, nullptr, 0);
   return hipGetLastError();
 }
 
+// trace_n == nullptr: the plain forward; otherwise the traced one (trace arrays of this view).
 hipError_t launch_render_fwd(int K, const float* records, const uint32_t* ranges, const uint32_t* prims,
                              const CamDev* cam, int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
-                             int32_t* nc, int32_t* wk, hipStream_t s) {
+                             int32_t* nc, int32_t* wk, int32_t* tn, int32_t* ti, float* tz, int cap, hipStream_t s) {
   switch (K) {
 #define DRK_CASE(k) \
-  case k: return launch_fwd_k<k>(records, ranges, prims, cam, ntiles, opt, rgb, T, ne, cons, nc, wk, s);
+  case k: return launch_fwd_k<k>(records, ranges, prims, cam, ntiles, opt, rgb, T, ne, cons, nc, wk, tn, ti, tz, cap, s);
     DRK_CASE(3) DRK_CASE(4) DRK_CASE(5) DRK_CASE(6) DRK_CASE(7) DRK_CASE(8) DRK_CASE(9) DRK_CASE(10)
     DRK_CASE(11) DRK_CASE(12) DRK_CASE(13) DRK_CASE(14) DRK_CASE(15) DRK_CASE(16)
 #undef DRK_CASE

@@ -15,7 +15,8 @@ from . import _lib
 from ._lib import DRK_OK, DRK_EOVERFLOW, check, lib
 
 EXPORT = {"depth_keys": 0, "tile_counts": 1, "pair_tiles": 2, "pair_prims": 3, "ranges": 4, "emitted": 5,
-          "consumed": 6, "contributors": 7, "hits": 8, "kernels": 9}
+          "consumed": 6, "contributors": 7, "hits": 8, "kernels": 9, "pair_keys": 10}
+KEY_MODES = {"centre": 0, "centric": 1, "nearest": 2}
 
 
 def _stream_handle(device=None) -> int:
@@ -87,10 +88,12 @@ def camera_struct(cam) -> _lib.Camera:
 
 
 def make_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, near=0.2, lowpass_sl=math.sqrt(0.5),
-              cache_len=8, cull_mode=0, validate=0) -> _lib.Opts:
+              cache_len=8, cull_mode=0, validate=0, key_mode=0) -> _lib.Opts:
+    """key_mode: 0 / "centre", 1 / "centric", 2 / "nearest" (pre-sort key of the tile lists)."""
     o = _lib.Opts()
     o.alpha_min, o.alpha_max, o.T_min, o.near_plane, o.lowpass_sl = alpha_min, alpha_max, T_min, near, lowpass_sl
     o.cache_len, o.cull_mode, o.validate = cache_len, cull_mode, validate
+    o.key_mode = KEY_MODES[key_mode] if isinstance(key_mode, str) else int(key_mode)
     return o
 
 
@@ -150,6 +153,20 @@ class Rasterizer:
             T = torch.empty(npx, dtype=torch.float32, device=dev)
         check(lib().drk_render_fwd(self._ws, _ptr(rgb), _ptr(T), C.c_void_p(_stream_handle())), "drk_render_fwd")
         return rgb, T
+
+    def render_trace(self, cap: int = 64):
+        """Forward render that also records each pixel's composited contributions front to back.
+        Returns rgb (flat), T (flat), trace_n [px], trace_idx [px][cap], trace_z [px][cap]."""
+        npx = sum(int(c.width) * int(c.height) for c in self._cams)
+        dev = self._scene.mu.device
+        rgb = torch.empty(3 * npx, dtype=torch.float32, device=dev)
+        T = torch.empty(npx, dtype=torch.float32, device=dev)
+        tn = torch.empty(npx, dtype=torch.int32, device=dev)
+        ti = torch.full((npx, cap), -1, dtype=torch.int32, device=dev)
+        tz = torch.full((npx, cap), float("nan"), dtype=torch.float32, device=dev)
+        check(lib().drk_render_trace(self._ws, _ptr(rgb), _ptr(T), int(cap), _ptr(tn), _ptr(ti), _ptr(tz),
+                                     C.c_void_p(_stream_handle())), "drk_render_trace")
+        return rgb, T, tn, ti, tz
 
     def render_bwd(self, rgb: torch.Tensor, dL_drgb: torch.Tensor) -> DRKScene:
         sc = self._scene
@@ -229,3 +246,17 @@ class DRKRenderFunction(torch.autograd.Function):
 def render(ras: Rasterizer, scene: DRKScene, cams, opts=None):
     """Differentiable render of the scene tensors (which may require grad)."""
     return DRKRenderFunction.apply(ras, cams, opts, scene.sh_degree, *scene.tensors())
+
+
+def trace_metrics(trace_n: torch.Tensor, trace_z: torch.Tensor, cap: int) -> dict:
+    """Sorting-accuracy measures of traces from ``Rasterizer.render_trace`` (cap <= 64), computed by
+    drk_trace_metrics: accuracy, mean Kendall's tau, MAE of the composited depths against their
+    sorted order, plus the counts they are taken over."""
+    if trace_z.shape[-1] != cap:
+        raise ValueError("trace_z must be [px][cap]")
+    out = torch.empty(6, dtype=torch.float64, device=trace_n.device)
+    check(lib().drk_trace_metrics(_ptr(trace_n.contiguous()), _ptr(trace_z.contiguous()), int(trace_n.numel()),
+                                  int(cap), _ptr(out), C.c_void_p(_stream_handle(trace_n.device))), "drk_trace_metrics")
+    n, ok, tau, npx2, err, trunc = out.cpu().tolist()
+    return dict(accuracy=ok / n if n else float("nan"), kendall_tau=tau / npx2 if npx2 else float("nan"),
+                mae=err / n if n else float("nan"), n=int(n), pixels=int(npx2), truncated=int(trunc))

@@ -22,13 +22,15 @@ def log(msg):
     sys.stdout.flush()
 
 
-def oracle_opts(cache_len=8, lowpass=True, cull_mode=0):
-    return O.Opts(lowpass_sl=math.sqrt(0.5) if lowpass else 0.0, cache_len=cache_len, cull_mode=cull_mode).f32()
+def oracle_opts(cache_len=8, lowpass=True, cull_mode=0, key_mode=0):
+    return O.Opts(lowpass_sl=math.sqrt(0.5) if lowpass else 0.0, cache_len=cache_len, cull_mode=cull_mode,
+                  key_mode=key_mode).f32()
 
 
-def gpu_opts(cache_len=8, lowpass=True, cull_mode=0):
+def gpu_opts(cache_len=8, lowpass=True, cull_mode=0, key_mode=0):
     from paper_2412_11752_amd import make_opts
-    return make_opts(lowpass_sl=math.sqrt(0.5) if lowpass else 0.0, cache_len=cache_len, cull_mode=cull_mode)
+    return make_opts(lowpass_sl=math.sqrt(0.5) if lowpass else 0.0, cache_len=cache_len, cull_mode=cull_mode,
+                     key_mode=key_mode)
 
 
 def oracle_flat_lists(tiles):
