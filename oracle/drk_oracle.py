@@ -330,7 +330,13 @@ def eval_pairs(P: Prims, cam: Cam, opts: Opts, px: torch.Tensor, py: torch.Tenso
         at = alpha
     at = torch.clamp(at, max=opts.alpha_max)
     contrib = ok & (at >= opts.alpha_min)
-    return dict(alpha=at, rt=rt, zc=zc, den=den, ok=ok, contrib=contrib, u=u, v=v, color=colors)
+    # unit normal of the plane in the camera frame (the image of the plane under X -> R X + t),
+    # turned toward the camera: n_c . mu_c < 0
+    a = torch.linalg.cross(tu @ cam.R.T, tv @ cam.R.T)
+    a = a / torch.linalg.vector_norm(a, dim=-1, keepdim=True)
+    side = ((P.mu @ cam.R.T + cam.t) * a).sum(-1)
+    nc = torch.where((side > 0)[:, None], -a, a)
+    return dict(alpha=at, rt=rt, zc=zc, den=den, ok=ok, contrib=contrib, u=u, v=v, color=colors, normal=nc)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -435,6 +441,8 @@ class PixelResult:
     emitted: List[List[int]]  # per pixel, primitive indices actually composited, in order
     weights: List[List[float]]
     emitted_z: List[List[float]]  # per pixel, view depth of the hit of each composited contribution
+    depth: np.ndarray = None  # (P,) sum over composited contributions of T_i alpha_i * view depth of the hit
+    normal: np.ndarray = None  # (P, 3) sum of T_i alpha_i * unit camera-frame normal facing the camera
 
 
 def render_pixels(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, chunk: int = 64,
@@ -462,6 +470,8 @@ def render_pixels(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, chu
         emitted: List[List[int]] = [[] for _ in range(npix)]
         weights: List[List[float]] = [[] for _ in range(npix)]
         emitted_z: List[List[float]] = [[] for _ in range(npix)]
+        out_depth = np.zeros(npix)
+        out_normal = np.zeros((npix, 3))
         bg = cam.bg.numpy()
         for c0 in range(0, npix, chunk):
             cx_ = px_t[c0:c0 + chunk].to(F64)[:, None] + 0.5
@@ -485,8 +495,8 @@ def render_pixels(scene, camera, opts: Opts, px: np.ndarray, py: np.ndarray, chu
             pidx = pl + c0
             res = eval_pairs(P.index(pj), cam, opts, px_t[pidx], py_t[pidx], colors[pj])
             _finish_pixels(res, pidx, pj, akey, opts, bg, out_rgb, out_T, out_n, out_nc, knife, emitted, weights,
-                           emitted_z, c0, min(chunk, npix - c0))
-    return PixelResult(out_rgb, out_T, out_n, out_nc, knife, emitted, weights, emitted_z)
+                           emitted_z, c0, min(chunk, npix - c0), out_depth, out_normal)
+    return PixelResult(out_rgb, out_T, out_n, out_nc, knife, emitted, weights, emitted_z, out_depth, out_normal)
 
 
 def _near(x, thr, rel=1e-6):
@@ -494,7 +504,7 @@ def _near(x, thr, rel=1e-6):
 
 
 def _finish_pixels(res, pidx, pj, akey, opts, bg, out_rgb, out_T, out_n, out_nc, knife, emitted, weights,
-                   emitted_z, c0, cnt):
+                   emitted_z, c0, cnt, out_depth, out_normal):
     contrib = res["contrib"].numpy()
     ok = res["ok"].numpy()
     at = res["alpha"].numpy()
@@ -502,6 +512,7 @@ def _finish_pixels(res, pidx, pj, akey, opts, bg, out_rgb, out_T, out_n, out_nc,
     zc = res["zc"].numpy()
     den = res["den"].numpy()
     col = res["color"].numpy()
+    nrm = res["normal"].numpy()
     pidx = pidx.numpy()
     pj = pj.numpy()
     # knife-edge decisions (value within 1e-6 relative of a threshold)
@@ -546,6 +557,8 @@ def _finish_pixels(res, pidx, pj, akey, opts, bg, out_rgb, out_T, out_n, out_nc,
         emitted[p] = [int(pj[s]) for s in em_s[:n]]
         emitted_z[p] = [float(zc[s]) for s in em_s[:n]]
         weights[p] = w
+        out_depth[p] = sum(wi * zc[s] for wi, s in zip(w, em_s))
+        out_normal[p] = np.sum([wi * nrm[s] for wi, s in zip(w, em_s)], axis=0) if n else 0.0
 
 
 def render_image(scene, camera, opts: Opts, **kw) -> PixelResult:
@@ -1011,3 +1024,114 @@ def sort_metrics(seqs: Sequence[Sequence[float]], cap: Optional[int] = None) -> 
     return dict(accuracy=n_ok / n_el if n_el else float("nan"),
                 kendall_tau=float(np.mean(taus)) if taus else float("nan"),
                 mae=err / n_el if n_el else float("nan"), n=n_el, pixels=len(taus))
+
+
+# ---------------------------------------------------------------------------------------------
+# Mesh to DRK (the section "Converting Mesh to DRK" and its supplement): one DRK per planar convex face,
+# with the basis endpoints at the face's vertices.  Readings: the centre is the mean of the
+# vertices; the plane frame has t_u toward the first vertex and the normal of the face's winding
+# (sum of the cross products of consecutive centred vertices); theta_k are the vertex directions in
+# the listed order (theta_0 = 0); eta = 1, so the L1 level sets (Eq. L1) are the face polygon
+# itself, and s_k = d_k / sqrt(2 ln 2) puts the vertices on the level E = 2 ln 2, where g = 1/2 and
+# Psi(g) = 1/2 for every tau: the half-opacity contour is the face outline, and tau sets how sharp
+# it is.  A face with m < K vertices gets K - m extra endpoints on its edges: edge i (from vertex i
+# to vertex i+1) takes floor((K - m) / m) of them, plus one when i < (K - m) mod m, evenly spaced
+# along it; endpoints on the edges leave the L1 polygon unchanged.
+
+MESH_LEVEL = math.sqrt(2.0 * math.log(2.0))
+
+
+def _quat_from_frame(tu, tv, n):
+    """(w, x, y, z) of the rotation whose columns are t_u, t_v, n (Shepperd's method)."""
+    R = [[tu[0], tv[0], n[0]], [tu[1], tv[1], n[1]], [tu[2], tv[2], n[2]]]
+    t = R[0][0] + R[1][1] + R[2][2]
+    if t > 0.0:
+        r = math.sqrt(1.0 + t)
+        return (0.5 * r, (R[2][1] - R[1][2]) / (2.0 * r), (R[0][2] - R[2][0]) / (2.0 * r), (R[1][0] - R[0][1]) / (2.0 * r))
+    i = max(range(3), key=lambda k: R[k][k])
+    j, k = (i + 1) % 3, (i + 2) % 3
+    r = math.sqrt(1.0 + R[i][i] - R[j][j] - R[k][k])
+    q = [0.0, 0.0, 0.0, 0.0]
+    q[0] = (R[k][j] - R[j][k]) / (2.0 * r)
+    q[1 + i] = 0.5 * r
+    q[1 + j] = (R[j][i] + R[i][j]) / (2.0 * r)
+    q[1 + k] = (R[k][i] + R[i][k]) / (2.0 * r)
+    return tuple(q)
+
+
+def mesh_face_drk(P: np.ndarray, K: int):
+    """One face (m, 3) -> (mu, (t_u, t_v, n), theta[K], s[K]) in float64, or None when the face is
+    degenerate, not convex, or wound the other way round its own normal."""
+    P = np.asarray(P, np.float64)
+    m = len(P)
+    if m < 3 or m > K:
+        return None
+    mu = P.mean(axis=0)
+    D = P - mu
+    a = np.zeros(3)
+    for i in range(m):
+        a += np.cross(D[i], D[(i + 1) % m])
+    na = float(np.linalg.norm(a))
+    d0 = float(np.linalg.norm(D[0]))
+    if not (na > 0.0 and d0 > 0.0):
+        return None
+    n = a / na
+    tu = D[0] / d0
+    tv = np.cross(n, tu)
+    x = [float(D[i] @ tu) for i in range(m)]
+    y = [float(D[i] @ tv) for i in range(m)]
+    ang = [0.0] + [math.atan2(y[i], x[i]) % TWO_PI for i in range(1, m)]
+    # extra endpoints on the edges, round robin from edge 0
+    extra = [(K - m) // m + (1 if i < (K - m) % m else 0) for i in range(m)]
+    xs, ys, th = [], [], []
+    for i in range(m):
+        xa, ya, xb, yb = x[i], y[i], x[(i + 1) % m], y[(i + 1) % m]
+        xs.append(xa)
+        ys.append(ya)
+        th.append(ang[i])
+        for c in range(1, extra[i] + 1):
+            f = c / (extra[i] + 1)
+            px, py = xa + f * (xb - xa), ya + f * (yb - ya)
+            xs.append(px)
+            ys.append(py)
+            th.append(math.atan2(py, px) % TWO_PI)
+    for k in range(1, K):
+        gap = th[k] - th[k - 1]
+        if not (0.0 < gap < math.pi):
+            return None
+    if not (0.0 < th[0] + TWO_PI - th[K - 1] < math.pi):
+        return None
+    s = [math.hypot(xs[k], ys[k]) / MESH_LEVEL for k in range(K)]
+    return mu, (tu, tv, n), th, s
+
+
+def mesh_to_drk(vertices: np.ndarray, faces: np.ndarray, colors: np.ndarray, K: int, tau: float = 0.95,
+                opacity: float = 0.99):
+    """Converts a polygon mesh (vertices (nv, 3); faces (nf, m) vertex indices, -1 padding; RGB per
+    face (nf, 3)) to a DRK scene with K bases (float32 SoA).  Faces that cannot be converted get
+    opacity 0 (culled by the renderer)."""
+    from drk_synth import Scene
+    V = np.asarray(vertices, np.float64)
+    F = np.asarray(faces)
+    nf = F.shape[0]
+    mu = np.zeros((3, nf))
+    q = np.zeros((4, nf))
+    q[0] = 1.0
+    sc = np.ones((K, nf))
+    th = np.tile((np.arange(K) * (TWO_PI / K))[:, None], (1, nf))
+    op = np.zeros(nf)
+    for f in range(nf):
+        idx = [int(i) for i in F[f] if i >= 0]
+        r = mesh_face_drk(V[idx], K)
+        if r is None:
+            continue
+        m_, (tu, tv, n), t_, s_ = r
+        mu[:, f] = m_
+        q[:, f] = _quat_from_frame(tu, tv, n)
+        sc[:, f] = s_
+        th[:, f] = t_
+        op[f] = opacity
+    th32 = np.minimum(th.astype(np.float32), np.nextafter(np.float32(TWO_PI), np.float32(0)))
+    return Scene(mu.astype(np.float32), q.astype(np.float32), sc.astype(np.float32), th32,
+                 np.ones(nf, np.float32), np.full(nf, tau, np.float32), op.astype(np.float32),
+                 np.ascontiguousarray(np.asarray(colors, np.float32).T), -1)

@@ -638,3 +638,92 @@ def test_per_tile_keys_change_order_not_images_of_separated_layers():
         r = O.render_image(sc, cam, O.Opts(cache_len=1, key_mode=mode))
         np.testing.assert_allclose(r.rgb, ref.rgb, atol=1e-12)
         assert O.sort_metrics(r.emitted_z)["accuracy"] == 1.0
+
+
+# ---- Mesh to DRK and the depth / normal channels (section "Converting Mesh to DRK" and supplement)
+def _face_alpha(scene, j, pts_uv):
+    s = scene.scale[:, j].astype(np.float64)
+    th = scene.theta[:, j].astype(np.float64)
+    return _alpha(pts_uv[:, 0], pts_uv[:, 1], s, th, float(scene.eta[j]), float(scene.tau[j]),
+                  float(scene.opacity[j]))
+
+
+def _to_uv(scene, j, P):
+    R = O.quat_to_rotmat(torch.as_tensor(scene.q[:, j].astype(np.float64))).numpy()
+    D = np.asarray(P, np.float64) - scene.mu[:, j].astype(np.float64)
+    return np.stack([D @ R[:, 0], D @ R[:, 1]], -1)
+
+
+@pytest.mark.parametrize("m,K", [(3, 3), (3, 5), (4, 4), (4, 8), (5, 8), (6, 16)])
+def test_mesh_face_outline_is_the_half_opacity_contour(m, K):
+    """Every vertex and every point of every edge of the face sits at alpha = o Psi(1/2) = o / 2; the
+    centre is opaque and points 10% beyond the outline are transparent."""
+    rng = np.random.default_rng(m * 100 + K)
+    ang = np.sort(rng.uniform(0, 2 * math.pi, m))
+    ang = 2 * math.pi * (np.arange(m) + rng.uniform(0.2, 0.8, m)) / m      # convex, gaps < pi
+    rad = rng.uniform(0.5, 1.5, m)
+    # a random plane in 3D
+    R = O.quat_to_rotmat(torch.as_tensor(rng.normal(size=4))).numpy()
+    c = rng.uniform(-1, 1, 3)
+    P = c + (rad * np.cos(ang))[:, None] * R[:, 0] + (rad * np.sin(ang))[:, None] * R[:, 1]
+    sc = O.mesh_to_drk(P, np.arange(m)[None, :], np.array([[0.2, 0.5, 0.9]]), K=K, tau=0.9, opacity=0.8)
+    assert sc.opacity[0] == np.float32(0.8)
+    uv = _to_uv(sc, 0, P)
+    np.testing.assert_allclose(_face_alpha(sc, 0, uv), 0.4, atol=2e-5)
+    t = np.linspace(0.05, 0.95, 7)
+    edges = np.concatenate([uv[i] + t[:, None] * (uv[(i + 1) % m] - uv[i]) for i in range(m)])
+    np.testing.assert_allclose(_face_alpha(sc, 0, edges), 0.4, atol=2e-5)
+    assert _face_alpha(sc, 0, np.zeros((1, 2)))[0] == pytest.approx(0.8, abs=1e-6)
+    # 10% outside: g < 1/2, Psi on its flat first piece; 10% inside: g > (3 - tau)/4, the flat last piece
+    flat = (1 - 0.9) / (1 + 0.9)
+    assert (_face_alpha(sc, 0, 1.1 * edges) <= 0.8 * flat * 0.5).all()
+    assert (_face_alpha(sc, 0, 0.9 * edges) >= 0.8 * 2 * 0.9 / (1 + 0.9)).all()
+    # the frame: the rotation of q has the face normal as its third column
+    Rq = O.quat_to_rotmat(torch.as_tensor(sc.q[:, 0].astype(np.float64))).numpy()
+    nrm = np.cross(P[1] - P[0], P[2] - P[1])
+    np.testing.assert_allclose(Rq[:, 2], nrm / np.linalg.norm(nrm), atol=1e-6)
+
+
+def test_mesh_rejects_degenerate_and_reversed_faces():
+    V = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0], [2, 0, 0], [0.6, 0.4, 0]], float)
+    F = np.array([[0, 1, 2, 3], [0, 1, 4, -1], [0, 1, 5, 2], [0, 3, 2, 1], [0, 1, 2, -1]])
+    sc = O.mesh_to_drk(V, F, np.ones((5, 3)), K=4)
+    # square ok; collinear triangle degenerate; concave quad (gap >= pi at the reflex vertex is
+    # impossible here, but the angles stop increasing); the square listed clockwise is a valid face
+    # of the opposite normal; the triangle is padded to 4 bases
+    assert sc.opacity[0] > 0 and sc.opacity[1] == 0 and sc.opacity[2] == 0 and sc.opacity[3] > 0 and sc.opacity[4] > 0
+    R0 = O.quat_to_rotmat(torch.as_tensor(sc.q[:, 0].astype(np.float64))).numpy()
+    R3 = O.quat_to_rotmat(torch.as_tensor(sc.q[:, 3].astype(np.float64))).numpy()
+    np.testing.assert_allclose(R0[:, 2], -R3[:, 2], atol=1e-6)
+
+
+def test_depth_and_normal_of_a_fronto_parallel_face():
+    """A square face at depth 3 seen head-on: inside, the depth channel is alpha * 3 and the normal
+    channel alpha * (0, 0, -1) (turned toward the camera), with alpha = min(o, 0.99); outside, both
+    are zero."""
+    z = 3.0
+    V = np.array([[-0.5, -0.5, z], [0.5, -0.5, z], [0.5, 0.5, z], [-0.5, 0.5, z]])
+    for F in (np.array([[0, 1, 2, 3]]), np.array([[3, 2, 1, 0]])):
+        sc = O.mesh_to_drk(V, F, np.array([[1.0, 0.5, 0.25]]), K=4, tau=0.98, opacity=0.97)
+        fx, fy, cx, cy = intrinsics_hfov(32, 32, 60.0)
+        cam = Camera(32, 32, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.zeros(3, np.float32),
+                     np.zeros(3, np.float32))
+        r = O.render_image(sc, cam, O.Opts(lowpass_sl=0.0))
+        # pixel (16, 16) is near the centre, pixel (0, 0) far outside
+        c = 16 * 32 + 16
+        a = r.T[c]
+        assert r.depth[c] == pytest.approx((1 - a) * z, rel=1e-9)
+        np.testing.assert_allclose(r.normal[c], [0, 0, -(1 - a)], atol=1e-9)
+        assert 1 - a == pytest.approx(0.97, abs=1e-3)
+        assert r.depth[0] == 0.0 and np.all(r.normal[0] == 0.0)
+
+
+def test_depth_channel_is_the_weighted_sum_of_hit_depths():
+    """depth = sum_i T_i alpha_i Z_i over the composited contributions, normal likewise with unit
+    normals: the weights telescope with the transmittance."""
+    scene, cam = config_c1()
+    r = O.render_image(scene, cam, O.Opts())
+    for p in np.nonzero(r.n_emit > 2)[0][:50]:
+        assert r.depth[p] == pytest.approx(sum(w * z for w, z in zip(r.weights[p], r.emitted_z[p])), rel=1e-12)
+        assert np.linalg.norm(r.normal[p]) <= sum(r.weights[p]) + 1e-12
+        assert sum(r.weights[p]) + r.T[p] == pytest.approx(1.0, abs=1e-12)
