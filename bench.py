@@ -209,6 +209,66 @@ def sortacc_phase(args, ras, ds, frames, W, H, rgb, T):
     return out
 
 
+def mesh_phase(args, W, H):
+    """Mesh to DRK (section "Converting Mesh to DRK"): a 917k-face scene of 64 randomly placed
+    icospheres (20480 triangles) and tori (8192 quads) converted on the GPU with K = 4, then rendered
+    at W x H with the depth and normal channels, for each pre-sort key; plus the sorting accuracy of
+    each key on it (traced, first 64 composited contributions per pixel)."""
+    import torch
+    from drk_synth import camera_lookat, mesh_scene
+    from paper_2412_11752_amd import Rasterizer, make_opts, mesh_to_drk, trace_metrics
+    V, F, C = mesh_scene(5, n_instances=64, ico_level=5, torus=(128, 64), half=3.0)
+    v = torch.as_tensor(np.ascontiguousarray(V.T, np.float32), device="cuda")
+    f = torch.as_tensor(np.ascontiguousarray(F, np.int32), device="cuda")
+    c = torch.as_tensor(np.ascontiguousarray(C.T), device="cuda")
+    ds, rej = mesh_to_drk(v, f, c, 4, 0.95, 0.99)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        ds, rej = mesh_to_drk(v, f, c, 4, 0.95, 0.99)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out = {"scene": f"{F.shape[0]} faces (64 icospheres of 20480 triangles and tori of 8192 quads in a 6-unit box), K=4",
+           "convert_ms": round(e0.elapsed_time(e1) / 10, 4), "rejected": rej, "render": {}, "sortacc": {}}
+    log(f"mesh: {F.shape[0]} faces converted in {out['convert_ms']:.3f} ms ({rej} rejected)")
+    cams = [camera_lookat((9.0 * math.cos(a), 1.5, 9.0 * math.sin(a)), (0, 0, 0), (0, 1, 0), W, H, 60.0)
+            for a in np.linspace(0, 2 * math.pi, args.warmup + args.steps, endpoint=False)]
+    ras = Rasterizer(ds.n, 4, W, H, pair_capacity=1 << 25)
+    names = {0: "centre", 1: "centric", 2: "nearest"}
+    for mode in (0, 1, 2):
+        opts = make_opts(key_mode=mode)
+        for i in range(args.warmup):
+            ras.preprocess(ds, [cams[i]], opts)
+            ras.bin_sort()
+            ras.render_depth_normal()
+        code, need = ras.status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ras.preprocess(ds, [cams[args.warmup + i]], opts)
+            ras.bin_sort()
+            ras.render_depth_normal()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        code, need = ras.status()
+        out["render"][names[mode]] = {"mpix_s": round(args.steps * W * H / dt / 1e6, 2), "pairs": need,
+                                      "status": int(code)}
+        row = {}
+        for L in (1, 8):
+            ras.preprocess(ds, [cams[args.warmup]], make_opts(key_mode=mode, cache_len=L))
+            ras.bin_sort()
+            _, _, tn, ti, tz = ras.render_trace(64)
+            m = trace_metrics(tn, tz, 64)
+            row[str(L)] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in m.items()}
+            del tn, ti, tz
+        out["sortacc"][names[mode]] = row
+        log(f"mesh {names[mode]}: {out['render'][names[mode]]}, L=1 acc {row['1']['accuracy']:.3f} tau "
+            f"{row['1']['kendall_tau']:.4f}, L=8 acc {row['8']['accuracy']:.3f} tau {row['8']['kendall_tau']:.4f}")
+    ras.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,7 +278,7 @@ def main():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--phases", default="fwd,serve",
-                    help="fwd, fwdbwd (backward switched off), serve, ksweep, sortacc")
+                    help="fwd, fwdbwd (backward switched off), serve, ksweep, sortacc, mesh")
     ap.add_argument("--ksweep", default="3,5,8,16", help="radial basis counts of the ksweep phase")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the Poisson arrival trace")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
@@ -327,6 +387,10 @@ def main():
     ksweep = None
     if "ksweep" in phases:
         ksweep = ksweep_phase(args, opts, W, H)
+    mesh = None
+    if "mesh" in phases:
+        mesh = mesh_phase(args, W, H)
+        torch.cuda.empty_cache()
     serve = None
     if "serve" in phases and not args.profile:
         serve = serve_phase(args, opts)
@@ -354,6 +418,8 @@ def main():
         line["ksweep"] = ksweep
     if sortacc is not None:
         line["sortacc"] = sortacc
+    if mesh is not None:
+        line["mesh"] = mesh
     if "fwdbwd" in result:
         line["ms_breakdown"]["render_bwd"] = round(float(result["fwdbwd"]["ms"][:, 3].mean()), 4)
     print(json.dumps(line), flush=True)

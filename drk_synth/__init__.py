@@ -10,3 +10,4 @@ from .scenes import (  # noqa: F401
     scene_clusters, config_c1, config_c2, config_c3, config_c4_scenes,
     config_c5, c3_camera_path, random_target,
 )
+from .meshes import mesh_icosphere, mesh_scene, mesh_torus  # noqa: F401,E402

@@ -69,6 +69,19 @@ typedef struct drk_scene {
   const float* color;
 } drk_scene;
 
+/* Writable scene arrays (device, caller-allocated), the layout of drk_scene with RGB colour
+ * [3][n]: the output of drk_mesh_to_drk.                                                      */
+typedef struct drk_scene_out {
+  float* mu;
+  float* q;
+  float* scale;
+  float* theta;
+  float* eta;
+  float* tau;
+  float* opacity;
+  float* color;
+} drk_scene_out;
+
 /* Gradient buffers: same shapes as drk_scene's arrays (device, caller-allocated, overwritten). */
 typedef struct drk_scene_grad {
   float* mu;
@@ -170,6 +183,31 @@ drk_status drk_render_trace(drk_ws* ws, float* rgb, float* T_final, int32_t cap,
  * so the last bits, may vary between calls).                                                  */
 drk_status drk_trace_metrics(const int32_t* trace_n, const float* trace_z, int64_t npx, int32_t cap, double* out,
                              void* stream);
+
+/* drk_render_fwd that also writes the depth and normal channels (supplement, mesh conversion:
+ * rendered depth and normal images), blended with the colour's weights T_i alpha_i (Eq. 1):
+ *   depth  [V][H][W]     float32 output: sum of T_i alpha_i * view depth of the hit
+ *   normal [V][3][H][W]  float32 output: sum of T_i alpha_i * unit camera-frame normal of the
+ *                        primitive's plane, turned toward the camera
+ * Divide by 1 - T_final for the expected depth and normal of the covered part.                */
+drk_status drk_render_depth_normal(drk_ws* ws, float* rgb, float* T_final, float* depth, float* normal,
+                                   void* stream);
+
+/* Mesh to DRK (section "Converting Mesh to DRK" and its supplement): one DRK per planar convex
+ * face, with the basis endpoints at the face's vertices, without any optimisation.
+ *   vertices [3][nv] float32 (device)      faces [nf][m] int32 vertex indices (device), -1 pads
+ *   face_rgb [3][nf] float32 (device)      K: bases per DRK, 3 <= K <= 16, m <= K
+ * Per face (float64): centre = mean of the vertices; t_u toward the first vertex; normal from the
+ * face's winding; theta_k = the vertex directions in the listed order (theta_0 = 0); faces with
+ * fewer than K vertices get endpoints evenly spaced along their edges (edge i takes
+ * floor((K-m')/m') of them, one more when i < (K-m') mod m'); s_k = distance / sqrt(2 ln 2), so the
+ * face outline is the alpha = o/2 contour; eta = 1 (straight L1 edges), the given tau and opacity,
+ * the face's RGB colour.  A face that is degenerate, not convex, has an index outside [0, nv) or
+ * a sector of pi or more gets opacity 0 (never rendered) and is counted in *rejected (device
+ * uint32, may be NULL; overwritten).                                                           */
+drk_status drk_mesh_to_drk(const float* vertices, int64_t nv, const int32_t* faces, int64_t nf, int32_t m,
+                           const float* face_rgb, int32_t K, float tau, float opacity, const drk_scene_out* out,
+                           uint32_t* rejected, void* stream);
 
 /* Step 4 (supplement S4: backward front to back, consistent with cache sorting).  Recomputes
  * each pixel's emission sequence and accumulates dL/dparameter for every primitive:

@@ -1108,10 +1108,11 @@ def mesh_face_drk(P: np.ndarray, K: int):
 def mesh_to_drk(vertices: np.ndarray, faces: np.ndarray, colors: np.ndarray, K: int, tau: float = 0.95,
                 opacity: float = 0.99):
     """Converts a polygon mesh (vertices (nv, 3); faces (nf, m) vertex indices, -1 padding; RGB per
-    face (nf, 3)) to a DRK scene with K bases (float32 SoA).  Faces that cannot be converted get
-    opacity 0 (culled by the renderer)."""
+    face (nf, 3)) to a DRK scene with K bases (float32 SoA).  Vertices are taken in float32 (as the
+    ABI carries them) and promoted exactly.  Faces that cannot be converted get opacity 0 (culled by
+    the renderer)."""
     from drk_synth import Scene
-    V = np.asarray(vertices, np.float64)
+    V = np.asarray(vertices, np.float32).astype(np.float64)
     F = np.asarray(faces)
     nf = F.shape[0]
     mu = np.zeros((3, nf))

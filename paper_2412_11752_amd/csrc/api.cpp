@@ -47,8 +47,10 @@ hipError_t tile_ranges(const uint32_t*, const uint64_t*, uint32_t*, int, hipStre
 hipError_t set_u64(uint64_t*, uint64_t, hipStream_t);
 hipError_t fill_u32(uint32_t*, uint32_t, int64_t, hipStream_t);
 hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
-                             float*, float*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, float*, int,
+                             float*, float*, int32_t*, int32_t*, int32_t*, int32_t*, int, void*, int32_t*, float*, int,
                              hipStream_t);
+hipError_t launch_mesh_to_drk(const float*, int64_t, const int32_t*, int64_t, int, const float*, int, float, float,
+                              const drk_scene_out&, uint32_t*, hipStream_t);
 hipError_t launch_render_bwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
                              const float*, const float*, float*, int64_t, hipStream_t);
 hipError_t launch_preprocess_bwd(const SceneDev&, const Views*, const OptsDev&, const uint32_t*, const float*, int64_t,
@@ -462,8 +464,9 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
 
 namespace {
 
-drk_status render_views(drk_ws* ws, float* rgb, float* T_final, int32_t cap, int32_t* trace_n, int32_t* trace_idx,
-                        float* trace_z, hipStream_t s) {
+// mode 0 colour, 1 trace (a0 = counts, a1 = indices, a2 = depths), 2 depth (a0) and normal (a2).
+drk_status render_views(drk_ws* ws, float* rgb, float* T_final, int mode, int32_t cap, void* a0, int32_t* a1,
+                        float* a2, hipStream_t s) {
   size_t off = 0;
   const size_t px_max = (size_t)ws->max_w * ws->max_h;
   for (int v = 0; v < ws->views.nv; ++v) {
@@ -474,10 +477,12 @@ drk_status render_views(drk_ws* ws, float* rgb, float* T_final, int32_t cap, int
                           ws->pair_prims + (size_t)v * ws->cap, &ws->views_dev->cam[v], cam.tiles_x * cam.tiles_y,
                           ws->opts, rgb + 3 * off,
                           T_final ? T_final + off : nullptr, ws->n_emit + v * px_max, ws->consumed + v * px_max,
-                          ws->contrib + v * px_max, ws->work_px + 2 * v * px_max,
-                          trace_n ? trace_n + off : nullptr, trace_n ? trace_idx + off * cap : nullptr,
-                          trace_n ? trace_z + off * cap : nullptr, cap, s),
-        trace_n ? "render_trace" : "render_fwd");
+                          ws->contrib + v * px_max, ws->work_px + 2 * v * px_max, mode,
+                          mode == 1 ? (void*)(static_cast<int32_t*>(a0) + off)
+                                    : (mode == 2 ? (void*)(static_cast<float*>(a0) + off) : nullptr),
+                          mode == 1 ? a1 + off * cap : nullptr,
+                          mode == 1 ? a2 + off * cap : (mode == 2 ? a2 + 3 * off : nullptr), cap, s),
+        mode == 1 ? "render_trace" : (mode == 2 ? "render_depth_normal" : "render_fwd"));
     if (st) return st;
     off += npx;
   }
@@ -489,7 +494,34 @@ drk_status render_views(drk_ws* ws, float* rgb, float* T_final, int32_t cap, int
 drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream) {
   if (!ws || !rgb) { set_error("null argument"); return DRK_EINVAL; }
   if (!ws->have_bins) { set_error("drk_render_fwd before drk_bin_sort"); return DRK_EINVAL; }
-  return render_views(ws, rgb, T_final, 0, nullptr, nullptr, nullptr, reinterpret_cast<hipStream_t>(stream));
+  return render_views(ws, rgb, T_final, 0, 0, nullptr, nullptr, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+drk_status drk_render_depth_normal(drk_ws* ws, float* rgb, float* T_final, float* depth, float* normal, void* stream) {
+  if (!ws || !rgb || !depth || !normal) { set_error("null argument"); return DRK_EINVAL; }
+  if (!ws->have_bins) { set_error("drk_render_depth_normal before drk_bin_sort"); return DRK_EINVAL; }
+  return render_views(ws, rgb, T_final, 2, 0, depth, nullptr, normal, reinterpret_cast<hipStream_t>(stream));
+}
+
+drk_status drk_mesh_to_drk(const float* vertices, int64_t nv, const int32_t* faces, int64_t nf, int32_t m,
+                           const float* face_rgb, int32_t K, float tau, float opacity, const drk_scene_out* out,
+                           uint32_t* rejected, void* stream) {
+  if (!out || (nf > 0 && (!vertices || !faces || !face_rgb || !out->mu || !out->q || !out->scale || !out->theta ||
+                          !out->eta || !out->tau || !out->opacity || !out->color))) {
+    set_error("null argument");
+    return DRK_EINVAL;
+  }
+  if (nv < 0 || nf < 0 || nv > 0x7FFFFFFF || K < 3 || K > kMaxK || m < 3 || m > K) {
+    set_error("mesh sizes out of range (need 3 <= m <= K <= %d, 0 <= nv < 2^31)", kMaxK);
+    return DRK_EINVAL;
+  }
+  if (!(tau > -1.0f && tau < 1.0f) || !(opacity > 0.0f && opacity <= 1.0f)) {
+    set_error("tau must be in (-1, 1) and opacity in (0, 1]");
+    return DRK_EINVAL;
+  }
+  return check_hip(launch_mesh_to_drk(vertices, nv, faces, nf, m, face_rgb, K, tau, opacity, *out, rejected,
+                                      reinterpret_cast<hipStream_t>(stream)),
+                   "mesh_to_drk");
 }
 
 drk_status drk_render_trace(drk_ws* ws, float* rgb, float* T_final, int32_t cap, int32_t* trace_n,
@@ -497,7 +529,7 @@ drk_status drk_render_trace(drk_ws* ws, float* rgb, float* T_final, int32_t cap,
   if (!ws || !rgb || !trace_n || !trace_idx || !trace_z) { set_error("null argument"); return DRK_EINVAL; }
   if (!ws->have_bins) { set_error("drk_render_trace before drk_bin_sort"); return DRK_EINVAL; }
   if (cap < 1 || cap > 1024) { set_error("trace cap %d outside [1, 1024]", cap); return DRK_EINVAL; }
-  return render_views(ws, rgb, T_final, cap, trace_n, trace_idx, trace_z, reinterpret_cast<hipStream_t>(stream));
+  return render_views(ws, rgb, T_final, 1, cap, trace_n, trace_idx, trace_z, reinterpret_cast<hipStream_t>(stream));
 }
 
 drk_status drk_trace_metrics(const int32_t* trace_n, const float* trace_z, int64_t npx, int32_t cap, double* out,

@@ -40,7 +40,8 @@ enum RecField : int {
   R_LPCUT = 27,               // d^2 |r_d|^2 / W^2 beyond which the low-pass term < alpha_min
   R_BOX = 28,                 // 4 entries: pixel-space box (x0, x1, y0, y1) of the support polygon
   R_ETHR = 32,                // energy beyond which alpha < alpha_min, with margin (c^2 (1 + 1e-3) + 1e-2)
-  R_SEC = 36,                 // per-sector arrays follow, each K long (33..35 unused, 16-byte alignment)
+  R_NRM = 33,                 // 3 entries: unit camera-frame plane normal, turned toward the camera
+  R_SEC = 36,                 // per-sector arrays follow, each K long (16-byte alignment)
 };
 // Per-sector arrays (offset R_SEC + field * K + k):
 enum SecField : int {

@@ -472,7 +472,12 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
   // alpha = o Psi(exp(-E/2)) is decreasing in E and equals alpha_min at E = c^2; the margin keeps
   // the raster's float32 test conservative against the rounding of exp and Psi
   rec[R_ETHR] = (float)(g.c * g.c * 1.001 + 1e-2);
-  rec[R_ETHR + 1] = rec[R_ETHR + 2] = rec[R_ETHR + 3] = 0.0f;
+  {
+    // unit normal of the plane, turned toward the camera (n . mu_c < 0), for the normal channel
+    const double na = sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]);
+    const double sgn = dN > 0.0 ? -1.0 : 1.0;
+    for (int i = 0; i < 3; ++i) rec[R_NRM + i] = (float)(sgn * a2[i] / na);
+  }
   rec[R_BOX + 0] = (float)(box[0] - 0.01);
   rec[R_BOX + 1] = (float)(box[1] + 0.01);
   rec[R_BOX + 2] = (float)(box[2] - 0.01);

@@ -10,9 +10,14 @@
 
 namespace drk {
 
-// With TRACE the kernel also records, per pixel, the primitive index and hit depth of its first
-// trace_cap composited contributions (and their count), for the sorting-accuracy measures.
-template <int K, bool TRACE>
+// Output variants: MODE 0 colour only; MODE 1 (trace) also records, per pixel, the primitive index
+// and hit depth of its first trace_cap composited contributions (and their count), for the
+// sorting-accuracy measures; MODE 2 also blends the hit depth and the plane normal with the
+// colour's weights into the depth and normal channels (aux0 = trace_n or depth, aux1 = trace_idx,
+// aux2 = trace_z or normal).
+constexpr int kFwdPlain = 0, kFwdTrace = 1, kFwdDepthNormal = 2;
+
+template <int K, int MODE>
 __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp, OptsDev opt,
                                                        float* __restrict__ rgb, float* __restrict__ T_out,
@@ -20,8 +25,13 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
                                                        int32_t* __restrict__ consumed_out,
                                                        int32_t* __restrict__ contrib_out,
                                                        int32_t* __restrict__ work_out,
-                                                       int32_t* __restrict__ trace_n, int32_t* __restrict__ trace_idx,
-                                                       float* __restrict__ trace_z, int trace_cap) {
+                                                       void* __restrict__ aux0, int32_t* __restrict__ aux1,
+                                                       float* __restrict__ aux2, int trace_cap) {
+  constexpr bool TRACE = MODE == kFwdTrace;
+  constexpr bool GEOM = MODE == kFwdDepthNormal;
+  int32_t* trace_n = TRACE ? static_cast<int32_t*>(aux0) : nullptr;
+  int32_t* trace_idx = aux1;
+  float* trace_z = aux2;
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
   __shared__ float4 lds[kBatch * RF4];
@@ -42,6 +52,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   const size_t trace_base = TRACE && inside ? ((size_t)y * cam.W + x) * (size_t)trace_cap : 0;
 
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  float Dz = 0.0f, N0 = 0.0f, N1 = 0.0f, N2 = 0.0f;   // depth / normal channels (MODE 2)
   int n_emit = 0, n_contrib = 0, n_hit = 0, n_full = 0;
   int consumed = (int)(end - start);
   bool done = !inside;
@@ -91,6 +102,13 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
                 trace_z[trace_base + n_emit] = cache.key[0];
               }
             }
+            if constexpr (GEOM) {
+              const float* nr = c - R_RGB + R_NRM;
+              Dz = fmaf(w, cache.key[0], Dz);
+              N0 = fmaf(w, nr[0], N0);
+              N1 = fmaf(w, nr[1], N1);
+              N2 = fmaf(w, nr[2], N2);
+            }
             ++n_emit;
           }
           const float x2[2] = {at, __uint_as_float(lidx[i])};
@@ -121,6 +139,13 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
               trace_z[trace_base + n_emit] = cache.key[s];
             }
           }
+          if constexpr (GEOM) {
+            const float* nr = c - R_RGB + R_NRM;
+            Dz = fmaf(w, cache.key[s], Dz);
+            N0 = fmaf(w, nr[0], N0);
+            N1 = fmaf(w, nr[1], N1);
+            N2 = fmaf(w, nr[2], N2);
+          }
           ++n_emit;
         }
       }
@@ -139,29 +164,39 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
     work_out[pidx] = n_hit;                 // entries whose hit was evaluated (wave box passed)
     work_out[plane + pidx] = n_full;        // entries that went through the full kernel
     if constexpr (TRACE) trace_n[pidx] = n_emit;
+    if constexpr (GEOM) {
+      static_cast<float*>(aux0)[pidx] = Dz;
+      aux2[pidx] = N0;
+      aux2[plane + pidx] = N1;
+      aux2[2 * plane + pidx] = N2;
+    }
   }
 }
 
 template <int K>
 static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, const uint32_t* prims, const CamDev* cam,
                                int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
-                               int32_t* wk, int32_t* tn, int32_t* ti, float* tz, int cap, hipStream_t s) {
-  if (tn)
-    hipLaunchKernelGGL((k_render_fwd<K, true>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt, rgb, T,
-                       ne, cons, nc, wk, tn, ti, tz, cap);
+                               int32_t* wk, int mode, void* a0, int32_t* a1, float* a2, int cap, hipStream_t s) {
+  if (mode == kFwdTrace)
+    hipLaunchKernelGGL((k_render_fwd<K, kFwdTrace>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt,
+                       rgb, T, ne, cons, nc, wk, a0, a1, a2, cap);
+  else if (mode == kFwdDepthNormal)
+    hipLaunchKernelGGL((k_render_fwd<K, kFwdDepthNormal>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam,
+                       opt, rgb, T, ne, cons, nc, wk, a0, nullptr, a2, 0);
   else
-    hipLaunchKernelGGL((k_render_fwd<K, false>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt, rgb,
-                       T, ne, cons, nc, wk, nullptr, nullptr, nullptr, 0);
+    hipLaunchKernelGGL((k_render_fwd<K, kFwdPlain>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt,
+                       rgb, T, ne, cons, nc, wk, nullptr, nullptr, nullptr, 0);
   return hipGetLastError();
 }
 
-// trace_n == nullptr: the plain forward; otherwise the traced one (trace arrays of this view).
+// mode 0: colour only; 1: trace (a0 = counts, a1 = indices, a2 = depths, cap entries per pixel);
+// 2: depth (a0) and normal (a2) channels.  Pointers are those of this view.
 hipError_t launch_render_fwd(int K, const float* records, const uint32_t* ranges, const uint32_t* prims,
                              const CamDev* cam, int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
-                             int32_t* nc, int32_t* wk, int32_t* tn, int32_t* ti, float* tz, int cap, hipStream_t s) {
+                             int32_t* nc, int32_t* wk, int mode, void* a0, int32_t* a1, float* a2, int cap, hipStream_t s) {
   switch (K) {
 #define DRK_CASE(k) \
-  case k: return launch_fwd_k<k>(records, ranges, prims, cam, ntiles, opt, rgb, T, ne, cons, nc, wk, tn, ti, tz, cap, s);
+  case k: return launch_fwd_k<k>(records, ranges, prims, cam, ntiles, opt, rgb, T, ne, cons, nc, wk, mode, a0, a1, a2, cap, s);
     DRK_CASE(3) DRK_CASE(4) DRK_CASE(5) DRK_CASE(6) DRK_CASE(7) DRK_CASE(8) DRK_CASE(9) DRK_CASE(10)
     DRK_CASE(11) DRK_CASE(12) DRK_CASE(13) DRK_CASE(14) DRK_CASE(15) DRK_CASE(16)
 #undef DRK_CASE

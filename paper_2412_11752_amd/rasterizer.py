@@ -168,6 +168,19 @@ class Rasterizer:
                                      C.c_void_p(_stream_handle())), "drk_render_trace")
         return rgb, T, tn, ti, tz
 
+    def render_depth_normal(self):
+        """Forward render with the depth [px] and normal [3][px] channels (flat, views packed).
+        Returns rgb, T, depth, normal."""
+        npx = sum(int(c.width) * int(c.height) for c in self._cams)
+        dev = self._scene.mu.device
+        rgb = torch.empty(3 * npx, dtype=torch.float32, device=dev)
+        T = torch.empty(npx, dtype=torch.float32, device=dev)
+        depth = torch.empty(npx, dtype=torch.float32, device=dev)
+        normal = torch.empty(3 * npx, dtype=torch.float32, device=dev)
+        check(lib().drk_render_depth_normal(self._ws, _ptr(rgb), _ptr(T), _ptr(depth), _ptr(normal),
+                                            C.c_void_p(_stream_handle())), "drk_render_depth_normal")
+        return rgb, T, depth, normal
+
     def render_bwd(self, rgb: torch.Tensor, dL_drgb: torch.Tensor) -> DRKScene:
         sc = self._scene
         g = DRKScene(*[torch.empty_like(t) for t in sc.tensors()], sh_degree=sc.sh_degree)
@@ -260,3 +273,24 @@ def trace_metrics(trace_n: torch.Tensor, trace_z: torch.Tensor, cap: int) -> dic
     n, ok, tau, npx2, err, trunc = out.cpu().tolist()
     return dict(accuracy=ok / n if n else float("nan"), kendall_tau=tau / npx2 if npx2 else float("nan"),
                 mae=err / n if n else float("nan"), n=int(n), pixels=int(npx2), truncated=int(trunc))
+
+
+def mesh_to_drk(vertices: torch.Tensor, faces: torch.Tensor, face_rgb: torch.Tensor, K: int, tau: float = 0.95,
+                opacity: float = 0.99):
+    """Converts a polygon mesh on the GPU to a DRK scene (drk_mesh_to_drk): vertices [3][nv] float32,
+    faces [nf][m] int32 (-1 pads short faces), face_rgb [3][nf] float32, all CUDA tensors.
+    Returns (DRKScene with RGB colour, number of rejected faces)."""
+    for name, t, dt in (("vertices", vertices, torch.float32), ("faces", faces, torch.int32),
+                        ("face_rgb", face_rgb, torch.float32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt} CUDA tensor")
+    nv, (nf, m) = int(vertices.shape[1]), faces.shape
+    dev = vertices.device
+    f32 = lambda *shape: torch.empty(*shape, dtype=torch.float32, device=dev)
+    sc = DRKScene(f32(3, nf), f32(4, nf), f32(K, nf), f32(K, nf), f32(nf), f32(nf), f32(nf), f32(3, nf), -1)
+    out = _lib.SceneOut(*[t.data_ptr() for t in sc.tensors()])
+    rej = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(lib().drk_mesh_to_drk(_ptr(vertices), nv, _ptr(faces), int(nf), int(m), _ptr(face_rgb), int(K),
+                                float(tau), float(opacity), C.byref(out), _ptr(rej), C.c_void_p(_stream_handle(dev))),
+          "drk_mesh_to_drk")
+    return sc, int(rej.item())
