@@ -1136,3 +1136,46 @@ def mesh_to_drk(vertices: np.ndarray, faces: np.ndarray, colors: np.ndarray, K: 
     return Scene(mu.astype(np.float32), q.astype(np.float32), sc.astype(np.float32), th32,
                  np.ones(nf, np.float32), np.full(nf, tau, np.float32), op.astype(np.float32),
                  np.ascontiguousarray(np.asarray(colors, np.float32).T), -1)
+
+
+# ---------------------------------------------------------------------------------------------
+# Parametrization and the optimizer step (supplement S4, Parametrization and Model Training).
+# Raw (unconstrained) parameters map to the renderer's: o = sigmoid, s_k = exp, q normalised,
+# tau = -0.1 + 1.09 sigmoid (the range (-0.1, 0.99)), eta = sigmoid, colour and centre unchanged.
+# Angles (reading): the K sector gaps are proportional to a_k = sigmoid(raw_k) + 1/(K - 2) and sum to
+# 2 pi; theta_k is their cumulative sum before k (theta_0 = 0; q carries the kernel's rotation).
+# Since a_k lies in (1/(K-2), 1 + 1/(K-2)), every gap is below (1 + 1/(K-2)) / (1 + 1/(K-2) +
+# (K-1)/(K-2)) = 1/2 of the turn: the residual is what keeps the sectors under pi.
+
+TAU_LO, TAU_SPAN = -0.1, 1.09
+
+
+def activate(raw: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
+    """Raw parameters (float64 tensors, keys mu, q [N, 4], scale / theta [N, K], eta, tau,
+    opacity [N], color) -> activated parameters, differentiably."""
+    K = raw["theta"].shape[-1]
+    a = torch.sigmoid(raw["theta"]) + 1.0 / (K - 2)
+    gaps = TWO_PI * a / a.sum(-1, keepdim=True)
+    theta = torch.cumsum(gaps, -1) - gaps
+    return {"mu": raw["mu"], "q": raw["q"] / torch.linalg.vector_norm(raw["q"], dim=-1, keepdim=True),
+            "scale": torch.exp(raw["scale"]), "theta": theta, "eta": torch.sigmoid(raw["eta"]),
+            "tau": TAU_LO + TAU_SPAN * torch.sigmoid(raw["tau"]), "opacity": torch.sigmoid(raw["opacity"]),
+            "color": raw["color"]}
+
+
+def activate_vjp(raw: Dict[str, torch.Tensor], g_act: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
+    """Gradient with respect to the raw parameters of sum(g_act * activate(raw)) (float64 autograd)."""
+    leaves = {k: v.detach().clone().requires_grad_(True) for k, v in raw.items()}
+    act = activate(leaves)
+    total = sum((act[k] * g_act[k]).sum() for k in act)
+    total.backward()
+    return {k: v.grad.detach() for k, v in leaves.items()}
+
+
+def adam_step(p, m, v, g, lr, beta1, beta2, eps, step):
+    """One Adam update (Kingma and Ba), bias-corrected, step >= 1; returns (p, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** step)
+    vh = v / (1.0 - beta2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -727,3 +727,77 @@ def test_depth_channel_is_the_weighted_sum_of_hit_depths():
         assert r.depth[p] == pytest.approx(sum(w * z for w, z in zip(r.weights[p], r.emitted_z[p])), rel=1e-12)
         assert np.linalg.norm(r.normal[p]) <= sum(r.weights[p]) + 1e-12
         assert sum(r.weights[p]) + r.T[p] == pytest.approx(1.0, abs=1e-12)
+
+
+# ---- Parametrization and Adam (supplement S4)
+def _raw(n, K, seed, spread=3.0):
+    rng = np.random.default_rng(seed)
+    return {"mu": torch.as_tensor(rng.normal(size=(n, 3))), "q": torch.as_tensor(rng.normal(size=(n, 4))),
+            "scale": torch.as_tensor(rng.normal(-2, 1, (n, K))), "theta": torch.as_tensor(rng.normal(0, spread, (n, K))),
+            "eta": torch.as_tensor(rng.normal(size=n)), "tau": torch.as_tensor(rng.normal(size=n)),
+            "opacity": torch.as_tensor(rng.normal(size=n)), "color": torch.as_tensor(rng.normal(size=(n, 48)))}
+
+
+def test_activation_closed_forms():
+    K = 8
+    raw = {k: torch.zeros_like(v) for k, v in _raw(3, K, 0).items()}
+    raw["q"][:, 0] = 2.0
+    a = O.activate(raw)
+    np.testing.assert_allclose(a["opacity"].numpy(), 0.5)
+    np.testing.assert_allclose(a["eta"].numpy(), 0.5)
+    np.testing.assert_allclose(a["tau"].numpy(), -0.1 + 1.09 * 0.5)
+    np.testing.assert_allclose(a["scale"].numpy(), 1.0)
+    np.testing.assert_allclose(a["q"].numpy(), np.tile([1.0, 0, 0, 0], (3, 1)))
+    # equal raw angles: K equal sectors starting at 0
+    np.testing.assert_allclose(a["theta"].numpy(), np.tile(2 * math.pi * np.arange(K) / K, (3, 1)), atol=1e-15)
+    # tau's range: (-0.1, 0.99)
+    t = O.activate({**raw, "tau": torch.tensor([-50.0, 50.0, 0.0])})["tau"].numpy()
+    assert t[0] == pytest.approx(-0.1, abs=1e-12) and t[1] == pytest.approx(0.99, abs=1e-12)
+
+
+@pytest.mark.parametrize("K", [3, 5, 8, 16])
+def test_activated_angles_are_valid_for_any_raw_values(K):
+    """theta_0 = 0, increasing, every gap (wrap included) below pi for raw values whose sigmoids do
+    not round to 0 or 1.  The supremum of the largest gap is exactly pi for every K, reached only as
+    one sigmoid -> 1 and the others -> 0: (1 + 1/(K-2)) / (1 + K/(K-2)) = 1/2 of the turn."""
+    for spread in (1.0, 5.0):
+        th = O.activate(_raw(500, K, K, spread))["theta"].numpy()
+        gaps = np.diff(np.concatenate([th, np.full((th.shape[0], 1), 2 * math.pi)], 1), axis=1)
+        assert (th[:, 0] == 0).all() and (gaps > 0).all() and (gaps < math.pi).all()
+    raw = {k: v[:1] for k, v in _raw(1, K, 1).items()}
+    raw["theta"] = torch.full((1, K), -60.0, dtype=torch.float64)
+    raw["theta"][0, 2] = 60.0
+    g = np.diff(np.concatenate([O.activate(raw)["theta"].numpy()[0], [2 * math.pi]]))
+    assert 2 * math.pi * (1 + 1 / (K - 2)) / (1 + K / (K - 2)) == pytest.approx(math.pi, rel=1e-15)
+    assert g.max() == pytest.approx(math.pi, rel=1e-12)
+
+
+def test_activation_vjp_against_central_differences():
+    raw = _raw(4, 5, 3)
+    rng = np.random.default_rng(4)
+    g_act = {k: torch.as_tensor(rng.normal(size=v.shape)) for k, v in raw.items()}
+    grads = O.activate_vjp(raw, g_act)
+    f = lambda r: sum(float((O.activate(r)[k] * g_act[k]).sum()) for k in g_act)
+    h = 1e-6
+    for k in raw:
+        flat = raw[k].reshape(-1)
+        for i in range(0, flat.numel(), max(1, flat.numel() // 6)):
+            rp = {kk: vv.clone() for kk, vv in raw.items()}
+            rm = {kk: vv.clone() for kk, vv in raw.items()}
+            rp[k].reshape(-1)[i] += h
+            rm[k].reshape(-1)[i] -= h
+            fd = (f(rp) - f(rm)) / (2 * h)
+            assert float(grads[k].reshape(-1)[i]) == pytest.approx(fd, rel=1e-6, abs=1e-8), (k, i)
+
+
+def test_adam_first_step_and_fixed_point():
+    """At step 1 the bias-corrected update is lr * g / (|g| + eps): each parameter moves by lr
+    against the sign of its gradient; with zero gradient and zero moments nothing moves."""
+    g = np.array([3.0, -0.2, 1e-3, 0.0])
+    p, m, v = O.adam_step(np.zeros(4), np.zeros(4), np.zeros(4), g, 0.01, 0.9, 0.999, 1e-15, 1)
+    np.testing.assert_allclose(p, [-0.01, 0.01, -0.01, 0.0], rtol=1e-9)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+    # two steps with a constant gradient: the update stays lr * sign(g) (m_hat = g, v_hat = g^2)
+    p2, _, _ = O.adam_step(p, m, v, g, 0.01, 0.9, 0.999, 1e-15, 2)
+    np.testing.assert_allclose(p2, 2 * p, rtol=1e-9)
