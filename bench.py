@@ -269,6 +269,60 @@ def mesh_phase(args, W, H):
     return out
 
 
+def train_phase(args):
+    """Parametrization and optimizer kernels at the headline size (1M DRKs, K = 8, SH3: 74 floats
+    each), raw parameters laid out in one flat buffer so one Adam launch updates all of them.
+    Algorithmic bytes per DRK: activation reads 74 and writes 74 floats; its VJP reads the 23 raw
+    floats it needs (q, s, theta, eta, tau, o) and 74 gradients and writes 74; Adam reads p, m, v,
+    g and writes p, m, v (28 B per float).  The raster backward these would feed is switched off."""
+    import torch
+    from paper_2412_11752_amd import DRKScene, activate, activate_bwd, adam_step
+    n, K, ncol = args.n, 8, 48
+    rows = [("mu", 3), ("q", 4), ("scale", K), ("theta", K), ("eta", 1), ("tau", 1), ("opacity", 1), ("color", ncol)]
+    total = sum(r for _, r in rows) * n
+    g = torch.Generator(device="cuda").manual_seed(9)
+    flat = torch.randn(total, device="cuda", generator=g)
+    gflat = torch.randn(total, device="cuda", generator=g) * 1e-3
+
+    def views(buf):
+        out, off = {}, 0
+        for name, r in rows:
+            t = buf[off:off + r * n]
+            out[name] = t.view(r, n) if name not in ("eta", "tau", "opacity") else t
+            off += r * n
+        return DRKScene(out["mu"], out["q"], out["scale"], out["theta"], out["eta"], out["tau"], out["opacity"],
+                        out["color"], 3)
+    raw, gact = views(flat), views(gflat)
+    m = torch.zeros_like(flat)
+    v = torch.zeros_like(flat)
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    def time_it(name, fn, nbytes, reps=20):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = nbytes / (ms / 1e3) / 1e9
+        res[name] = {"ms": round(ms, 4), "bytes": int(nbytes), "GB_s": round(gbs, 1), "frac_hbm": round(gbs / 8000.0, 3)}
+        log(f"train {name}: {ms:.4f} ms, {gbs:.0f} GB/s ({gbs / 8000.0:.2f} of 8 TB/s)")
+    fl = 74
+    time_it("activate", lambda: activate(raw), n * fl * 8)
+    time_it("activate_bwd", lambda: activate_bwd(raw, gact), n * (23 + fl + fl) * 4)
+    step = [0]
+
+    def adam():
+        step[0] += 1
+        adam_step(flat, m, v, gflat, 5e-3, 0.9, 0.999, 1e-15, step[0])
+    time_it("adam", adam, total * 28)
+    return {"n_prims": n, "floats_per_prim": fl, "kernels": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,7 +332,7 @@ def main():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--phases", default="fwd,serve",
-                    help="fwd, fwdbwd (backward switched off), serve, ksweep, sortacc, mesh")
+                    help="fwd, fwdbwd (backward switched off), serve, ksweep, sortacc, mesh, train")
     ap.add_argument("--ksweep", default="3,5,8,16", help="radial basis counts of the ksweep phase")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the Poisson arrival trace")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
@@ -387,6 +441,10 @@ def main():
     ksweep = None
     if "ksweep" in phases:
         ksweep = ksweep_phase(args, opts, W, H)
+    train = None
+    if "train" in phases:
+        train = train_phase(args)
+        torch.cuda.empty_cache()
     mesh = None
     if "mesh" in phases:
         mesh = mesh_phase(args, W, H)
@@ -420,6 +478,8 @@ def main():
         line["sortacc"] = sortacc
     if mesh is not None:
         line["mesh"] = mesh
+    if train is not None:
+        line["train"] = train
     if "fwdbwd" in result:
         line["ms_breakdown"]["render_bwd"] = round(float(result["fwdbwd"]["ms"][:, 3].mean()), 4)
     print(json.dumps(line), flush=True)

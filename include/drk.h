@@ -193,6 +193,28 @@ drk_status drk_trace_metrics(const int32_t* trace_n, const float* trace_z, int64
 drk_status drk_render_depth_normal(drk_ws* ws, float* rgb, float* T_final, float* depth, float* normal,
                                    void* stream);
 
+/* Parametrization (supplement S4): raw, unconstrained parameters -> the renderer's parameters.
+ *   raw  a drk_scene whose arrays hold raw values (same shapes; q need not be unit length)
+ *   out  the activated arrays (same shapes), written:
+ *        mu, colour copied; q / |q|; s_k = exp(raw); eta, o = sigmoid(raw);
+ *        tau = -0.1 + 1.09 sigmoid(raw), in (-0.1, 0.99);
+ *        theta: sector gaps proportional to sigmoid(raw_k) + 1/(K - 2), summing to 2 pi,
+ *        theta_k = the gaps before k (theta_0 = 0); every gap is below pi unless the sigmoids
+ *        saturate in float32 (|raw| above about 17), where a gap of pi makes the primitive invalid.
+ * Float32, one thread per primitive.                                                            */
+drk_status drk_activate(const drk_scene* raw, const drk_scene_out* out, void* stream);
+
+/* Vector-Jacobian product of drk_activate: from dL/d(activated) (g_act, read) and the raw
+ * parameters, writes dL/d(raw) into g_raw (same shapes).                                        */
+drk_status drk_activate_bwd(const drk_scene* raw, const drk_scene_grad* g_act, const drk_scene_out* g_raw,
+                            void* stream);
+
+/* One Adam step (bias-corrected; the supplement's training follows 3D-GS's Adam) on n float32
+ * elements in place: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  step >= 1.                    */
+drk_status drk_adam_step(float* param, float* m, float* v, const float* grad, int64_t n, float lr, float beta1,
+                         float beta2, float eps, int32_t step, void* stream);
+
 /* Mesh to DRK (section "Converting Mesh to DRK" and its supplement): one DRK per planar convex
  * face, with the basis endpoints at the face's vertices, without any optimisation.
  *   vertices [3][nv] float32 (device)      faces [nf][m] int32 vertex indices (device), -1 pads

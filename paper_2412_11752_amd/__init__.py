@@ -6,8 +6,8 @@ and fails loudly if it has not been built.
 """
 from .rasterizer import (  # noqa: F401
     DRKScene, Rasterizer, DRKRenderFunction, render, camera_struct, make_opts, EXPORT, KEY_MODES, trace_metrics,
-    mesh_to_drk,
+    mesh_to_drk, activate, activate_bwd, adam_step,
 )
 
 __all__ = ["DRKScene", "Rasterizer", "DRKRenderFunction", "render", "camera_struct", "make_opts", "EXPORT",
-           "KEY_MODES", "trace_metrics", "mesh_to_drk"]
+           "KEY_MODES", "trace_metrics", "mesh_to_drk", "activate", "activate_bwd", "adam_step"]

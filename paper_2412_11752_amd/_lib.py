@@ -14,7 +14,8 @@ STATUS_NAMES = {0: "DRK_OK", 1: "DRK_EINVAL", 2: "DRK_ENOMEM", 3: "DRK_EOVERFLOW
 EXPORTED = [
     "drk_opts_default", "drk_last_error", "drk_version", "drk_ws_create", "drk_ws_destroy", "drk_ws_size_query",
     "drk_preprocess", "drk_bin_sort", "drk_render_fwd", "drk_render_trace", "drk_trace_metrics",
-    "drk_render_depth_normal", "drk_mesh_to_drk", "drk_render_bwd",
+    "drk_render_depth_normal", "drk_mesh_to_drk", "drk_activate", "drk_activate_bwd", "drk_adam_step",
+    "drk_render_bwd",
     "drk_ws_status", "drk_ws_export",
     "drk_serve_create", "drk_serve_destroy", "drk_serve_add_scene", "drk_serve_submit", "drk_serve_poll",
 ]
@@ -91,6 +92,9 @@ def lib() -> C.CDLL:
         "drk_trace_metrics": [vp, vp, i64, i32, vp, vp],
         "drk_render_depth_normal": [vp, vp, vp, vp, vp, vp],
         "drk_mesh_to_drk": [vp, i64, vp, i64, i32, vp, i32, C.c_float, C.c_float, C.POINTER(SceneOut), vp, vp],
+        "drk_activate": [C.POINTER(Scene), C.POINTER(SceneOut), vp],
+        "drk_activate_bwd": [C.POINTER(Scene), C.POINTER(SceneGrad), C.POINTER(SceneOut), vp],
+        "drk_adam_step": [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp],
         "drk_render_bwd": [vp, C.POINTER(Scene), vp, vp, C.POINTER(SceneGrad), vp],
         "drk_ws_status": [vp, vp, C.POINTER(i64)],
         "drk_ws_export": [vp, i32, i32, vp, i64, C.POINTER(i64), vp],

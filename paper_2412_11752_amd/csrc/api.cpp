@@ -49,6 +49,9 @@ hipError_t fill_u32(uint32_t*, uint32_t, int64_t, hipStream_t);
 hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
                              float*, float*, int32_t*, int32_t*, int32_t*, int32_t*, int, void*, int32_t*, float*, int,
                              hipStream_t);
+hipError_t launch_activate(const drk_scene&, const drk_scene_out&, int, hipStream_t);
+hipError_t launch_activate_bwd(const drk_scene&, const drk_scene_grad&, const drk_scene_out&, int, hipStream_t);
+hipError_t launch_adam(float*, float*, float*, const float*, int64_t, float, float, float, float, int, hipStream_t);
 hipError_t launch_mesh_to_drk(const float*, int64_t, const int32_t*, int64_t, int, const float*, int, float, float,
                               const drk_scene_out&, uint32_t*, hipStream_t);
 hipError_t launch_render_bwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
@@ -501,6 +504,61 @@ drk_status drk_render_depth_normal(drk_ws* ws, float* rgb, float* T_final, float
   if (!ws || !rgb || !depth || !normal) { set_error("null argument"); return DRK_EINVAL; }
   if (!ws->have_bins) { set_error("drk_render_depth_normal before drk_bin_sort"); return DRK_EINVAL; }
   return render_views(ws, rgb, T_final, 2, 0, depth, nullptr, normal, reinterpret_cast<hipStream_t>(stream));
+}
+
+namespace {
+
+// Checks the shape fields of a raw scene; returns the colour row count, or -1 (error set).
+int raw_colour_rows(const drk_scene* raw) {
+  if (!raw || raw->n < 0 || raw->K < 3 || raw->K > kMaxK) { set_error("raw scene: n >= 0 and 3 <= K <= %d", kMaxK); return -1; }
+  if (raw->color_mode == 0) return 3;
+  if (raw->color_mode == 1 && raw->sh_degree >= 0 && raw->sh_degree <= 3) return 3 * (raw->sh_degree + 1) * (raw->sh_degree + 1);
+  set_error("raw scene: color_mode 0, or 1 with sh_degree in [0, 3]");
+  return -1;
+}
+
+bool all_set(const void* const* p, int cnt) {
+  for (int i = 0; i < cnt; ++i)
+    if (!p[i]) return false;
+  return true;
+}
+
+}  // namespace
+
+drk_status drk_activate(const drk_scene* raw, const drk_scene_out* out, void* stream) {
+  const int ncol = raw_colour_rows(raw);
+  if (ncol < 0) return DRK_EINVAL;
+  const void* ptrs[16] = {raw->mu, raw->q, raw->scale, raw->theta, raw->eta, raw->tau, raw->opacity, raw->color,
+                          out ? out->mu : nullptr, out ? out->q : nullptr, out ? out->scale : nullptr,
+                          out ? out->theta : nullptr, out ? out->eta : nullptr, out ? out->tau : nullptr,
+                          out ? out->opacity : nullptr, out ? out->color : nullptr};
+  if (raw->n > 0 && !all_set(ptrs, 16)) { set_error("null array"); return DRK_EINVAL; }
+  return check_hip(launch_activate(*raw, *out, ncol, reinterpret_cast<hipStream_t>(stream)), "activate");
+}
+
+drk_status drk_activate_bwd(const drk_scene* raw, const drk_scene_grad* g_act, const drk_scene_out* g_raw,
+                            void* stream) {
+  const int ncol = raw_colour_rows(raw);
+  if (ncol < 0) return DRK_EINVAL;
+  if (!g_act || !g_raw) { set_error("null argument"); return DRK_EINVAL; }
+  const void* ptrs[24] = {raw->mu, raw->q, raw->scale, raw->theta, raw->eta, raw->tau, raw->opacity, raw->color,
+                          g_act->mu, g_act->q, g_act->scale, g_act->theta, g_act->eta, g_act->tau, g_act->opacity,
+                          g_act->color, g_raw->mu, g_raw->q, g_raw->scale, g_raw->theta, g_raw->eta, g_raw->tau,
+                          g_raw->opacity, g_raw->color};
+  if (raw->n > 0 && !all_set(ptrs, 24)) { set_error("null array"); return DRK_EINVAL; }
+  return check_hip(launch_activate_bwd(*raw, *g_act, *g_raw, ncol, reinterpret_cast<hipStream_t>(stream)),
+                   "activate_bwd");
+}
+
+drk_status drk_adam_step(float* param, float* m, float* v, const float* grad, int64_t n, float lr, float beta1,
+                         float beta2, float eps, int32_t step, void* stream) {
+  if (n < 0 || (n > 0 && (!param || !m || !v || !grad))) { set_error("null array or n < 0"); return DRK_EINVAL; }
+  if (step < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f)) {
+    set_error("adam: step >= 1, betas in [0, 1), eps > 0");
+    return DRK_EINVAL;
+  }
+  return check_hip(launch_adam(param, m, v, grad, n, lr, beta1, beta2, eps, step, reinterpret_cast<hipStream_t>(stream)),
+                   "adam");
 }
 
 drk_status drk_mesh_to_drk(const float* vertices, int64_t nv, const int32_t* faces, int64_t nf, int32_t m,

@@ -294,3 +294,38 @@ def mesh_to_drk(vertices: torch.Tensor, faces: torch.Tensor, face_rgb: torch.Ten
                                 float(tau), float(opacity), C.byref(out), _ptr(rej), C.c_void_p(_stream_handle(dev))),
           "drk_mesh_to_drk")
     return sc, int(rej.item())
+
+
+def _scene_like(sc: DRKScene) -> DRKScene:
+    return DRKScene(*[torch.empty_like(t) for t in sc.tensors()], sh_degree=sc.sh_degree)
+
+
+def activate(raw: DRKScene) -> DRKScene:
+    """Raw, unconstrained parameters -> the renderer's parameters (drk_activate; supplement S4)."""
+    out = _scene_like(raw)
+    o = _lib.SceneOut(*[t.data_ptr() for t in out.tensors()])
+    cs = raw.c_struct()
+    check(lib().drk_activate(C.byref(cs), C.byref(o), C.c_void_p(_stream_handle(raw.mu.device))), "drk_activate")
+    return out
+
+
+def activate_bwd(raw: DRKScene, g_act: DRKScene) -> DRKScene:
+    """dL/d(raw) from dL/d(activated) (drk_activate_bwd)."""
+    out = _scene_like(raw)
+    o = _lib.SceneOut(*[t.data_ptr() for t in out.tensors()])
+    g = _lib.SceneGrad(*[t.contiguous().data_ptr() for t in g_act.tensors()])
+    cs = raw.c_struct()
+    check(lib().drk_activate_bwd(C.byref(cs), C.byref(g), C.byref(o), C.c_void_p(_stream_handle(raw.mu.device))),
+          "drk_activate_bwd")
+    return out
+
+
+def adam_step(param: torch.Tensor, m: torch.Tensor, v: torch.Tensor, grad: torch.Tensor, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, step: int = 1) -> None:
+    """In-place bias-corrected Adam on contiguous float32 CUDA tensors of equal size (drk_adam_step)."""
+    for t in (param, m, v, grad):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != param.numel():
+            raise ValueError("adam_step needs contiguous float32 CUDA tensors of one size")
+    check(lib().drk_adam_step(_ptr(param), _ptr(m), _ptr(v), _ptr(grad), int(param.numel()), float(lr), float(beta1),
+                              float(beta2), float(eps), int(step), C.c_void_p(_stream_handle(param.device))),
+          "drk_adam_step")
