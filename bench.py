@@ -5,7 +5,9 @@ Workload (default): 1M DRKs (K = 8, SH degree 3) in 64 anisotropic clusters of a
 rendered at 1920x1080 along a 100-frame camera path inside the box.  Inputs are resident in HBM
 before the timed region starts.
 
-  fwd phase     : per step one view: preprocess -> bin/sort -> forward raster   -> value (Mpix/s)
+  fwd phase     : per step one view: preprocess -> bin/sort -> forward raster   -> value (Mpix/s);
+                  consecutive steps alternate over --streams workspaces and streams (default 2),
+                  so one view's preprocess and sort overlap the previous view's raster
   fwd+bwd phase : per step one view: the forward above + backward raster + per-primitive backward
 
 Prints ONE JSON line on stdout; progress goes to stderr.
@@ -68,8 +70,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def sized_rasterizer(ds, frames, W, H, opts):
-    """A rasterizer whose pair buffer fits every frame of the list (sized in an untimed pass)."""
+def sized_rasterizer(ds, frames, W, H, opts, count=1):
+    """`count` rasterizers whose pair buffers fit every frame of the list (sized in an untimed pass)."""
     from paper_2412_11752_amd import Rasterizer
     ras = Rasterizer(ds.n, ds.K, W, H, pair_capacity=1 << 26)
     need = 0
@@ -80,49 +82,71 @@ def sized_rasterizer(ds, frames, W, H, opts):
         need = max(need, nd)
     cap = int(need * 1.05) + 4096
     ras.close()
-    return Rasterizer(ds.n, ds.K, W, H, pair_capacity=cap), cap, need
+    out = [Rasterizer(ds.n, ds.K, W, H, pair_capacity=cap) for _ in range(count)]
+    return (out[0] if count == 1 else out), cap, need
 
 
-def timed(ras, ds, frames, opts, args, rgb, T, bwd=False):
-    """Times args.steps frames (after args.warmup untimed ones); per-stage HIP events on the stream
-    the library runs on.  Returns (wall seconds, [steps][4] ms: preprocess, bin/sort, fwd, bwd)."""
+class Lane:
+    """One in-flight frame slot: a workspace, its output buffers and its stream."""
+
+    def __init__(self, ras, W, H, stream):
+        import torch
+        self.ras, self.stream = ras, stream
+        self.rgb = torch.empty(3 * W * H, device="cuda")
+        self.T = torch.empty(W * H, device="cuda")
+
+
+def make_lanes(ras_list, W, H):
+    """Frame slots: the first on the current stream, the others on their own default-priority
+    streams (consecutive frames are independent, so slot i % n renders frame i)."""
+    import torch
+    return [Lane(r, W, H, torch.cuda.current_stream() if i == 0 else torch.cuda.Stream())
+            for i, r in enumerate(ras_list)]
+
+
+def timed(lanes, ds, frames, opts, args, bwd=False):
+    """Times args.steps frames (after args.warmup untimed ones), frame i on lane i % len(lanes);
+    per-stage HIP events on each frame's stream.  Returns (wall seconds, [steps][4] ms: preprocess,
+    bin/sort, fwd, bwd)."""
     import torch
     from paper_2412_11752_amd._lib import DRK_OK, DrkError
-    stream = torch.cuda.current_stream()
-    g_up = torch.full_like(rgb, 0.01) if bwd else None
+    g_up = [torch.full_like(ln.rgb, 0.01) for ln in lanes] if bwd else None
+
+    def frame(i, e=None):
+        k = i % len(lanes)
+        ln = lanes[k]
+        with torch.cuda.stream(ln.stream):
+            if e: e[0].record(ln.stream)
+            ln.ras.preprocess(ds, [frames[i]], opts)
+            if e: e[1].record(ln.stream)
+            ln.ras.bin_sort()
+            if e: e[2].record(ln.stream)
+            ln.ras.render_fwd(ln.rgb, ln.T)
+            if e: e[3].record(ln.stream)
+            if bwd:
+                ln.ras.render_bwd(ln.rgb, g_up[k])
+            if e: e[4].record(ln.stream)
     for i in range(args.warmup):
-        ras.preprocess(ds, [frames[i]], opts)
-        ras.bin_sort()
-        ras.render_fwd(rgb, T)
-        if bwd:
-            ras.render_bwd(rgb, g_up)
+        frame(i)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for s in range(args.steps):
-        cam = frames[args.warmup + s]
-        e = ev[s]
-        e[0].record(stream)
-        ras.preprocess(ds, [cam], opts)
-        e[1].record(stream)
-        ras.bin_sort()
-        e[2].record(stream)
-        ras.render_fwd(rgb, T)
-        e[3].record(stream)
-        if bwd:
-            ras.render_bwd(rgb, g_up)
-        e[4].record(stream)
+        frame(args.warmup + s, ev[s])
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
                     e[3].elapsed_time(e[4])] for e in ev])
-    code, _ = ras.status()
-    if code != DRK_OK:
-        raise DrkError(code, "timed loop")
+    for ln in lanes:
+        with torch.cuda.stream(ln.stream):
+            code, _ = ln.ras.status()
+        if code != DRK_OK:
+            raise DrkError(code, "timed loop")
     return t_total, ms
 
 
 def raster_work(ras, ds, frames, opts, args, rgb, T):
+    # (sequential, on the current stream: the counts do not depend on timing)
     """Work units of the forward raster per launch, averaged over the timed frames (re-rendered:
     the pipeline is deterministic), counted by the kernel itself."""
     tot = dict(listed=0, hits=0, kernels=0, contributors=0, emitted=0)
@@ -152,11 +176,12 @@ def ksweep_phase(args, opts, W, H):
         t0 = time.time()
         host = scene_clusters(2, args.n, K=K, half=10.0)
         ds = DRKScene.from_host(host, device="cuda")
+        # one frame in flight: the per-stage times compare K without overlap between frames
         ras, cap, need = sized_rasterizer(ds, frames, W, H, opts)
-        rgb = torch.empty(3 * W * H, device="cuda")
-        T = torch.empty(W * H, device="cuda")
-        t_total, ms = timed(ras, ds, frames, opts, args, rgb, T)
-        work = raster_work(ras, ds, frames, opts, args, rgb, T)
+        rl = [ras]
+        lanes = make_lanes(rl, W, H)
+        t_total, ms = timed(lanes, ds, frames, opts, args)
+        work = raster_work(ras, ds, frames, opts, args, lanes[0].rgb, lanes[0].T)
         raster_ms = float(ms[:, 2].mean())
         row = {"mpix_s": round(args.steps * W * H / t_total / 1e6, 2),
                "ms_preprocess": round(float(ms[:, 0].mean()), 4), "ms_bin_sort": round(float(ms[:, 1].mean()), 4),
@@ -166,13 +191,14 @@ def ksweep_phase(args, opts, W, H):
                "ns_per_hit": round(raster_ms * 1e6 / max(work["hits"], 1), 4)}
         log(f"ksweep K={K}: {row} (scene gen + sizing {time.time() - t0:.1f}s)")
         out[str(K)] = row
-        ras.close()
+        for r in rl:
+            r.close()
         del ds
         torch.cuda.empty_cache()
     return out
 
 
-def sortacc_phase(args, ras, ds, frames, W, H, rgb, T):
+def sortacc_phase(args, lanes, ds, frames, W, H):
     """Sorting accuracy of the pre-sort keys (supplement, cache-sorting evaluation): randomly placed
     and oriented kernels (1500 DRKs, K = 8, scales 0.05-0.5 in a 2-unit box) rendered at 512x512
     with each key and cache length, traced front to back and measured by drk_trace_metrics; plus
@@ -200,7 +226,7 @@ def sortacc_phase(args, ras, ds, frames, W, H, rgb, T):
                                                   f"mae {v['mae']:.4f}" for L, v in row.items()))
     r2.close()
     for mode in (0, 1, 2):
-        t_total, ms = timed(ras, ds, frames, make_opts(key_mode=mode), args, rgb, T)
+        t_total, ms = timed(lanes[:1], ds, frames, make_opts(key_mode=mode), args)   # one frame in flight
         out["cost"][names[mode]] = {"mpix_s": round(args.steps * W * H / t_total / 1e6, 2),
                                     "ms_preprocess": round(float(ms[:, 0].mean()), 4),
                                     "ms_bin_sort": round(float(ms[:, 1].mean()), 4),
@@ -334,6 +360,8 @@ def main():
     ap.add_argument("--phases", default="fwd,serve",
                     help="fwd, fwdbwd (backward switched off), serve, ksweep, sortacc, mesh, train")
     ap.add_argument("--ksweep", default="3,5,8,16", help="radial basis counts of the ksweep phase")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="frames in flight: consecutive frames alternate over this many workspaces and streams")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the Poisson arrival trace")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget (0 = skip)")
@@ -361,22 +389,28 @@ def main():
     n_frames = args.warmup + args.steps
     frames = [cams[i % len(cams)] for i in range(n_frames)]
 
-    ras, cap, need = sized_rasterizer(ds, frames, W, H, opts)
-    log(f"pairs per view (max over frames): {need}  capacity {cap}")
-    rgb = torch.empty(3 * W * H, device=dev)
-    T = torch.empty(W * H, device=dev)
+    rl, cap, need = sized_rasterizer(ds, frames, W, H, opts, count=args.streams)
+    rl = rl if isinstance(rl, list) else [rl]
+    lanes = make_lanes(rl, W, H)
+    ras, rgb, T = rl[0], lanes[0].rgb, lanes[0].T
+    log(f"pairs per view (max over frames): {need}  capacity {cap}; {len(lanes)} frame(s) in flight")
     result = {}
 
     phases = [p for p in args.phases.split(",") if p]
     if "fwd" in phases:
-        t_total, ms = timed(ras, ds, frames, opts, args, rgb, T, bwd=False)
+        t_total, ms = timed(lanes, ds, frames, opts, args, bwd=False)
         mpix = args.steps * W * H / t_total / 1e6
         log(f"fwd: {t_total * 1e3 / args.steps:.3f} ms/step, {mpix:.1f} Mpix/s; "
             f"preprocess {ms[:, 0].mean():.3f} ms, bin/sort {ms[:, 1].mean():.3f} ms, raster {ms[:, 2].mean():.3f} ms")
         result["fwd"] = dict(t_total=t_total, ms=ms, mpix=mpix)
+        if len(lanes) > 1 and not args.profile:
+            t1, ms1 = timed(lanes[:1], ds, frames, opts, args, bwd=False)
+            result["fwd1"] = dict(mpix=args.steps * W * H / t1 / 1e6, ms=ms1)
+            log(f"fwd, one frame in flight: {t1 * 1e3 / args.steps:.3f} ms/step, {result['fwd1']['mpix']:.1f} Mpix/s; "
+                f"raster {ms1[:, 2].mean():.3f} ms")
     if "fwdbwd" in phases:
         try:
-            t_total, ms = timed(ras, ds, frames, opts, args, rgb, T, bwd=True)
+            t_total, ms = timed(lanes, ds, frames, opts, args, bwd=True)
             its = args.steps / t_total
             log(f"fwd+bwd: {t_total * 1e3 / args.steps:.3f} ms/step, {its:.2f} it/s; bwd {ms[:, 3].mean():.3f} ms")
             result["fwdbwd"] = dict(t_total=t_total, ms=ms, its=its)
@@ -397,6 +431,12 @@ def main():
                     "kernel_evaluations_per_launch": work["kernels"],
                     "contributors_per_launch": work["contributors"],
                     "emitted_per_launch": work["emitted"]}
+        if "fwd1" in result:
+            iso_ms = float(result["fwd1"]["ms"][:, 2].mean())
+            iso = work["flops"] / (iso_ms / 1e3) / 1e12
+            # the same launches with one frame in flight (no other frame's kernels sharing the GPU)
+            roofline["isolated"] = {"avg_launch_ms": round(iso_ms, 4), "achieved": round(iso, 3),
+                                    "frac": round(iso / VALU_PEAK_TFLOPS, 4)}
         log(f"raster work: {work['listed'] / 1e6:.1f}M listed, {work['hits'] / 1e6:.1f}M hits, "
             f"{work['kernels'] / 1e6:.1f}M kernel evaluations, {work['contributors'] / 1e6:.1f}M "
             f"contributors, {work['emitted'] / 1e6:.1f}M emitted per view -> {achieved:.2f} TFLOP/s")
@@ -435,8 +475,10 @@ def main():
 
     sortacc = None
     if "sortacc" in phases:
-        sortacc = sortacc_phase(args, ras, ds, frames, W, H, rgb, T)
-    ras.close()
+        sortacc = sortacc_phase(args, lanes, ds, frames, W, H)
+    for r in rl:
+        r.close()
+    del lanes
     torch.cuda.empty_cache()
     ksweep = None
     if "ksweep" in phases:
@@ -463,8 +505,11 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{scene.n} DRKs (K={K}, SH3) in 64 anisotropic clusters of a 20-unit box, "
-                               f"{W}x{H}, camera path inside the box, one view per step",
-                   "n_prims": scene.n, "K": K, "width": W, "height": H, "pairs_per_view": pairs_last},
+                               f"{W}x{H}, camera path inside the box, one view per step, {args.streams} consecutive "
+                               f"frames in flight on separate streams",
+                   "n_prims": scene.n, "K": K, "width": W, "height": H, "pairs_per_view": pairs_last,
+                   "frames_in_flight": args.streams},
+        "one_frame_in_flight_mpix_s": round(result["fwd1"]["mpix"], 3) if "fwd1" in result else None,
         "fwd_bwd_it_per_s": round(result["fwdbwd"]["its"], 3) if "fwdbwd" in result else None,
         "ms_breakdown": {k: round(float(fwd["ms"][:, i].mean()), 4) for i, k in
                          enumerate(["preprocess", "bin_sort", "render_fwd"])} if fwd else None,

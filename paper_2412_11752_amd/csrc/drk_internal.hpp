@@ -51,8 +51,8 @@ enum SecField : int {
   S_ID = 3,    // 1 / delta_k, delta_k = theta_{k+1} - theta_k (wrapping)
   S_A = 4,     // 1 / (s_k sin delta_k)
   S_B = 5,     // 1 / (s_{k+1} sin delta_k)
-  S_IK2 = 6,   // 1 / s_k^2
-  S_IN2 = 7,   // 1 / s_{k+1}^2
+  S_IK2 = 6,   // 1 / s_k^2 (1 / s_{k+1}^2 is the next sector's entry)
+  S_WLO = 7,   // min(1 / s_k^2, 1 / s_{k+1}^2) (1 - 1e-5): lower bound of the sector's L2 weight
   S_NFIELDS = 8
 };
 __host__ __device__ inline int rec_floats(int K) { return (R_SEC + S_NFIELDS * K + 3) & ~3; }

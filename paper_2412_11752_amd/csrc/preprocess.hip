@@ -515,7 +515,7 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
     rec[R_SEC + S_A * K + k] = (float)(1.0 / (sk * sd));
     rec[R_SEC + S_B * K + k] = (float)(1.0 / (sn * sd));
     rec[R_SEC + S_IK2 * K + k] = (float)(1.0 / (sk * sk));
-    rec[R_SEC + S_IN2 * K + k] = (float)(1.0 / (sn * sn));
+    rec[R_SEC + S_WLO * K + k] = (float)(fmin(1.0 / (sk * sk), 1.0 / (sn * sn)) * 0.99999);
   }
 }
 

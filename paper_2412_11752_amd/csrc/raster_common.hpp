@@ -83,10 +83,10 @@ struct Eval {
 // evaluated as cos^2(pi t/2)/s_k^2 + sin^2(pi t/2)/s_{k+1}^2: two positive terms, so that very
 // different lengths in one sector do not cancel.
 //
-// The two early-outs are exact in float32.  cos^2 + sin^2 of the polynomial stays within 1.1e-6 of 1,
-// so w_lo = min(1/s_k^2, 1/s_{k+1}^2) * 0.99999 is below the weight after rounding; every other
-// rounding step is monotone, so E >= E_lo = eta r1^2 + (1 - eta) r2 w_lo, and E > R_ETHR (c^2 with a
-// margin) gives o Psi(exp(-E/2)) < alpha_min.  Likewise r2 > R_R2CUT bounds E from below by
+// The two early-outs are exact in float32.  cos^2 + sin^2 of the polynomial lies within
+// [1 - 1.8e-7, 1 + 4.4e-7], so w_lo = min(1/s_k^2, 1/s_{k+1}^2) (1 - 1e-5) (stored per sector) is below
+// the weight after rounding; every other rounding step is monotone, so E >= E_lo = eta r1^2 +
+// (1 - eta) r2 w_lo, and E > R_ETHR (c^2 with a margin) gives o Psi(exp(-E/2)) < alpha_min.  Likewise r2 > R_R2CUT bounds E from below by
 // r2 / max_k s_k^2.  Either test only rejects when the low-pass term is also below alpha_min.
 template <int K>
 __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix& p, const RasterParams& rp, float& at,
@@ -127,15 +127,14 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
     D = fmaf(ck, u, sk * v);             // dot(d_k, p)         = r2 cos(phi)
     r1 = fmaf(sec[S_A * K + k], fabsf(B), sec[S_B * K + k] * fabsf(A));
     const float eta = r[R_ETA];
-    const float ik2 = sec[S_IK2 * K + k], in2 = sec[S_IN2 * K + k];
     const float r1sq = r1 * r1, oeta = 1.0f - eta;
-    const float E_lo = fmaf(eta, r1sq, oeta * (r2 * (fminf(ik2, in2) * 0.99999f)));
+    const float E_lo = fmaf(eta, r1sq, oeta * (r2 * sec[S_WLO * K + k]));
     if (E_lo > r[R_ETHR] && !lp_in) return false;
     phi = atan2_fast(A, D);
     t = phi * sec[S_ID * K + k];
     sh = sinhalf_fast(t);
     ch = sinhalf_fast(1.0f - t);
-    ws = fmaf(ch * ch, ik2, (sh * sh) * in2);
+    ws = fmaf(ch * ch, sec[S_IK2 * K + k], (sh * sh) * sec[S_IK2 * K + kn]);
     E = fmaf(eta, r1sq, oeta * (r2 * ws));
   }
   const float g = exp_fast(-0.5f * E);

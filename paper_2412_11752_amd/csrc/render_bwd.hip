@@ -84,7 +84,7 @@ __device__ void pair_grad(const float* __restrict__ r, const Pix& pix, const Ras
       const float ck = sec[S_C * K + k], sk = sec[S_S * K + k];
       const float cn = sec[S_C * K + kn], sn = sec[S_S * K + kn];
       const float id = sec[S_ID * K + k], ak = sec[S_A * K + k], bk = sec[S_B * K + k];
-      const float isk2 = sec[S_IK2 * K + k], isn2 = sec[S_IN2 * K + k];
+      const float isk2 = sec[S_IK2 * K + k], isn2 = sec[S_IK2 * K + kn];
       const float s_k = 1.0f / sqrtf(isk2), s_n = 1.0f / sqrtf(isn2);
       const float cot = (ck * cn + sk * sn) * (ak * s_k);       // cos(delta) / sin(delta)
       const float g_r1 = gE * 2.0f * eta * ev.r1;
