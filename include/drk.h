@@ -121,6 +121,10 @@ typedef struct drk_camera {
 typedef struct drk_opts {
   float alpha_min, alpha_max, T_min, near_plane, lowpass_sl;
   int32_t cache_len, cull_mode, validate, key_mode;
+  int32_t launch_order;   /* raster launch order of the tiles: 0 (default) longest lists first, so
+                             the launch does not end on a few long tiles; 1 row-major, which leaves
+                             that tail to kernels of other streams (frames rendered concurrently
+                             overlap better).  Images are identical either way.                   */
 } drk_opts;
 
 typedef struct drk_ws drk_ws;
@@ -152,8 +156,9 @@ drk_status drk_preprocess(drk_ws* ws, const drk_scene* scene, const drk_camera* 
  * radix sort of primitives by centre depth, duplication into (tile, primitive) pairs in that
  * order, stable radix sort of the pairs by tile id.  key_mode 1 or 2: duplication in primitive
  * order with the per-pair key, stable radix sort of the pairs by key, then by tile id.  Then
- * per-tile [start, end) ranges.  The resulting per-tile lists are ordered by (tile, key,
- * primitive index).  If a view needs more pairs than pair_capacity the overflow is recorded
+ * per-tile [start, end) ranges, and (launch_order 0) the raster's launch order: tiles by
+ * decreasing list length (the longest lists start first).  The
+ * resulting per-tile lists are ordered by (tile, key, primitive index).  If a view needs more pairs than pair_capacity the overflow is recorded
  * (see drk_ws_status) and that view renders nothing.                                         */
 drk_status drk_bin_sort(drk_ws* ws, void* stream);
 

@@ -46,7 +46,8 @@ class Camera(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("alpha_min", C.c_float), ("alpha_max", C.c_float), ("T_min", C.c_float),
                 ("near_plane", C.c_float), ("lowpass_sl", C.c_float), ("cache_len", C.c_int32),
-                ("cull_mode", C.c_int32), ("validate", C.c_int32), ("key_mode", C.c_int32)]
+                ("cull_mode", C.c_int32), ("validate", C.c_int32), ("key_mode", C.c_int32),
+                ("launch_order", C.c_int32)]
 
 
 class ServeCfg(C.Structure):

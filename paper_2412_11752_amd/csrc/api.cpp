@@ -44,9 +44,11 @@ hipError_t scan_counts(const uint32_t*, const uint32_t*, const uint64_t*, int64_
 hipError_t compact_visible(const uint32_t*, const uint32_t*, int64_t, uint32_t*, uint64_t*, uint64_t*, uint64_t*,
                            uint32_t*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t tile_ranges(const uint32_t*, const uint64_t*, uint32_t*, int, hipStream_t);
+hipError_t tile_length_keys(const uint32_t*, int, uint32_t*, uint32_t*, hipStream_t);
 hipError_t set_u64(uint64_t*, uint64_t, hipStream_t);
 hipError_t fill_u32(uint32_t*, uint32_t, int64_t, hipStream_t);
-hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const OptsDev&,
+hipError_t launch_render_fwd(int, const float*, const uint32_t*, const uint32_t*, const CamDev*, int, const uint32_t*,
+                             const OptsDev&,
                              float*, float*, int32_t*, int32_t*, int32_t*, int32_t*, int, void*, int32_t*, float*, int,
                              hipStream_t);
 hipError_t launch_activate(const drk_scene&, const drk_scene_out&, int, hipStream_t);
@@ -98,6 +100,8 @@ struct drk_ws {
   uint32_t* dup_big = nullptr;    // sorted slots of the primitives duplicated a workgroup at a time
   uint32_t* dup_count = nullptr;  // their count
   double* keygeo = nullptr;       // per view and primitive: float64 data of the per-tile keys (KG_N)
+  uint32_t* tile_order = nullptr; // per view: tiles by decreasing list length (the raster's launch order)
+  uint32_t* tk = nullptr;         // tile-order sort scratch: 4 x max_tiles
 
   SceneDev scene{};
   Views views{};
@@ -169,6 +173,8 @@ size_t layout(drk_ws* ws, bool assign, char* base) {
   SLOT(dup_big, uint32_t, N)
   SLOT(dup_count, uint32_t, 4)
   SLOT(keygeo, double, V * N * KG_N)
+  SLOT(tile_order, uint32_t, V * (size_t)ws->max_tiles)
+  SLOT(tk, uint32_t, 4 * (size_t)ws->max_tiles)
 #undef SLOT
   return p.off;
 }
@@ -256,8 +262,8 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   if (!(opts->alpha_min > 0.0f && opts->alpha_min < 1.0f) || !(opts->alpha_max > 0.0f && opts->alpha_max < 1.0f) ||
       !(opts->T_min > 0.0f && opts->T_min < 1.0f) || !(opts->near_plane > 0.0f) || !(opts->lowpass_sl >= 0.0f) ||
       opts->cache_len < 1 || opts->cache_len > kMaxCache || opts->cull_mode < 0 || opts->cull_mode > 2 ||
-      opts->key_mode < 0 || opts->key_mode > 2) {
-    set_error("invalid drk_opts (cache_len must be in [1, %d], key_mode in [0, 2])", kMaxCache);
+      opts->key_mode < 0 || opts->key_mode > 2 || opts->launch_order < 0 || opts->launch_order > 1) {
+    set_error("invalid drk_opts (cache_len must be in [1, %d], key_mode in [0, 2], launch_order 0 or 1)", kMaxCache);
     return DRK_EINVAL;
   }
   SceneDev sc;
@@ -270,6 +276,7 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   od.alpha_min = opts->alpha_min; od.alpha_max = opts->alpha_max; od.T_min = opts->T_min;
   od.near_plane = opts->near_plane; od.lowpass_sl = opts->lowpass_sl; od.cache_len = opts->cache_len;
   od.cull_mode = opts->cull_mode; od.validate = opts->validate; od.key_mode = opts->key_mode;
+  od.launch_order = opts->launch_order;
   drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
   if (st) return st;
   if ((st = check_hip(fill_u32(ws->counters, 0u, 2 * ws->max_views, s), "clear counters"))) return st;
@@ -336,6 +343,7 @@ drk_opts drk_opts_default(void) {
   o.cull_mode = 0;
   o.validate = 0;
   o.key_mode = 0;
+  o.launch_order = 0;
   return o;
 }
 
@@ -457,9 +465,19 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
     uint32_t* pv[3] = {src_v, passes == 2 ? mid_v : fv, fv};
     if ((st = check_hip(radix_sort(bits, ws->n_eff + v, pk, pv, ws->hist, ws->tot, s), "tile sort"))) return st;
     // 5. ranges
-    if ((st = check_hip(tile_ranges(fk, ws->n_eff + v, ws->ranges + (size_t)v * 2 * ws->max_tiles, ntiles, s),
-                        "ranges")))
-      return st;
+    uint32_t* rg = ws->ranges + (size_t)v * 2 * ws->max_tiles;
+    if ((st = check_hip(tile_ranges(fk, ws->n_eff + v, rg, ntiles, s), "ranges"))) return st;
+    // 6. raster launch order: tiles by decreasing list length (stable: equal lengths keep tile order)
+    if (ws->opts.launch_order != 0) continue;
+    uint32_t* t0 = ws->tk;
+    uint32_t* t1 = ws->tk + ws->max_tiles;
+    uint32_t* t2 = ws->tk + 2 * (size_t)ws->max_tiles;
+    uint32_t* t3 = ws->tk + 3 * (size_t)ws->max_tiles;
+    if ((st = check_hip(tile_length_keys(rg, ntiles, t0, t1, s), "tile keys"))) return st;
+    if ((st = check_hip(set_u64(ws->n_prims + 1, (uint64_t)ntiles, s), "tile count"))) return st;
+    uint32_t* ok_[3] = {t0, t2, t0};
+    uint32_t* ov_[3] = {t1, t3, ws->tile_order + (size_t)v * ws->max_tiles};
+    if ((st = check_hip(radix_sort(16, ws->n_prims + 1, ok_, ov_, ws->hist, ws->tot, s), "tile order"))) return st;
   }
   ws->have_bins = true;
   return DRK_OK;
@@ -478,6 +496,7 @@ drk_status render_views(drk_ws* ws, float* rgb, float* T_final, int mode, int32_
     drk_status st = check_hip(
         launch_render_fwd(ws->K, ws->records + (size_t)v * ws->max_n * ws->RF, ws->ranges + (size_t)v * 2 * ws->max_tiles,
                           ws->pair_prims + (size_t)v * ws->cap, &ws->views_dev->cam[v], cam.tiles_x * cam.tiles_y,
+                          ws->opts.launch_order == 0 ? ws->tile_order + (size_t)v * ws->max_tiles : nullptr,
                           ws->opts, rgb + 3 * off,
                           T_final ? T_final + off : nullptr, ws->n_emit + v * px_max, ws->consumed + v * px_max,
                           ws->contrib + v * px_max, ws->work_px + 2 * v * px_max, mode,

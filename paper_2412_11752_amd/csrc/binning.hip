@@ -303,6 +303,21 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ til
   }
 }
 
+// Sort keys of the tiles by decreasing list length (lengths above 65535 tie), values = tile ids.
+__global__ void __launch_bounds__(256) k_tile_keys(const uint32_t* __restrict__ ranges, int ntiles,
+                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= ntiles) return;
+  const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+  keys[t] = 0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu);
+  vals[t] = (uint32_t)t;
+}
+
+hipError_t tile_length_keys(const uint32_t* ranges, int ntiles, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_keys, dim3((ntiles + 255) / 256), dim3(256), 0, s, ranges, ntiles, keys, vals);
+  return hipGetLastError();
+}
+
 hipError_t tile_ranges(const uint32_t* tiles, const uint64_t* d_n, uint32_t* ranges, int ntiles, hipStream_t s) {
   hipLaunchKernelGGL(k_ranges_clear, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s, ranges, ntiles);
   hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, s, tiles, d_n, ranges);

@@ -19,7 +19,8 @@ constexpr int kFwdPlain = 0, kFwdTrace = 1, kFwdDepthNormal = 2;
 
 template <int K, int MODE>
 __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
-                                                       const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp, OptsDev opt,
+                                                       const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp,
+                                                       const uint32_t* __restrict__ tile_order, OptsDev opt,
                                                        float* __restrict__ rgb, float* __restrict__ T_out,
                                                        int32_t* __restrict__ n_emit_out,
                                                        int32_t* __restrict__ consumed_out,
@@ -37,7 +38,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   __shared__ float4 lds[kBatch * RF4];
   __shared__ uint32_t lidx[kBatch];
   const CamDev& cam = *camp;
-  const int tile = blockIdx.x;
+  const int tile = tile_order ? (int)tile_order[blockIdx.x] : (int)blockIdx.x;   // launch order
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   const int tid = threadIdx.x;
   const int x = tx * kTile + (tid & (kTile - 1));
@@ -175,16 +176,16 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
 
 template <int K>
 static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, const uint32_t* prims, const CamDev* cam,
-                               int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
+                               int ntiles, const uint32_t* order, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
                                int32_t* wk, int mode, void* a0, int32_t* a1, float* a2, int cap, hipStream_t s) {
   if (mode == kFwdTrace)
-    hipLaunchKernelGGL((k_render_fwd<K, kFwdTrace>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt,
+    hipLaunchKernelGGL((k_render_fwd<K, kFwdTrace>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, order, opt,
                        rgb, T, ne, cons, nc, wk, a0, a1, a2, cap);
   else if (mode == kFwdDepthNormal)
     hipLaunchKernelGGL((k_render_fwd<K, kFwdDepthNormal>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam,
-                       opt, rgb, T, ne, cons, nc, wk, a0, nullptr, a2, 0);
+                       order, opt, rgb, T, ne, cons, nc, wk, a0, nullptr, a2, 0);
   else
-    hipLaunchKernelGGL((k_render_fwd<K, kFwdPlain>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, opt,
+    hipLaunchKernelGGL((k_render_fwd<K, kFwdPlain>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, order, opt,
                        rgb, T, ne, cons, nc, wk, nullptr, nullptr, nullptr, 0);
   return hipGetLastError();
 }
@@ -192,11 +193,11 @@ static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, con
 // mode 0: colour only; 1: trace (a0 = counts, a1 = indices, a2 = depths, cap entries per pixel);
 // 2: depth (a0) and normal (a2) channels.  Pointers are those of this view.
 hipError_t launch_render_fwd(int K, const float* records, const uint32_t* ranges, const uint32_t* prims,
-                             const CamDev* cam, int ntiles, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
+                             const CamDev* cam, int ntiles, const uint32_t* order, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
                              int32_t* nc, int32_t* wk, int mode, void* a0, int32_t* a1, float* a2, int cap, hipStream_t s) {
   switch (K) {
 #define DRK_CASE(k) \
-  case k: return launch_fwd_k<k>(records, ranges, prims, cam, ntiles, opt, rgb, T, ne, cons, nc, wk, mode, a0, a1, a2, cap, s);
+  case k: return launch_fwd_k<k>(records, ranges, prims, cam, ntiles, order, opt, rgb, T, ne, cons, nc, wk, mode, a0, a1, a2, cap, s);
     DRK_CASE(3) DRK_CASE(4) DRK_CASE(5) DRK_CASE(6) DRK_CASE(7) DRK_CASE(8) DRK_CASE(9) DRK_CASE(10)
     DRK_CASE(11) DRK_CASE(12) DRK_CASE(13) DRK_CASE(14) DRK_CASE(15) DRK_CASE(16)
 #undef DRK_CASE

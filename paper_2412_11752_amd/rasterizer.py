@@ -88,12 +88,14 @@ def camera_struct(cam) -> _lib.Camera:
 
 
 def make_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, near=0.2, lowpass_sl=math.sqrt(0.5),
-              cache_len=8, cull_mode=0, validate=0, key_mode=0) -> _lib.Opts:
-    """key_mode: 0 / "centre", 1 / "centric", 2 / "nearest" (pre-sort key of the tile lists)."""
+              cache_len=8, cull_mode=0, validate=0, key_mode=0, launch_order=0) -> _lib.Opts:
+    """key_mode: 0 / "centre", 1 / "centric", 2 / "nearest" (pre-sort key of the tile lists);
+    launch_order: 0 longest tile lists first, 1 row-major (see drk_opts)."""
     o = _lib.Opts()
     o.alpha_min, o.alpha_max, o.T_min, o.near_plane, o.lowpass_sl = alpha_min, alpha_max, T_min, near, lowpass_sl
     o.cache_len, o.cull_mode, o.validate = cache_len, cull_mode, validate
     o.key_mode = KEY_MODES[key_mode] if isinstance(key_mode, str) else int(key_mode)
+    o.launch_order = int(launch_order)
     return o
 
 
