@@ -147,11 +147,12 @@ struct Spans {
   double bx0, bx1, by0, by1;        // box of every projected segment and the low-pass square
   int r0, r1;                       // initialised rows [r0, r1]
   int W, H, tx, ty;
-  // near-plane clipping state (Sutherland-Hodgman order)
+  // near-plane clipping state (Sutherland-Hodgman order); every point in front of the near plane is
+  // projected once (its pixel coordinates kept beside it) and reused by both edges it ends
   bool have_prev, prev_in, have_first;
-  double prev[3], first[3];
+  double prev[3], first[3], prev_xy[2], first_xy[2];
   bool pending_exit, have_first_entry;
-  double exit_pt[3], first_entry[3];
+  double exit_xy[2], first_entry_xy[2];
 };
 
 __device__ inline void spans_init(Spans& sp, const CamDev& cam) {
@@ -211,52 +212,54 @@ __device__ inline void project(const CamDev& cam, const double p[3], double& x, 
   y = ((double)cam.fy * p[1]) / p[2] + (double)cam.cy;
 }
 
-__device__ inline void spans_edge3(Spans& sp, const CamDev& cam, const double a[3], const double b[3]) {
-  double x0, y0, x1, y1;
-  project(cam, a, x0, y0);
-  project(cam, b, x1, y1);
-  spans_segment(sp, x0, y0, x1, y1);
-}
-
-// Camera-space polygon vertex stream, clipped to z >= near in Sutherland-Hodgman order.
-__device__ inline void clip_edge(Spans& sp, const CamDev& cam, double nearp, const double a[3], const double b[3]) {
+// Camera-space polygon vertex stream, clipped to z >= near in Sutherland-Hodgman order.  axy / bxy
+// are the pixel coordinates of a / b (used only when the point is in front of the near plane).
+__device__ inline void clip_edge(Spans& sp, const CamDev& cam, double nearp, const double a[3], const double axy[2],
+                                 const double b[3], const double bxy[2]) {
   bool ain = a[2] >= nearp, bin = b[2] >= nearp;
-  double I[3];
+  double Ixy[2] = {0.0, 0.0};
   if (ain != bin) {
     double t = (nearp - a[2]) / (b[2] - a[2]);
+    double I[3];
     for (int i = 0; i < 3; ++i) I[i] = a[i] + t * (b[i] - a[i]);
+    project(cam, I, Ixy[0], Ixy[1]);
   }
   if (ain && bin) {
-    spans_edge3(sp, cam, a, b);
+    spans_segment(sp, axy[0], axy[1], bxy[0], bxy[1]);
   } else if (ain && !bin) {            // exit
-    spans_edge3(sp, cam, a, I);
+    spans_segment(sp, axy[0], axy[1], Ixy[0], Ixy[1]);
     sp.pending_exit = true;
-    for (int i = 0; i < 3; ++i) sp.exit_pt[i] = I[i];
+    sp.exit_xy[0] = Ixy[0]; sp.exit_xy[1] = Ixy[1];
   } else if (!ain && bin) {            // entry
     if (sp.pending_exit) {
-      spans_edge3(sp, cam, sp.exit_pt, I);
+      spans_segment(sp, sp.exit_xy[0], sp.exit_xy[1], Ixy[0], Ixy[1]);
       sp.pending_exit = false;
     } else if (!sp.have_first_entry) {
       sp.have_first_entry = true;
-      for (int i = 0; i < 3; ++i) sp.first_entry[i] = I[i];
+      sp.first_entry_xy[0] = Ixy[0]; sp.first_entry_xy[1] = Ixy[1];
     }
-    spans_edge3(sp, cam, I, b);
+    spans_segment(sp, Ixy[0], Ixy[1], bxy[0], bxy[1]);
   }
 }
 
 __device__ inline void push_vertex(Spans& sp, const CamDev& cam, double nearp, const double p[3]) {
+  double pxy[2] = {0.0, 0.0};
+  if (p[2] >= nearp) project(cam, p, pxy[0], pxy[1]);
   if (!sp.have_first) {
     sp.have_first = true;
     for (int i = 0; i < 3; ++i) sp.first[i] = p[i];
+    sp.first_xy[0] = pxy[0]; sp.first_xy[1] = pxy[1];
   } else {
-    clip_edge(sp, cam, nearp, sp.prev, p);
+    clip_edge(sp, cam, nearp, sp.prev, sp.prev_xy, p, pxy);
   }
   for (int i = 0; i < 3; ++i) sp.prev[i] = p[i];
+  sp.prev_xy[0] = pxy[0]; sp.prev_xy[1] = pxy[1];
 }
 
 __device__ inline void close_polygon(Spans& sp, const CamDev& cam, double nearp) {
-  if (sp.have_first) clip_edge(sp, cam, nearp, sp.prev, sp.first);
-  if (sp.pending_exit && sp.have_first_entry) spans_edge3(sp, cam, sp.exit_pt, sp.first_entry);
+  if (sp.have_first) clip_edge(sp, cam, nearp, sp.prev, sp.prev_xy, sp.first, sp.first_xy);
+  if (sp.pending_exit && sp.have_first_entry)
+    spans_segment(sp, sp.exit_xy[0], sp.exit_xy[1], sp.first_entry_xy[0], sp.first_entry_xy[1]);
 }
 
 // tangent-plane (x, y) -> camera frame
@@ -293,6 +296,8 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
     // Eq. L1 level set; sbar: Eq. radial).  Both are maximal at the ends of each half sector, where
     // they equal s_k, s_{k+1} or the bisector values below; each half is covered by the quad of its
     // circular sector (half-angle delta/4 < pi/4).
+    // cos / sin of theta_k: the previous sector's end angle is this sector's start angle
+    double cth = cos(g.th[0]), sth = sin(g.th[0]);
     for (int k = 0; k < K; ++k) {
       const double thk = g.th[k];
       const double thn = (k + 1 < K) ? g.th[k + 1] : g.th[0] + kTwoPi;
@@ -307,7 +312,7 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
       const double a1 = thk + 0.5 * dl, m0 = thk + 0.25 * dl, m1 = thk + 0.75 * dl;
       const double ca1 = cos(a1), sa1 = sin(a1);
       double p[3];
-      lift(g, cam, rho0 * cos(thk), rho0 * sin(thk), p);
+      lift(g, cam, rho0 * cth, rho0 * sth, p);
       push_vertex(sp, cam, nearp, p);
       lift(g, cam, rho0 * sec * cos(m0), rho0 * sec * sin(m0), p);
       push_vertex(sp, cam, nearp, p);
@@ -317,7 +322,9 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
       push_vertex(sp, cam, nearp, p);
       lift(g, cam, rho1 * sec * cos(m1), rho1 * sec * sin(m1), p);
       push_vertex(sp, cam, nearp, p);
-      lift(g, cam, rho1 * cos(thn), rho1 * sin(thn), p);
+      cth = cos(thn);
+      sth = sin(thn);
+      lift(g, cam, rho1 * cth, rho1 * sth, p);
       push_vertex(sp, cam, nearp, p);
     }
   }
