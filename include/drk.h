@@ -135,7 +135,11 @@ const char* drk_version(void);
 
 /* Workspace for up to max_views views of up to max_n primitives with K bases at up to
  * max_w x max_h pixels, with pair_capacity tile-primitive pairs per view.  Allocates device
- * memory on the current device.  Returns DRK_ENOMEM / DRK_EINVAL / DRK_EDEVICE on failure. */
+ * memory on the current device.  Returns DRK_ENOMEM / DRK_EINVAL / DRK_EDEVICE on failure.
+ * The preprocess stores each primitive's tile-row spans in a buffer of 16 * max_n + 65536 rows per
+ * view; the environment variable DRK_SPAN_ROWS (a non-negative integer, read here and by
+ * drk_ws_size_query) sets another size.  Primitives whose rows do not fit have their spans
+ * re-derived during drk_bin_sort, which is slower but gives the same pairs. */
 drk_status drk_ws_create(int64_t max_n, int32_t K, int32_t max_views, int32_t max_w, int32_t max_h,
                          int64_t pair_capacity, drk_ws** out);
 drk_status drk_ws_destroy(drk_ws* ws);

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -351,6 +352,17 @@ const char* drk_last_error(void) { return g_err.c_str(); }
 
 const char* drk_version(void) { return "libdrk 0.1 (gfx950)"; }
 
+// Rows of stored tile-row spans per view: 16 per primitive plus 65536 unless DRK_SPAN_ROWS gives
+// another count (primitives whose rows do not fit are re-derived during duplication).
+static int64_t span_row_capacity(int64_t max_n) {
+  if (const char* e = std::getenv("DRK_SPAN_ROWS")) {
+    char* end = nullptr;
+    const long long v = std::strtoll(e, &end, 10);
+    if (end != e && *end == '\0' && v >= 0) return (int64_t)v;
+  }
+  return 16 * max_n + 65536;
+}
+
 drk_status drk_ws_size_query(int64_t max_n, int32_t K, int32_t max_views, int32_t max_w, int32_t max_h,
                              int64_t pair_capacity, size_t* bytes) {
   if (!bytes) { set_error("bytes is null"); return DRK_EINVAL; }
@@ -359,7 +371,7 @@ drk_status drk_ws_size_query(int64_t max_n, int32_t K, int32_t max_views, int32_
   tmp.max_n = max_n; tmp.K = K; tmp.RF = rec_floats(K); tmp.max_views = max_views;
   tmp.max_w = max_w; tmp.max_h = max_h; tmp.cap = pair_capacity;
   tmp.max_tiles = ((max_w + kTile - 1) / kTile) * ((max_h + kTile - 1) / kTile);
-  tmp.row_cap = 16 * max_n + 65536;
+  tmp.row_cap = span_row_capacity(max_n);
   *bytes = layout(&tmp, false, nullptr);
   return DRK_OK;
 }
@@ -373,7 +385,7 @@ drk_status drk_ws_create(int64_t max_n, int32_t K, int32_t max_views, int32_t ma
   ws->max_n = max_n; ws->K = K; ws->RF = rec_floats(K); ws->max_views = max_views;
   ws->max_w = max_w; ws->max_h = max_h; ws->cap = pair_capacity;
   ws->max_tiles = ((max_w + kTile - 1) / kTile) * ((max_h + kTile - 1) / kTile);
-  ws->row_cap = 16 * max_n + 65536;
+  ws->row_cap = span_row_capacity(max_n);
   if (hipGetDevice(&ws->device) != hipSuccess) { delete ws; set_error("hipGetDevice failed"); return DRK_EDEVICE; }
   size_t bytes = layout(ws, false, nullptr);
   void* base = nullptr;

@@ -673,7 +673,8 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
                                                    uint32_t* __restrict__ pair_tiles, uint32_t* __restrict__ pair_prims,
                                                    const uint64_t* __restrict__ total_ptr, int64_t capacity,
                                                    const uint64_t* __restrict__ n_sorted,
-                                                   uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_count,
+                                                   uint32_t* __restrict__ big_list, int64_t list_len,
+                                                   uint32_t* __restrict__ big_count,
                                                    const double* __restrict__ keygeo, uint32_t* __restrict__ pair_keys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)*n_sorted) return;
@@ -684,7 +685,12 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
   const uint32_t off = offsets[i];
   const CamDev& cam = views->cam[v];
   const uint2 meta = opt.cull_mode == 2 ? make_uint2(0u, 0u) : span_meta[j];
-  if (cnt > kDupSmall && (opt.cull_mode == 2 || meta.x != kNoSpans)) {
+  if (opt.cull_mode != 2 && meta.x == kNoSpans) {
+    // spans not stored (row buffer full): re-derived by k_duplicate_rebuild, listed from the end
+    big_list[list_len - 1 - atomicAdd(big_count + 1, 1u)] = (uint32_t)i;
+    return;
+  }
+  if (cnt > kDupSmall) {
     big_list[atomicAdd(big_count, 1u)] = (uint32_t)i;   // written by k_duplicate_big
     return;
   }
@@ -698,41 +704,70 @@ __global__ void __launch_bounds__(128) k_duplicate(SceneDev sc, const Views* __r
     return;
   }
   uint32_t w = 0;
-  if (meta.x != kNoSpans) {
-    const int r0 = (int)(meta.y & 0xFFFFu), nr = (int)(meta.y >> 16);
-    const uint32_t* rows = span_rows + meta.x;
-    for (int r = 0; r < nr && w < cnt; ++r) {
-      const uint32_t e = rows[r];
-      if (e == 0xFFFFFFFFu) continue;
-      const int i0 = (int)(e & 0xFFFFu), i1 = (int)(e >> 16);
-      const uint32_t base = (uint32_t)((r0 + r) * cam.tiles_x);
-      for (int c = i0; c <= i1 && w < cnt; ++c, ++w) {
-        pair_tiles[off + w] = base + (uint32_t)c;
-        pair_prims[off + w] = j;
-        if (kg) pair_keys[off + w] = tile_key(kg, cam, opt, base + (uint32_t)c);
-      }
-    }
-    return;
-  }
-  Geo g;
-  bool invalid;
-  if (!load_geo(sc, j, cam, opt, g, &invalid)) return;
-  Spans sp;
-  build_spans(g, cam, opt, sp);
-  for (int r = sp.r0; r <= sp.r1 && w < cnt; ++r) {
-    int i0, i1;
-    if (!row_tiles(sp, r, i0, i1)) continue;
+  const int r0 = (int)(meta.y & 0xFFFFu), nr = (int)(meta.y >> 16);
+  const uint32_t* rows = span_rows + meta.x;
+  for (int r = 0; r < nr && w < cnt; ++r) {
+    const uint32_t e = rows[r];
+    if (e == 0xFFFFFFFFu) continue;
+    const int i0 = (int)(e & 0xFFFFu), i1 = (int)(e >> 16);
+    const uint32_t base = (uint32_t)((r0 + r) * cam.tiles_x);
     for (int c = i0; c <= i1 && w < cnt; ++c, ++w) {
-      pair_tiles[off + w] = (uint32_t)(r * cam.tiles_x + c);
+      pair_tiles[off + w] = base + (uint32_t)c;
       pair_prims[off + w] = j;
-      if (kg) pair_keys[off + w] = tile_key(kg, cam, opt, (uint32_t)(r * cam.tiles_x + c));
+      if (kg) pair_keys[off + w] = tile_key(kg, cam, opt, base + (uint32_t)c);
     }
   }
 }
 
-// Duplication of the primitives with more than kDupSmall tiles: one workgroup per primitive walks
-// its stored rows; the lanes write the tiles of a row side by side (coalesced).
-__global__ void __launch_bounds__(256) k_duplicate_big(const Views* __restrict__ views, OptsDev opt, int v,
+// Duplication of the primitives whose row spans did not fit the row buffer: rebuilt from the scene
+// (the same polygon and spans as k_polygon), one thread per primitive.  Kept apart from
+// k_duplicate so that the common path does not carry this code's registers and private arrays.
+__global__ void __launch_bounds__(128) k_duplicate_rebuild(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
+                                                           int v, const uint32_t* __restrict__ sorted_prims,
+                                                           const uint32_t* __restrict__ offsets,
+                                                           const uint32_t* __restrict__ tile_counts,
+                                                           uint32_t* __restrict__ pair_tiles,
+                                                           uint32_t* __restrict__ pair_prims,
+                                                           const uint64_t* __restrict__ total_ptr, int64_t capacity,
+                                                           const uint32_t* __restrict__ list, int64_t list_len,
+                                                           const uint32_t* __restrict__ list_count,
+                                                           const double* __restrict__ keygeo,
+                                                           uint32_t* __restrict__ pair_keys) {
+  if ((int64_t)*total_ptr > capacity) return;
+  const uint32_t nreb = list_count[1];
+  const CamDev& cam = views->cam[v];
+  for (uint32_t item = blockIdx.x * blockDim.x + threadIdx.x; item < nreb; item += gridDim.x * blockDim.x) {
+    const uint32_t i = list[list_len - 1 - item];
+    const uint32_t j = sorted_prims[i];
+    const uint32_t cnt = tile_counts[j];
+    const uint32_t off = offsets[i];
+    const double* kg = pair_keys ? keygeo + (int64_t)j * KG_N : nullptr;
+    Geo g;
+    bool invalid;
+    if (!load_geo(sc, j, cam, opt, g, &invalid)) continue;
+    Spans sp;
+    build_spans(g, cam, opt, sp);
+    uint32_t w = 0;
+    for (int r = sp.r0; r <= sp.r1 && w < cnt; ++r) {
+      int i0, i1;
+      if (!row_tiles(sp, r, i0, i1)) continue;
+      for (int c = i0; c <= i1 && w < cnt; ++c, ++w) {
+        pair_tiles[off + w] = (uint32_t)(r * cam.tiles_x + c);
+        pair_prims[off + w] = j;
+        if (kg) pair_keys[off + w] = tile_key(kg, cam, opt, (uint32_t)(r * cam.tiles_x + c));
+      }
+    }
+  }
+}
+
+// Duplication of the primitives with more than kDupSmall tiles: one workgroup per primitive.  The
+// lanes load the primitive's stored row entries, an exclusive scan of the rows' tile counts gives
+// each row's first output slot, and the lanes then write all the primitive's pairs side by side
+// (slot p belongs to the last row whose first slot is <= p), in the same order as a row-by-row walk.
+constexpr int kDupBigBlock = 256;
+static_assert(kMaxTileRows <= kDupBigBlock, "one lane per stored tile row");
+
+__global__ void __launch_bounds__(kDupBigBlock) k_duplicate_big(const Views* __restrict__ views, OptsDev opt, int v,
                                                        const uint32_t* __restrict__ sorted_prims,
                                                        const uint32_t* __restrict__ offsets,
                                                        const uint32_t* __restrict__ tile_counts,
@@ -744,9 +779,13 @@ __global__ void __launch_bounds__(256) k_duplicate_big(const Views* __restrict__
                                                        const uint32_t* __restrict__ big_count,
                                                        const double* __restrict__ keygeo,
                                                        uint32_t* __restrict__ pair_keys) {
+  __shared__ uint32_t s_first[kDupBigBlock + 1];   // exclusive scan of the rows' tile counts
+  __shared__ uint32_t s_tile0[kDupBigBlock];       // first tile id of each row
+  __shared__ uint32_t s_wave[kDupBigBlock / 64];
   if ((int64_t)*total_ptr > capacity) return;
   const uint32_t nbig = *big_count;
   const CamDev& cam = views->cam[v];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (uint32_t item = blockIdx.x; item < nbig; item += gridDim.x) {
     const uint32_t i = big_list[item];
     const uint32_t j = sorted_prims[i];
@@ -754,7 +793,7 @@ __global__ void __launch_bounds__(256) k_duplicate_big(const Views* __restrict__
     const uint32_t off = offsets[i];
     const double* kg = pair_keys ? keygeo + (int64_t)j * KG_N : nullptr;
     if (opt.cull_mode == 2) {
-      for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+      for (uint32_t t = tid; t < cnt; t += kDupBigBlock) {
         pair_tiles[off + t] = t;
         pair_prims[off + t] = j;
         if (kg) pair_keys[off + t] = tile_key(kg, cam, opt, t);
@@ -763,21 +802,42 @@ __global__ void __launch_bounds__(256) k_duplicate_big(const Views* __restrict__
     }
     const uint2 meta = span_meta[j];
     const int r0 = (int)(meta.y & 0xFFFFu), nr = (int)(meta.y >> 16);
-    const uint32_t* rows = span_rows + meta.x;
-    uint32_t w = 0;
-    for (int r = 0; r < nr && w < cnt; ++r) {
-      const uint32_t e = rows[r];
-      if (e == 0xFFFFFFFFu) continue;
-      const uint32_t i0 = e & 0xFFFFu, i1 = e >> 16;
-      const uint32_t n_row = min(i1 - i0 + 1u, cnt - w);
-      const uint32_t base = (uint32_t)((r0 + r) * cam.tiles_x) + i0;
-      for (uint32_t t = threadIdx.x; t < n_row; t += blockDim.x) {
-        pair_tiles[off + w + t] = base + t;
-        pair_prims[off + w + t] = j;
-        if (kg) pair_keys[off + w + t] = tile_key(kg, cam, opt, base + t);
+    uint32_t n_row = 0;
+    if (tid < nr) {
+      const uint32_t e = span_rows[meta.x + tid];
+      if (e != 0xFFFFFFFFu) {
+        const uint32_t i0 = e & 0xFFFFu, i1 = e >> 16;
+        n_row = i1 - i0 + 1u;
+        s_tile0[tid] = (uint32_t)((r0 + tid) * cam.tiles_x) + i0;
       }
-      w += n_row;
     }
+    // inclusive scan within each wave, then across the four waves
+    uint32_t x = n_row;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wv] = x;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < wv; ++w) add += s_wave[w];
+    s_first[tid + 1] = x + add;
+    if (tid == 0) s_first[0] = 0;
+    __syncthreads();
+    const uint32_t total = min(s_first[nr], cnt);
+    for (uint32_t p = tid; p < total; p += kDupBigBlock) {
+      int lo = 0, hi = nr - 1;   // last row r with s_first[r] <= p (a non-empty row, as p < s_first[nr])
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_first[mid] <= p) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t tile = s_tile0[lo] + (p - s_first[lo]);
+      pair_tiles[off + p] = tile;
+      pair_prims[off + p] = j;
+      if (kg) pair_keys[off + p] = tile_key(kg, cam, opt, tile);
+    }
+    __syncthreads();   // the next primitive reuses the shared arrays
   }
 }
 
@@ -827,14 +887,19 @@ hipError_t launch_duplicate(const SceneDev& sc, const Views* views, const OptsDe
                             uint32_t* big_list, uint32_t* big_count, const double* keygeo, uint32_t* pair_keys,
                             hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
-  hipError_t e = fill_u32(big_count, 0u, 1, s);
+  // big_list holds sc.n entries: big primitives from the front (count big_count[0]) and primitives
+  // to rebuild from the back (count big_count[1]); together at most the sorted count <= sc.n
+  hipError_t e = fill_u32(big_count, 0u, 2, s);
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)((sc.n + 127) / 128));
   hipLaunchKernelGGL(k_duplicate, grid, dim3(128), 0, s, sc, views, opt, v, sorted_prims, offsets, tile_counts,
-                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, n_sorted, big_list, big_count,
+                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, n_sorted, big_list, sc.n,
+                     big_count, keygeo, pair_keys);
+  hipLaunchKernelGGL(k_duplicate_big, dim3(1024), dim3(kDupBigBlock), 0, s, views, opt, v, sorted_prims, offsets,
+                     tile_counts, span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, big_list, big_count,
                      keygeo, pair_keys);
-  hipLaunchKernelGGL(k_duplicate_big, dim3(1024), dim3(256), 0, s, views, opt, v, sorted_prims, offsets, tile_counts,
-                     span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, big_list, big_count, keygeo,
+  hipLaunchKernelGGL(k_duplicate_rebuild, dim3(512), dim3(128), 0, s, sc, views, opt, v, sorted_prims, offsets,
+                     tile_counts, pair_tiles, pair_prims, total_ptr, capacity, big_list, sc.n, big_count, keygeo,
                      pair_keys);
   return hipGetLastError();
 }

@@ -197,3 +197,29 @@ def test_launch_orders_give_identical_images():
     log(f"800x800: launch orders compared over {out[0][0].numel()} values")
     for a, b in zip(*out):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("key_mode", ["centre", "nearest"])
+def test_span_buffer_overflow_gives_the_same_lists(monkeypatch, key_mode):
+    """A row-span buffer of 64 rows (DRK_SPAN_ROWS) leaves almost every primitive's spans unstored, so
+    the duplication re-derives them from the scene: pairs, ranges, images and per-pixel counters are
+    bit-identical to those of the default buffer."""
+    need_gpu()
+    from drk_synth import config_c2
+    from paper_2412_11752_amd import DRKScene, make_opts
+    scene, cam = config_c2()
+    ds = DRKScene.from_host(scene)
+    out = []
+    for rows in (None, "64"):
+        if rows is None:
+            monkeypatch.delenv("DRK_SPAN_ROWS", raising=False)
+        else:
+            monkeypatch.setenv("DRK_SPAN_ROWS", rows)
+        ras = _rasterizer(scene, [cam], 1 << 23)
+        rgb, T = ras.forward(ds, [cam], make_opts(key_mode=key_mode))
+        out.append([rgb.clone(), T.clone()] + [ras.export(w).clone() for w in
+                                                ("pair_tiles", "pair_prims", "ranges", "emitted", "consumed")])
+        ras.close()
+    log(f"800x800 {key_mode} keys: {out[0][2].numel()} pairs with the default and the 64-row span buffer")
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
