@@ -311,21 +311,23 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
       const double sec = 1.0 / cos(0.25 * dl);
       const double a1 = thk + 0.5 * dl, m0 = thk + 0.25 * dl, m1 = thk + 0.75 * dl;
       const double ca1 = cos(a1), sa1 = sin(a1);
-      double p[3];
-      lift(g, cam, rho0 * cth, rho0 * sth, p);
-      push_vertex(sp, cam, nearp, p);
-      lift(g, cam, rho0 * sec * cos(m0), rho0 * sec * sin(m0), p);
-      push_vertex(sp, cam, nearp, p);
-      lift(g, cam, rho0 * ca1, rho0 * sa1, p);
-      push_vertex(sp, cam, nearp, p);
-      lift(g, cam, rho1 * ca1, rho1 * sa1, p);
-      push_vertex(sp, cam, nearp, p);
-      lift(g, cam, rho1 * sec * cos(m1), rho1 * sec * sin(m1), p);
-      push_vertex(sp, cam, nearp, p);
+      // the six vertices in the tangent plane, then pushed through one call site (one inlined copy
+      // of the clip and row walk instead of six keeps the kernel at 3 waves per SIMD)
+      double vx[6], vy[6];
+      vx[0] = rho0 * cth; vy[0] = rho0 * sth;
+      vx[1] = rho0 * sec * cos(m0); vy[1] = rho0 * sec * sin(m0);
+      vx[2] = rho0 * ca1; vy[2] = rho0 * sa1;
+      vx[3] = rho1 * ca1; vy[3] = rho1 * sa1;
+      vx[4] = rho1 * sec * cos(m1); vy[4] = rho1 * sec * sin(m1);
       cth = cos(thn);
       sth = sin(thn);
-      lift(g, cam, rho1 * cth, rho1 * sth, p);
-      push_vertex(sp, cam, nearp, p);
+      vx[5] = rho1 * cth; vy[5] = rho1 * sth;
+#pragma unroll 1
+      for (int q = 0; q < 6; ++q) {
+        double p[3];
+        lift(g, cam, vx[q], vy[q], p);
+        push_vertex(sp, cam, nearp, p);
+      }
     }
   }
   close_polygon(sp, cam, nearp);
