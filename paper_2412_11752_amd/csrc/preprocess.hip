@@ -414,6 +414,34 @@ __device__ inline uint32_t wave_alloc(uint32_t* ctr, uint32_t n) {
   return base + inc - n;
 }
 
+// Per-thread offsets from one atomic per workgroup of NWAVES waves (every thread of the block must
+// call it): a wave scan, then the wave totals scanned in LDS by one thread, which also takes the
+// block's range from the counter.  One atomic per wave on a single counter serialised a kernel of
+// 1M threads.
+template <int NWAVES>
+__device__ inline uint32_t block_alloc(uint32_t* ctr, uint32_t n) {
+  __shared__ uint32_t s_part[NWAVES + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = n;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) s_part[wv] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < NWAVES; ++w) {
+      const uint32_t t = s_part[w];
+      s_part[w] = run;
+      run += t;
+    }
+    s_part[NWAVES] = run ? atomicAdd(ctr, run) : 0u;
+  }
+  __syncthreads();
+  return s_part[NWAVES] + s_part[wv] + inc - n;
+}
+
 // Render record of a visible primitive (layout: RecField / SecField).
 __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const CamDev& cam, const OptsDev& opt,
                              const double box[4], float* rec, double* kg) {
@@ -532,7 +560,9 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
 // centre-depth key (float32 of ((r20 x + r21 y) + r22 z) + t2, computed in float64).  Primitives
 // that may touch the view are appended to the view's work list.  Per-view arrays are
 // [view][stride] with stride = the workspace capacity in primitives.
-__global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
+constexpr int kPreBlock = 256;
+
+__global__ void __launch_bounds__(kPreBlock) k_preprocess(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
                                                     uint32_t* __restrict__ depth_keys,
                                                     uint32_t* __restrict__ tile_counts,
                                                     uint32_t* __restrict__ work, uint32_t* __restrict__ work_count,
@@ -550,7 +580,7 @@ __global__ void __launch_bounds__(128) k_preprocess(SceneDev sc, const Views* __
     depth_keys[(int64_t)v * stride + j] = maybe ? __float_as_uint((float)g.muc[2]) : kCulledKey;
     tile_counts[(int64_t)v * stride + j] = 0;
   }
-  const uint32_t slot = wave_alloc(work_count + v, maybe ? 1u : 0u);
+  const uint32_t slot = block_alloc<kPreBlock / 64>(work_count + v, maybe ? 1u : 0u);
   if (maybe) work[(int64_t)v * stride + slot] = (uint32_t)j;
 }
 
@@ -873,8 +903,9 @@ hipError_t launch_preprocess(const SceneDev& sc, const Views* views, int nv, con
                              uint32_t* status, int64_t stride, double* keygeo, hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
   dim3 grid((unsigned)((sc.n + 127) / 128), (unsigned)nv);
-  hipLaunchKernelGGL(k_preprocess, grid, dim3(128), 0, s, sc, views, opt, depth_keys, tile_counts, work, work_count,
-                     status, stride);
+  dim3 grid_pre((unsigned)((sc.n + kPreBlock - 1) / kPreBlock), (unsigned)nv);
+  hipLaunchKernelGGL(k_preprocess, grid_pre, dim3(kPreBlock), 0, s, sc, views, opt, depth_keys, tile_counts, work,
+                     work_count, status, stride);
   hipLaunchKernelGGL(k_polygon, grid, dim3(128), 0, s, sc, views, opt, records, depth_keys, tile_counts, work,
                      work_count, span_meta, span_rows, rows_used, row_cap, stride, keygeo);
   return hipGetLastError();
