@@ -620,7 +620,7 @@ __global__ void __launch_bounds__(128) k_polygon(SceneDev sc, const Views* __res
       }
     }
   }
-  const uint32_t off = wave_alloc(rows_used + v, nrows);
+  const uint32_t off = block_alloc<2>(rows_used + v, nrows);
   if (!active) return;
   tile_counts[(int64_t)v * stride + j] = count;
   if (count == 0) {
