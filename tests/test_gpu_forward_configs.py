@@ -223,3 +223,34 @@ def test_span_buffer_overflow_gives_the_same_lists(monkeypatch, key_mode):
     log(f"800x800 {key_mode} keys: {out[0][2].numel()} pairs with the default and the 64-row span buffer")
     for a, b in zip(*out):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("cull_mode", [0, 1])
+def test_large_primitives_full_lists_match_oracle(cull_mode):
+    """Twelve DRKs a few hundred pixels wide at 256x256: most have more than 32 tiles, so their pairs
+    come from the workgroup-per-primitive duplication.  The whole sorted pair list is bit-exact
+    against the oracle's tile lists for the conservative polygon and the paper's endpoint polygon;
+    the image is compared for the conservative one (the endpoint polygon can drop support, and the
+    oracle's image evaluates every primitive at every pixel)."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene = _near_scene()
+    fx, fy, cx, cy = intrinsics_hfov(256, 256, 60.0)
+    cam = Camera(256, 256, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.array([0, 0, 2.5], np.float32),
+                 np.array([0.2, 0.1, 0.0], np.float32))
+    ras = _rasterizer(scene, [cam], 1 << 20)
+    rgb, _ = ras.forward(DRKScene.from_host(scene), [cam], gpu_opts(cull_mode=cull_mode))
+    counts = _u32(ras.export("tile_counts"))
+    log(f"cull mode {cull_mode}: tiles per DRK {sorted(counts.tolist())}")
+    assert (counts > 32).sum() >= 4
+    gt, gp = _u32(ras.export("pair_tiles")), _u32(ras.export("pair_prims"))
+    tiles, _, _ = O.tile_lists(scene, cam, oracle_opts(cull_mode=cull_mode))
+    ot = [t for t in sorted(tiles) for _ in tiles[t]]
+    op = [j for t in sorted(tiles) for _, j in tiles[t]]
+    assert np.array_equal(gt, np.array(ot)) and np.array_equal(gp, np.array(op))
+    if cull_mode != 0:
+        return
+    orc = O.render_image(scene, cam, oracle_opts())
+    worst, nk, _, _ = compare_image(rgb[0].cpu().numpy(), orc, cam.height, cam.width)
+    log(f"cull mode {cull_mode}: max err {worst:.2e}, knife {nk}")
+    assert worst <= IMG_TOL and nk <= 8
