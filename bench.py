@@ -6,8 +6,8 @@ rendered at 1920x1080 along a 100-frame camera path inside the box.  Inputs are 
 before the timed region starts.
 
   fwd phase     : per step one view: preprocess -> bin/sort -> forward raster   -> value (Mpix/s);
-                  consecutive steps alternate over --streams workspaces and streams (default 2),
-                  so one view's preprocess and sort overlap the previous view's raster
+                  consecutive steps alternate over --streams workspaces and streams (default 3),
+                  so one view's preprocess and sort overlap the previous views' rasters
   fwd+bwd phase : per step one view: the forward above + backward raster + per-primitive backward
 
 Prints ONE JSON line on stdout; progress goes to stderr.
@@ -360,7 +360,7 @@ def main():
     ap.add_argument("--phases", default="fwd,serve",
                     help="fwd, fwdbwd (backward switched off), serve, ksweep, sortacc, mesh, train")
     ap.add_argument("--ksweep", default="3,5,8,16", help="radial basis counts of the ksweep phase")
-    ap.add_argument("--streams", type=int, default=2,
+    ap.add_argument("--streams", type=int, default=3,
                     help="frames in flight: consecutive frames alternate over this many workspaces and streams")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the Poisson arrival trace")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
