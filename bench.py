@@ -42,8 +42,27 @@ def ops_hit(K: int) -> int:
 OPS_KERNEL = 27                # past both cuts: atan2, sin/cos(pi t/2), L2 weight, energy, exp, Psi, low-pass, clamp
 OPS_CACHE = 49                 # per contributor: 7 key compares + 2 selects per slot for key, alpha, index
 OPS_COMPOSITE = 10             # per emitted contribution: transmittance test and colour update
-VALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12   # 78.6: non-packed FP32 FMA issue rate
+VALU_PEAK_TFLOPS = 157.3                          # MI355X published FP32 vector peak (packed FMA counted as 2)
+VALU_NONPACKED_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12   # 78.6: one FMA per lane per clock (the build emits no packed FP32)
 HBM_PEAK_GBS = 8000.0
+
+
+def preprocess_bytes(n, visible, K, ncol):
+    """Algorithmic HBM bytes of the preprocess per view: every primitive's geometry read once to cull
+    it (centre, rotation, K scales and angles, eta, tau, opacity) and its key and tile count written;
+    each visible primitive's parameters read again with its colour, and its render record written."""
+    geo = 4 * (3 + 4 + 2 * K + 3)
+    rec = 4 * ((36 + 8 * K + 3) & ~3)
+    return n * (geo + 8) + visible * (geo + 4 * ncol + rec)
+
+
+def bin_sort_bytes(visible, pairs, tiles):
+    """Algorithmic HBM bytes of the bin/sort per view as implemented: compaction of the visible set
+    (key + index written), four 8-bit passes of the stable depth sort and the pair sort's passes
+    (each reads the keys twice and the values once and writes both: 20 B per element), the
+    duplication (8 B per pair written), the ranges (4 B per pair read)."""
+    tile_passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
+    return visible * 8 + visible * 20 * 4 + pairs * 8 + pairs * 20 * tile_passes + pairs * 4
 
 
 def raster_traffic():
@@ -150,16 +169,106 @@ def raster_work(ras, ds, frames, opts, args, rgb, T):
     """Work units of the forward raster per launch, averaged over the timed frames (re-rendered:
     the pipeline is deterministic), counted by the kernel itself."""
     tot = dict(listed=0, hits=0, kernels=0, contributors=0, emitted=0)
+    pairs, visible = [], []
     names = dict(listed="consumed", hits="hits", kernels="kernels", contributors="contributors", emitted="emitted")
+    counted = type(opts).from_buffer_copy(opts)
+    counted.counters = 1          # the instrumented launch writes the per-pixel work counters
     for s in range(args.steps):
-        ras.preprocess(ds, [frames[args.warmup + s]], opts)
+        ras.preprocess(ds, [frames[args.warmup + s]], counted)
         ras.bin_sort()
         ras.render_fwd(rgb, T)
         for k, e in names.items():
             tot[k] += int(ras.export(e).sum().item())
+        pairs.append(ras.status()[1])
+        visible.append(int((ras.export("tile_counts") != 0).sum().item()))
     out = {k: v // args.steps for k, v in tot.items()}
+    out["pairs_max"], out["pairs_mean"] = int(max(pairs)), float(np.mean(pairs))
+    out["visible_mean"] = float(np.mean(visible))
     out["flops"] = (tot["hits"] * ops_hit(ds.K) + tot["kernels"] * OPS_KERNEL + tot["contributors"] * OPS_CACHE
                     + tot["emitted"] * OPS_COMPOSITE) / args.steps
+    return out
+
+
+def c3_small_phase(args, ds, opts):
+    """The 1M-DRK cluster scene at 1297x840 along the same camera path (the 1297x840 image size of the
+    training-step workload): forward Mpix/s with the bench's frames in flight and with one."""
+    from drk_synth import c3_camera_path
+    W, H = 1297, 840
+    cams = c3_camera_path(202, 100, W, H, half=10.0)
+    frames = [cams[i % len(cams)] for i in range(args.warmup + args.steps)]
+    rl, cap, need = sized_rasterizer(ds, frames, W, H, opts, count=args.streams)
+    rl = rl if isinstance(rl, list) else [rl]
+    lanes = make_lanes(rl, W, H)
+    from paper_2412_11752_amd import make_opts
+    t_total, ms = timed(lanes, ds, frames, make_opts(launch_order=1) if len(lanes) > 1 else opts, args)
+    t1, ms1 = timed(lanes[:1], ds, frames, opts, args)
+    out = {"width": W, "height": H, "mpix_s": round(args.steps * W * H / t_total / 1e6, 2),
+           "ms_per_step": round(t_total * 1e3 / args.steps, 4), "frames_in_flight": len(lanes),
+           "one_frame_mpix_s": round(args.steps * W * H / t1 / 1e6, 2),
+           "ms_breakdown": {k: round(float(ms1[:, i].mean()), 4) for i, k in
+                            enumerate(["preprocess", "bin_sort", "render_fwd"])}, "pairs_max": need}
+    log(f"c3 1297x840: {out}")
+    for r in rl:
+        r.close()
+    return out
+
+
+def c5_phase(args, opts):
+    """3M DRKs (K = 16, SH3) in 64 clusters of a 40-unit box, eight 1920x1080 views per step in one
+    call with per-view sort buffers: Mpix/s of the forward and the device memory it holds."""
+    import torch
+    from drk_synth import config_c5
+    from paper_2412_11752_amd import DRKScene, Rasterizer
+    t0 = time.time()
+    scene, cams = config_c5()
+    ds = DRKScene.from_host(scene, device="cuda")
+    log(f"c5: {scene.n} DRKs K={scene.K}, {scene.nbytes() / 1e9:.2f} GB, gen {time.time() - t0:.1f}s")
+    W, H, V = cams[0].width, cams[0].height, len(cams)
+    probe = Rasterizer(scene.n, scene.K, W, H, max_views=V, pair_capacity=1 << 24)
+    probe.preprocess(ds, cams, opts)
+    probe.bin_sort()
+    need = probe.status()[1]
+    probe.close()
+    torch.cuda.empty_cache()
+    cap = int(need * 1.05) + 4096
+    free0, total = torch.cuda.mem_get_info()
+    ras = Rasterizer(scene.n, scene.K, W, H, max_views=V, pair_capacity=cap)
+    rgb = torch.empty(V * 3 * W * H, device="cuda")
+    T = torch.empty(V * W * H, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, args.warmup)):
+        ras.preprocess(ds, cams, opts)
+        ras.bin_sort()
+        ras.render_fwd(rgb, T)
+    steps = max(2, args.steps // 4)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    t_s = time.perf_counter()
+    stage = np.zeros(3)
+    for _ in range(steps):
+        ev[0].record(stream)
+        ras.preprocess(ds, cams, opts)
+        ev[1].record(stream)
+        ras.bin_sort()
+        ev[2].record(stream)
+        ras.render_fwd(rgb, T)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        stage += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+    dt = time.perf_counter() - t_s
+    free1, _ = torch.cuda.mem_get_info()
+    code, _ = ras.status()
+    out = {"n_prims": scene.n, "K": scene.K, "views": V, "width": W, "height": H,
+           "mpix_s": round(steps * V * W * H / dt / 1e6, 2), "ms_per_step": round(dt * 1e3 / steps, 3),
+           "ms_breakdown": {k: round(float(v) / steps, 3) for k, v in zip(["preprocess", "bin_sort", "render_fwd"], stage)},
+           "pairs_all_views_max": need, "scene_bytes": scene.nbytes(),
+           "workspace_bytes": Rasterizer.size_query(scene.n, scene.K, W, H, V, cap),
+           "device_bytes_in_use": int(total - free1), "device_bytes_before_workspace": int(total - free0),
+           "status": int(code), "fwd_bwd_it_per_s": None}
+    log(f"c5: {out}")
+    ras.close()
+    del ds, rgb, T
+    torch.cuda.empty_cache()
     return out
 
 
@@ -357,13 +466,16 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
-    ap.add_argument("--phases", default="fwd,serve",
-                    help="fwd, fwdbwd (backward switched off), serve, ksweep, sortacc, mesh, train")
+    ap.add_argument("--phases", default="fwd,c3small,c5,serve",
+                    help="fwd, fwdbwd (backward switched off), c3small (1297x840), c5 (3M DRKs K=16, 8 views), "
+                         "serve, ksweep, sortacc, mesh, train")
     ap.add_argument("--ksweep", default="3,5,8,16", help="radial basis counts of the ksweep phase")
     ap.add_argument("--streams", type=int, default=3,
                     help="frames in flight: consecutive frames alternate over this many workspaces and streams")
-    ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the Poisson arrival trace")
-    ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="length of the headline Poisson trace")
+    ap.add_argument("--serve-rates", default="200,800,1600,3200,6400",
+                    help="request arrival rates (1/s): the first is the headline point, the rest the load sweep")
+    ap.add_argument("--sweep-seconds", type=float, default=3.0, help="length of each sweep trace")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle sample budget (0 = skip)")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU baseline)")
     args = ap.parse_args()
@@ -421,28 +533,45 @@ def main():
             log(f"fwd+bwd unavailable: {e}")
 
     work = raster_work(ras, ds, frames, opts, args, rgb, T)
-    pairs_last = int(ras.export("pair_tiles").numel())
     fwd = result.get("fwd")
-    roofline = None
+    roofline, kernels_hbm = None, None
     if fwd is not None:
-        achieved = work["flops"] / (float(fwd["ms"][:, 2].mean()) / 1e3) / 1e12   # per-launch work / launch time
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
-                    "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": raster_traffic(),
-                    "kernel": "k_render_fwd", "avg_launch_ms": round(float(fwd["ms"][:, 2].mean()), 4),
+        # the raster's own launch time: from the one-frame-in-flight run (no other frame's kernels on
+        # the GPU), HIP events on the stream the kernel is launched on
+        one = result.get("fwd1", fwd)
+        iso_ms = float(one["ms"][:, 2].mean())
+        achieved = work["flops"] / (iso_ms / 1e3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": raster_traffic(),
+                    "kernel": "k_render_fwd", "avg_launch_ms": round(iso_ms, 4),
+                    "launch": "one frame in flight, longest tile lists first",
+                    "peak_nonpacked": round(VALU_NONPACKED_TFLOPS, 1),
+                    "frac_nonpacked": round(achieved / VALU_NONPACKED_TFLOPS, 4),
+                    "flops_per_launch": int(work["flops"]),
                     "listed_pairs_per_launch": work["listed"],
                     "hit_evaluations_per_launch": work["hits"],
                     "kernel_evaluations_per_launch": work["kernels"],
                     "contributors_per_launch": work["contributors"],
                     "emitted_per_launch": work["emitted"]}
         if "fwd1" in result:
-            iso_ms = float(result["fwd1"]["ms"][:, 2].mean())
-            iso = work["flops"] / (iso_ms / 1e3) / 1e12
-            # the same launches with one frame in flight (no other frame's kernels sharing the GPU)
-            roofline["isolated"] = {"avg_launch_ms": round(iso_ms, 4), "achieved": round(iso, 3),
-                                    "frac": round(iso / VALU_PEAK_TFLOPS, 4)}
+            fl_ms = float(fwd["ms"][:, 2].mean())
+            # the same launches beside the other frames in flight (they share the CUs)
+            roofline["in_flight"] = {"avg_launch_ms": round(fl_ms, 4),
+                                     "achieved": round(work["flops"] / (fl_ms / 1e3) / 1e12, 3)}
+        ncol = 3 * (scene.sh_degree + 1) ** 2 if scene.sh_degree >= 0 else 3
+        tiles = ((W + 15) // 16) * ((H + 15) // 16)
+        kernels_hbm = {}
+        for name, col, nbytes in (
+                ("preprocess", 0, preprocess_bytes(scene.n, work["visible_mean"], K, ncol)),
+                ("bin_sort", 1, bin_sort_bytes(work["visible_mean"], work["pairs_mean"], tiles))):
+            t = float(one["ms"][:, col].mean())
+            gbs = nbytes / (t / 1e3) / 1e9
+            kernels_hbm[name] = {"ms": round(t, 4), "bytes": int(nbytes), "GB_s": round(gbs, 1),
+                                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
         log(f"raster work: {work['listed'] / 1e6:.1f}M listed, {work['hits'] / 1e6:.1f}M hits, "
             f"{work['kernels'] / 1e6:.1f}M kernel evaluations, {work['contributors'] / 1e6:.1f}M "
-            f"contributors, {work['emitted'] / 1e6:.1f}M emitted per view -> {achieved:.2f} TFLOP/s")
+            f"contributors, {work['emitted'] / 1e6:.1f}M emitted per view -> {achieved:.2f} TFLOP/s "
+            f"in {iso_ms:.3f} ms; preprocess / bin-sort HBM {kernels_hbm}")
 
     # CPU oracle on a bounded sample of the same workload (first timed frame)
     cpu = None
@@ -494,6 +623,14 @@ def main():
     if "mesh" in phases:
         mesh = mesh_phase(args, W, H)
         torch.cuda.empty_cache()
+    c3_small = None
+    if "c3small" in phases:
+        c3_small = c3_small_phase(args, ds, opts)
+    c5 = None
+    if "c5" in phases:
+        del ds
+        torch.cuda.empty_cache()
+        c5 = c5_phase(args, opts)
     serve = None
     if "serve" in phases and not args.profile:
         serve = serve_phase(args, opts)
@@ -510,18 +647,25 @@ def main():
         "config": {"workload": f"{scene.n} DRKs (K={K}, SH3) in 64 anisotropic clusters of a 20-unit box, "
                                f"{W}x{H}, camera path inside the box, one view per step, {args.streams} consecutive "
                                f"frames in flight on separate streams",
-                   "n_prims": scene.n, "K": K, "width": W, "height": H, "pairs_per_view": pairs_last,
+                   "n_prims": scene.n, "K": K, "width": W, "height": H,
+                   "pairs_per_view": {"max": work["pairs_max"], "mean": round(work["pairs_mean"], 1)},
+                   "visible_per_view_mean": round(work["visible_mean"], 1),
                    "frames_in_flight": args.streams,
                    "launch_order": "row-major" if args.streams > 1 else "longest lists first",
                    "one_frame_launch_order": "longest lists first"},
         "one_frame_in_flight_mpix_s": round(result["fwd1"]["mpix"], 3) if "fwd1" in result else None,
         "fwd_bwd_it_per_s": round(result["fwdbwd"]["its"], 3) if "fwdbwd" in result else None,
-        "ms_breakdown": {k: round(float(fwd["ms"][:, i].mean()), 4) for i, k in
+        "ms_breakdown": {k: round(float(result.get("fwd1", fwd)["ms"][:, i].mean()), 4) for i, k in
                          enumerate(["preprocess", "bin_sort", "render_fwd"])} if fwd else None,
         "roofline": roofline,
+        "kernels_hbm": kernels_hbm,
         "cpu_baseline": cpu,
         "serve": serve,
     }
+    if c3_small is not None:
+        line["c3_1297x840"] = c3_small
+    if c5 is not None:
+        line["c5_3m_k16_8x1080p"] = c5
     if ksweep is not None:
         line["ksweep"] = ksweep
     if sortacc is not None:
@@ -536,11 +680,14 @@ def main():
 
 
 def serve_phase(args, opts):
-    """Continuous-batching server vs the plain sequential renderer on the same Poisson trace: 16
-    resident scenes of 50k-1M DRKs, resolutions drawn from {256^2, 800^2, 1297x840, 1920x1080}."""
+    """Continuous-batching server vs the plain sequential renderer on the same Poisson traces: 16
+    resident scenes of 50k-1M DRKs, resolutions drawn from {256^2, 800^2, 1297x840, 1920x1080}.  The
+    first rate is the headline point (its trace --serve-seconds long); the others sweep the offered
+    load past the plain renderer's saturation (--sweep-seconds each)."""
     import torch
     from drk_synth import camera_from_yaw_pitch, config_c4_scenes
     from paper_2412_11752_amd import DRKScene, Rasterizer
+    from paper_2412_11752_amd._lib import DRK_EAGAIN, check
     from paper_2412_11752_amd.serving import Server
 
     t0 = time.time()
@@ -549,16 +696,21 @@ def serve_phase(args, opts):
     log(f"serve: {len(scenes)} scenes, {sum(h.n for h in hosts) / 1e6:.2f}M DRKs total, gen {time.time() - t0:.1f}s")
     res = [(256, 256), (800, 800), (1297, 840), (1920, 1080)]
     rng = np.random.default_rng(33)
-    n_req = int(args.serve_seconds * args.serve_rate)
-    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, n_req))
-    which = rng.integers(0, len(scenes), n_req)
-    rsel = rng.integers(0, len(res), n_req)
-    cams = []
-    for i in range(n_req):
-        W, H = res[rsel[i]]
-        pos = rng.uniform(-8.0, 8.0, 3)
-        cams.append(camera_from_yaw_pitch(pos, rng.uniform(0, 2 * math.pi), math.radians(rng.uniform(-30, 30)), W, H))
-    srv = Server(max_inflight=8, use_graphs=True, opts=opts)
+
+    def trace(rate, seconds):
+        n_req = max(1, int(seconds * rate))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        which = rng.integers(0, len(scenes), n_req)
+        rsel = rng.integers(0, len(res), n_req)
+        cams = []
+        for i in range(n_req):
+            W, H = res[rsel[i]]
+            pos = rng.uniform(-8.0, 8.0, 3)
+            cams.append(camera_from_yaw_pitch(pos, rng.uniform(0, 2 * math.pi), math.radians(rng.uniform(-30, 30)),
+                                              W, H))
+        return arrivals, which, cams
+
+    srv = Server(max_inflight=8, use_graphs=True, opts=opts, queue_capacity=1 << 16)
     sids = [srv.add_scene(d) for d in scenes]
     # warm every (scene, resolution) workspace and graph once, untimed
     for si in range(len(scenes)):
@@ -566,63 +718,93 @@ def serve_phase(args, opts):
             cam = camera_from_yaw_pitch((0.0, 0.0, 0.0), 0.3, 0.1, W, H)
             out = torch.empty(3 * W * H, device="cuda")
             srv.wait(srv.submit(sids[si], cam, out))
-    torch.cuda.synchronize()
-    outs = [None] * n_req
-    rids = [0] * n_req
-    t_base = time.perf_counter()
-    for i in range(n_req):
-        while time.perf_counter() - t_base < arrivals[i]:
-            pass
-        W, H = cams[i].width, cams[i].height
-        outs[i] = torch.empty(3 * W * H, device="cuda")
-        rids[i] = srv.submit(sids[which[i]], cams[i], outs[i])
-    stats = [srv.wait(r) for r in rids]
-    lat = np.array([(st["done_us"] - st["submit_us"]) / 1e3 for st in stats])
-    span = (max(st["done_us"] for st in stats) - min(st["submit_us"] for st in stats)) / 1e6
-    mpix = sum(st["width"] * st["height"] for st in stats) / 1e6
-    served = {"mpix_s": round(mpix / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-              "p99_ms": round(float(np.percentile(lat, 99)), 3), "makespan_s": round(span, 3),
-              "failed": int(sum(st["status"] != 0 for st in stats))}
-    log(f"served: {n_req} requests, {served}")
-    # spot check: served results are bitwise the plain renderer's
     rasters = {}
 
-    def plain(i):
-        key = (which[i], cams[i].width, cams[i].height)
+    def plain(which_i, cam):
+        key = (which_i, cam.width, cam.height)
         if key not in rasters:
-            h = hosts[which[i]]
-            rasters[key] = Rasterizer(h.n, h.K, cams[i].width, cams[i].height, pair_capacity=1 << 22)
-        r = rasters[key]
-        rgb, _ = r.forward(scenes[which[i]], [cams[i]], opts)
+            h = hosts[which_i]
+            rasters[key] = Rasterizer(h.n, h.K, cam.width, cam.height, pair_capacity=1 << 22)
+        rgb, _ = rasters[key].forward(scenes[which_i], [cam], opts)
         return rgb
 
-    checked = 0
-    for i in rng.choice(n_req, min(12, n_req), replace=False):
-        assert torch.equal(plain(int(i)).reshape(-1), outs[int(i)]), f"served request {i} differs"
-        checked += 1
-    srv.close()
-    del outs
+    for si in range(len(scenes)):         # warm the plain renderer's workspaces too
+        for (W, H) in res:
+            plain(si, camera_from_yaw_pitch((0.0, 0.0, 0.0), 0.3, 0.1, W, H))
     torch.cuda.synchronize()
-    # plain sequential per-request rendering on the same trace (workspaces already warm)
-    for i in range(min(n_req, 64)):
-        plain(i)
-    torch.cuda.synchronize()
-    done = np.zeros(n_req)
-    t_base = time.perf_counter()
-    for i in range(n_req):
-        while time.perf_counter() - t_base < arrivals[i]:
-            pass
-        plain(i)
+
+    def run_served(arrivals, which, cams):
+        n_req = len(cams)
+        outs, rids = [None] * n_req, [0] * n_req
+        t_base = time.perf_counter()
+        for i in range(n_req):
+            while time.perf_counter() - t_base < arrivals[i]:
+                pass
+            outs[i] = torch.empty(3 * cams[i].width * cams[i].height, device="cuda")
+            while True:                      # a full queue pushes back on the client
+                code, rids[i] = srv.try_submit(sids[which[i]], cams[i], outs[i])
+                if code != DRK_EAGAIN:
+                    break
+                time.sleep(50e-6)
+            check(code, "drk_serve_submit")
+        stats = [srv.wait(r) for r in rids]
+        lat = np.array([(st["done_us"] - st["submit_us"]) / 1e3 for st in stats])
+        span = (max(st["done_us"] for st in stats) - min(st["submit_us"] for st in stats)) / 1e6
+        mpix = sum(st["width"] * st["height"] for st in stats) / 1e6
+        return outs, {"mpix_s": round(mpix / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 3), "makespan_s": round(span, 3),
+                      "failed": int(sum(st["status"] != 0 for st in stats))}, mpix
+
+    def run_plain(arrivals, which, cams, mpix):
+        n_req = len(cams)
+        done = np.zeros(n_req)
+        t_base = time.perf_counter()
+        for i in range(n_req):
+            while time.perf_counter() - t_base < arrivals[i]:
+                pass
+            plain(which[i], cams[i])
+            torch.cuda.synchronize()
+            done[i] = time.perf_counter() - t_base
+        lat = (done - arrivals) * 1e3
+        span = done[-1] - arrivals[0]
+        return {"mpix_s": round(float(mpix / span), 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3), "makespan_s": round(float(span), 3)}
+
+    rates = [float(r) for r in args.serve_rates.split(",") if r]
+    points, checked = [], 0
+    for k, rate in enumerate(rates):
+        seconds = args.serve_seconds if k == 0 else args.sweep_seconds
+        arrivals, which, cams = trace(rate, seconds)
+        outs, served, mpix = run_served(arrivals, which, cams)
+        if k == 0:
+            # spot check: served results are bitwise the plain renderer's
+            for i in rng.choice(len(cams), min(12, len(cams)), replace=False):
+                assert torch.equal(plain(which[int(i)], cams[int(i)]).reshape(-1), outs[int(i)]), \
+                    f"served request {i} differs"
+                checked += 1
+        del outs
         torch.cuda.synchronize()
-        done[i] = time.perf_counter() - t_base
-    lat_p = (done - arrivals) * 1e3
-    span_p = done[-1] - arrivals[0]
-    plain_res = {"mpix_s": round(mpix / span_p, 2), "p50_ms": round(float(np.percentile(lat_p, 50)), 3),
-                 "p99_ms": round(float(np.percentile(lat_p, 99)), 3), "makespan_s": round(span_p, 3)}
-    log(f"plain sequential: {plain_res}")
-    return {"requests": n_req, "rate_per_s": args.serve_rate, "trace_s": args.serve_seconds,
-            "scenes": len(scenes), "resolutions": res, "served": served, "plain_sequential": plain_res,
-            "bitwise_checked": checked}
+        plain_res = run_plain(arrivals, which, cams, mpix)
+        offered = mpix / float(arrivals[-1])
+        pt = {"rate_per_s": rate, "trace_s": seconds, "requests": len(cams), "offered_mpix_s": round(offered, 2),
+              "served": served, "plain_sequential": plain_res}
+        # keeping up: the last result arrives within 10% (and 50 ms) of the end of the trace
+        lim = 1.1 * float(arrivals[-1] - arrivals[0]) + 0.05
+        pt["served_keeps_up"] = bool(served["makespan_s"] <= lim and served["failed"] == 0)
+        pt["plain_keeps_up"] = bool(plain_res["makespan_s"] <= lim)
+        log(f"serve {rate:.0f} req/s x {seconds:.0f}s ({len(cams)} requests, offered {offered:.0f} Mpix/s): "
+            f"served {served}, plain {plain_res}")
+        points.append(pt)
+    srv.close()
+    for r in rasters.values():
+        r.close()
+    head = points[0]
+    keep = lambda key: max([p["rate_per_s"] for p in points if p[key]], default=None)
+    return {"requests": head["requests"], "rate_per_s": head["rate_per_s"], "trace_s": head["trace_s"],
+            "scenes": len(scenes), "resolutions": res, "served": head["served"],
+            "plain_sequential": head["plain_sequential"], "bitwise_checked": checked,
+            "sweep": points[1:], "max_rate_kept_up": {"served": keep("served_keeps_up"),
+                                                      "plain_sequential": keep("plain_keeps_up")}}
 
 
 if __name__ == "__main__":

@@ -125,6 +125,9 @@ typedef struct drk_opts {
                              the launch does not end on a few long tiles; 1 row-major, which leaves
                              that tail to kernels of other streams (frames rendered concurrently
                              overlap better).  Images are identical either way.                   */
+  int32_t counters;       /* 1: drk_render_fwd also writes the per-pixel work counters that
+                             drk_ws_export 5-9 read (instrumentation); 0 (default): it writes only
+                             the image and the transmittance.                                       */
 } drk_opts;
 
 typedef struct drk_ws drk_ws;
@@ -251,6 +254,12 @@ drk_status drk_mesh_to_drk(const float* vertices, int64_t nv, const int32_t* fac
 drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, const float* dL_drgb,
                           const drk_scene_grad* grads, void* stream);
 
+/* Number of drk_preprocess calls made on the workspace so far (host-side, no synchronisation).
+ * The lists, records and per-pixel state drk_render_bwd replays belong to the latest one, so a
+ * caller that keeps a forward output for a later backward records this value with it and checks
+ * that it is unchanged before calling drk_render_bwd.                                          */
+drk_status drk_ws_generation(drk_ws* ws, uint64_t* generation);
+
 /* Synchronises `stream` and reports the status word: DRK_OK, or DRK_EOVERFLOW with
  * *pairs_needed set to the largest pair count any view of the last drk_bin_sort needed.      */
 drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed);
@@ -263,6 +272,7 @@ drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed);
  *   2 pair tiles   uint32 [P]   (sorted)
  *   3 pair prims   uint32 [P]   (sorted)
  *   4 ranges       uint32 [2*tiles] (start, end per tile)
+ * Exports 5-9 need a forward rendered with drk_opts.counters = 1 (else DRK_EINVAL):
  *   5 emitted      int32  [H*W] (contributions composited per pixel, from the last forward)
  *   6 consumed     int32  [H*W] (list entries read per pixel before it terminated)
  *   7 contributors int32  [H*W] (entries with alpha >= alpha_min that entered the cache)

@@ -15,15 +15,14 @@
 
 namespace drk {
 
-static thread_local std::string g_err;
+// last error message of this thread (fixed storage: reporting an error allocates nothing)
+static thread_local char g_err[512];
 
 void set_error(const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
   va_end(ap);
-  g_err = buf;
 }
 
 // kernels in other translation units
@@ -39,7 +38,7 @@ hipError_t launch_pair_keys(const Views*, const OptsDev&, int, const uint32_t*, 
 hipError_t gather_pairs(const uint32_t*, const uint32_t*, const uint32_t*, const uint64_t*, uint32_t*, uint32_t*,
                         hipStream_t);
 hipError_t launch_trace_metrics(const int32_t*, const float*, int64_t, int, double*, hipStream_t);
-hipError_t radix_sort(int, const uint64_t*, uint32_t* const*, uint32_t* const*, uint32_t*, uint32_t*, hipStream_t);
+hipError_t radix_sort(int, const uint64_t*, uint32_t* const*, uint32_t* const*, int, uint32_t*, uint32_t*, hipStream_t);
 hipError_t scan_counts(const uint32_t*, const uint32_t*, const uint64_t*, int64_t, uint32_t*, uint64_t*, uint64_t*,
                        uint64_t*, int64_t, uint32_t*, hipStream_t);
 hipError_t compact_visible(const uint32_t*, const uint32_t*, int64_t, uint32_t*, uint64_t*, uint64_t*, uint64_t*,
@@ -108,6 +107,10 @@ struct drk_ws {
   Views views{};
   OptsDev opts{};
   bool have_pre = false, have_bins = false;
+  bool counted = false;           // the last forward wrote the per-pixel counters (exports 5-9)
+  bool lean = false;              // forward-only layout: no backward, counter or serving arrays
+  bool lean_keys = false;         // (lean layout) keep the per-tile key data (key_mode 1, 2)
+  uint64_t generation = 0;        // preprocess calls so far: identifies the frame the lists belong to
 };
 
 namespace {
@@ -158,22 +161,22 @@ size_t layout(drk_ws* ws, bool assign, char* base) {
   SLOT(ck, uint32_t, N)
   SLOT(cv, uint32_t, N)
   SLOT(status, uint32_t, V)
-  SLOT(n_emit, int32_t, V * px)
-  SLOT(consumed, int32_t, V * px)
-  SLOT(contrib, int32_t, V * px)
-  SLOT(work_px, int32_t, 2 * V * px)
+  SLOT(n_emit, int32_t, ws->lean ? 0 : V * px)
+  SLOT(consumed, int32_t, ws->lean ? 0 : V * px)
+  SLOT(contrib, int32_t, ws->lean ? 0 : V * px)
+  SLOT(work_px, int32_t, ws->lean ? 0 : 2 * V * px)
   SLOT(hist, uint32_t, 256 * 1024)
   SLOT(tot, uint32_t, 256)
-  SLOT(grad_rec, float, V * N * grad_fields(ws->K))
+  SLOT(grad_rec, float, ws->lean ? 0 : V * N * grad_fields(ws->K))
   SLOT(views_dev, Views, 1)
   SLOT(work, uint32_t, V * N)
   SLOT(counters, uint32_t, 2 * V)
   SLOT(span_meta, uint2, V * N)
   SLOT(span_rows, uint32_t, V * (size_t)ws->row_cap)
-  SLOT(out_rgb, float, 3 * px)
+  SLOT(out_rgb, float, ws->lean ? 0 : 3 * px)
   SLOT(dup_big, uint32_t, N)
   SLOT(dup_count, uint32_t, 4)
-  SLOT(keygeo, double, V * N * KG_N)
+  SLOT(keygeo, double, (ws->lean && !ws->lean_keys) ? 0 : V * N * KG_N)
   SLOT(tile_order, uint32_t, V * (size_t)ws->max_tiles)
   SLOT(tk, uint32_t, 4 * (size_t)ws->max_tiles)
 #undef SLOT
@@ -263,8 +266,10 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   if (!(opts->alpha_min > 0.0f && opts->alpha_min < 1.0f) || !(opts->alpha_max > 0.0f && opts->alpha_max < 1.0f) ||
       !(opts->T_min > 0.0f && opts->T_min < 1.0f) || !(opts->near_plane > 0.0f) || !(opts->lowpass_sl >= 0.0f) ||
       opts->cache_len < 1 || opts->cache_len > kMaxCache || opts->cull_mode < 0 || opts->cull_mode > 2 ||
-      opts->key_mode < 0 || opts->key_mode > 2 || opts->launch_order < 0 || opts->launch_order > 1) {
-    set_error("invalid drk_opts (cache_len must be in [1, %d], key_mode in [0, 2], launch_order 0 or 1)", kMaxCache);
+      opts->key_mode < 0 || opts->key_mode > 2 || opts->launch_order < 0 || opts->launch_order > 1 ||
+      opts->counters < 0 || opts->counters > 1) {
+    set_error("invalid drk_opts (cache_len must be in [1, %d], key_mode in [0, 2], launch_order and counters 0 or 1)",
+              kMaxCache);
     return DRK_EINVAL;
   }
   SceneDev sc;
@@ -278,6 +283,7 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   od.near_plane = opts->near_plane; od.lowpass_sl = opts->lowpass_sl; od.cache_len = opts->cache_len;
   od.cull_mode = opts->cull_mode; od.validate = opts->validate; od.key_mode = opts->key_mode;
   od.launch_order = opts->launch_order;
+  od.counters = opts->counters;
   drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
   if (st) return st;
   if ((st = check_hip(fill_u32(ws->counters, 0u, 2 * ws->max_views, s), "clear counters"))) return st;
@@ -291,6 +297,7 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   ws->opts = od;
   ws->have_pre = true;
   ws->have_bins = false;
+  ++ws->generation;
   return DRK_OK;
 }
 
@@ -345,10 +352,11 @@ drk_opts drk_opts_default(void) {
   o.validate = 0;
   o.key_mode = 0;
   o.launch_order = 0;
+  o.counters = 0;
   return o;
 }
 
-const char* drk_last_error(void) { return g_err.c_str(); }
+const char* drk_last_error(void) { return g_err; }
 
 const char* drk_version(void) { return "libdrk 0.1 (gfx950)"; }
 
@@ -438,7 +446,7 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
     if (!tile_keys) {
       uint32_t* kb[5] = {ws->ck, ws->dk_a, ws->dk_b, ws->dk_a, ws->dk_b};
       uint32_t* vb[5] = {ws->cv, ws->dv_a, ws->dv_b, ws->dv_a, ws->dv_b};
-      if ((st = check_hip(radix_sort(32, ws->n_prims, kb, vb, ws->hist, ws->tot, s), "depth sort"))) return st;
+      if ((st = check_hip(radix_sort(32, ws->n_prims, kb, vb, 5, ws->hist, ws->tot, s), "depth sort"))) return st;
       order = ws->dv_b;
     }
     // 2. offsets of each primitive's pairs in that order
@@ -464,7 +472,7 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
       // 3b. stable sort of the pair keys (values: pair ids), then tile and primitive in key order
       uint32_t* kk[5] = {ws->pk_tmp, ws->pk_tmp2, ws->pk_tmp, ws->pk_tmp2, ws->pk_tmp};
       uint32_t* kv[5] = {nullptr, ws->pv_tmp2, ws->pv_tmp, ws->pv_tmp2, ws->pv_tmp};
-      if ((st = check_hip(radix_sort(32, ws->n_eff + v, kk, kv, ws->hist, ws->tot, s), "key sort"))) return st;
+      if ((st = check_hip(radix_sort(32, ws->n_eff + v, kk, kv, 5, ws->hist, ws->tot, s), "key sort"))) return st;
       if ((st = check_hip(gather_pairs(ws->pv_tmp, fk, fv, ws->n_eff + v, ws->pk_tmp2, ws->pv_tmp2, s), "gather")))
         return st;
     }
@@ -473,9 +481,10 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
     uint32_t* src_v = tile_keys ? ws->pv_tmp2 : ws->pv_tmp;
     uint32_t* mid_k = tile_keys ? ws->pk_tmp : ws->pk_tmp2;
     uint32_t* mid_v = tile_keys ? ws->pv_tmp : ws->pv_tmp2;
-    uint32_t* pk[3] = {src_k, passes == 2 ? mid_k : fk, fk};
-    uint32_t* pv[3] = {src_v, passes == 2 ? mid_v : fv, fv};
-    if ((st = check_hip(radix_sort(bits, ws->n_eff + v, pk, pv, ws->hist, ws->tot, s), "tile sort"))) return st;
+    // the last pass writes fk/fv; up to 17 key bits (images up to 8192 x 2176) take three passes
+    uint32_t* pk[4] = {src_k, passes == 2 ? mid_k : fk, passes == 2 ? fk : mid_k, fk};
+    uint32_t* pv[4] = {src_v, passes == 2 ? mid_v : fv, passes == 2 ? fv : mid_v, fv};
+    if ((st = check_hip(radix_sort(bits, ws->n_eff + v, pk, pv, 4, ws->hist, ws->tot, s), "tile sort"))) return st;
     // 5. ranges
     uint32_t* rg = ws->ranges + (size_t)v * 2 * ws->max_tiles;
     if ((st = check_hip(tile_ranges(fk, ws->n_eff + v, rg, ntiles, s), "ranges"))) return st;
@@ -489,7 +498,7 @@ drk_status drk_bin_sort(drk_ws* ws, void* stream) {
     if ((st = check_hip(set_u64(ws->n_prims + 1, (uint64_t)ntiles, s), "tile count"))) return st;
     uint32_t* ok_[3] = {t0, t2, t0};
     uint32_t* ov_[3] = {t1, t3, ws->tile_order + (size_t)v * ws->max_tiles};
-    if ((st = check_hip(radix_sort(16, ws->n_prims + 1, ok_, ov_, ws->hist, ws->tot, s), "tile order"))) return st;
+    if ((st = check_hip(radix_sort(16, ws->n_prims + 1, ok_, ov_, 3, ws->hist, ws->tot, s), "tile order"))) return st;
   }
   ws->have_bins = true;
   return DRK_OK;
@@ -520,6 +529,7 @@ drk_status render_views(drk_ws* ws, float* rgb, float* T_final, int mode, int32_
     if (st) return st;
     off += npx;
   }
+  ws->counted = mode != 0 || ws->opts.counters != 0;
   return DRK_OK;
 }
 
@@ -673,6 +683,12 @@ drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, 
                    "preprocess_bwd");
 }
 
+drk_status drk_ws_generation(drk_ws* ws, uint64_t* generation) {
+  if (!ws || !generation) { set_error("null argument"); return DRK_EINVAL; }
+  *generation = ws->generation;
+  return DRK_OK;
+}
+
 drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed) {
   if (!ws) { set_error("null workspace"); return DRK_EINVAL; }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -692,6 +708,10 @@ drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int6
   const void* src = nullptr;
   int64_t count = 0;
   size_t esize = 4;
+  if (what >= 5 && what <= 9 && !ws->counted) {
+    set_error("per-pixel counters were not written: render with drk_opts.counters = 1");
+    return DRK_EINVAL;
+  }
   switch (what) {
     case 0: src = ws->depth_keys + (size_t)view * ws->max_n; count = N; break;
     case 1: src = ws->tile_counts + (size_t)view * ws->max_n; count = N; break;

@@ -128,9 +128,11 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
 
 // Stable sort of n (device) pairs by key bits [0, key_bits).  Pass p reads bufs[p] and writes
 // bufs[p + 1]; bufs must hold passes + 1 entries.  vin of the first pass may be null (value = index).
-hipError_t radix_sort(int key_bits, const uint64_t* d_n, uint32_t* const* kbufs, uint32_t* const* vbufs,
+hipError_t radix_sort(int key_bits, const uint64_t* d_n, uint32_t* const* kbufs, uint32_t* const* vbufs, int nbufs,
                       uint32_t* hist, uint32_t* tot, hipStream_t s) {
   const int passes = (key_bits + 7) / 8;
+  // pass p reads buffer p and writes buffer p + 1
+  if (key_bits < 1 || key_bits > 32 || passes + 1 > nbufs) return hipErrorInvalidValue;
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
     const int bits = (key_bits - shift) < 8 ? (key_bits - shift) : 8;

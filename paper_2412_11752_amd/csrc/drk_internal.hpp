@@ -74,7 +74,7 @@ struct Views {
 
 struct OptsDev {
   float alpha_min, alpha_max, T_min, near_plane, lowpass_sl;
-  int32_t cache_len, cull_mode, validate, key_mode, launch_order;
+  int32_t cache_len, cull_mode, validate, key_mode, launch_order, counters;
 };
 
 // Per (view, primitive) float64 data of the per-tile pre-sort keys (key_mode 1, 2), written by the

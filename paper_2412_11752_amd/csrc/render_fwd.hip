@@ -17,7 +17,9 @@ namespace drk {
 // aux2 = trace_z or normal).
 constexpr int kFwdPlain = 0, kFwdTrace = 1, kFwdDepthNormal = 2;
 
-template <int K, int MODE>
+// COUNT: also write the per-pixel work counters (instrumentation; the production launch of MODE 0
+// leaves them out).
+template <int K, int MODE, bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp,
                                                        const uint32_t* __restrict__ tile_order, OptsDev opt,
@@ -76,19 +78,19 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
       for (uint64_t m = mask; m; m &= m - 1) {
         const int i = __builtin_ctzll(m);
         const float* r = reinterpret_cast<const float*>(lds + i * RF4);
-        ++n_hit;
+        if constexpr (COUNT) ++n_hit;
         float at, Z;
         if (!drk_eval<K>(r, pix, rp, at, Z)) continue;
-        ++n_full;
+        if constexpr (COUNT) ++n_full;
         if (at >= rp.alpha_min) {
-          ++n_contrib;
+          if constexpr (COUNT) ++n_contrib;
           // pop the head (emit it), then insert the newcomer
           const float a = cache.pay[0][0];
           if (a > 0.0f) {
             const float test = T * (1.0f - a);
             if (test < rp.T_min) {
               done = true;
-              consumed = (int)(b0 - start) + i + 1;
+              if constexpr (COUNT) consumed = (int)(b0 - start) + i + 1;
               break;
             }
             const float* c = records + (size_t)__float_as_uint(cache.pay[1][0]) * RF + R_RGB;
@@ -159,11 +161,13 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
     rgb[plane + pidx] = fmaf(T, cam.bg[1], C1);
     rgb[2 * plane + pidx] = fmaf(T, cam.bg[2], C2);
     if (T_out) T_out[pidx] = T;
-    n_emit_out[pidx] = n_emit;
-    consumed_out[pidx] = consumed;
-    contrib_out[pidx] = n_contrib;
-    work_out[pidx] = n_hit;                 // entries whose hit was evaluated (wave box passed)
-    work_out[plane + pidx] = n_full;        // entries that went through the full kernel
+    if constexpr (COUNT) {
+      n_emit_out[pidx] = n_emit;
+      consumed_out[pidx] = consumed;
+      contrib_out[pidx] = n_contrib;
+      work_out[pidx] = n_hit;               // entries whose hit was evaluated (wave box passed)
+      work_out[plane + pidx] = n_full;      // entries that went through the full kernel
+    }
     if constexpr (TRACE) trace_n[pidx] = n_emit;
     if constexpr (GEOM) {
       static_cast<float*>(aux0)[pidx] = Dz;
@@ -179,19 +183,23 @@ static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, con
                                int ntiles, const uint32_t* order, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
                                int32_t* wk, int mode, void* a0, int32_t* a1, float* a2, int cap, hipStream_t s) {
   if (mode == kFwdTrace)
-    hipLaunchKernelGGL((k_render_fwd<K, kFwdTrace>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, order, opt,
-                       rgb, T, ne, cons, nc, wk, a0, a1, a2, cap);
+    hipLaunchKernelGGL((k_render_fwd<K, kFwdTrace, true>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, order,
+                       opt, rgb, T, ne, cons, nc, wk, a0, a1, a2, cap);
   else if (mode == kFwdDepthNormal)
-    hipLaunchKernelGGL((k_render_fwd<K, kFwdDepthNormal>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam,
-                       order, opt, rgb, T, ne, cons, nc, wk, a0, nullptr, a2, 0);
+    hipLaunchKernelGGL((k_render_fwd<K, kFwdDepthNormal, true>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims,
+                       cam, order, opt, rgb, T, ne, cons, nc, wk, a0, nullptr, a2, 0);
+  else if (opt.counters)
+    hipLaunchKernelGGL((k_render_fwd<K, kFwdPlain, true>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam,
+                       order, opt, rgb, T, ne, cons, nc, wk, nullptr, nullptr, nullptr, 0);
   else
-    hipLaunchKernelGGL((k_render_fwd<K, kFwdPlain>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, order, opt,
-                       rgb, T, ne, cons, nc, wk, nullptr, nullptr, nullptr, 0);
+    hipLaunchKernelGGL((k_render_fwd<K, kFwdPlain, false>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam,
+                       order, opt, rgb, T, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
   return hipGetLastError();
 }
 
-// mode 0: colour only; 1: trace (a0 = counts, a1 = indices, a2 = depths, cap entries per pixel);
-// 2: depth (a0) and normal (a2) channels.  Pointers are those of this view.
+// mode 0: colour only (per-pixel counters when opt.counters); 1: trace (a0 = counts, a1 = indices,
+// a2 = depths, cap entries per pixel); 2: depth (a0) and normal (a2) channels.  Modes 1 and 2 always
+// write the counters.  Pointers are those of this view.
 hipError_t launch_render_fwd(int K, const float* records, const uint32_t* ranges, const uint32_t* prims,
                              const CamDev* cam, int ntiles, const uint32_t* order, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons,
                              int32_t* nc, int32_t* wk, int mode, void* a0, int32_t* a1, float* a2, int cap, hipStream_t s) {

@@ -69,6 +69,7 @@ struct Request {
   int status = DRK_OK;
   bool done = false;
   int retries = 0;
+  int bypassed = 0;                // times a later request was admitted while this one waited
   WsEntry* ws = nullptr;
 };
 
@@ -130,8 +131,12 @@ void drop_entry(drk_server* s, WsEntry* e) {
 }
 
 // Finds an idle resident workspace for the request or creates one within the budget (evicting idle
-// ones, least recently used first).  Returns null when it does not fit now.
-WsEntry* acquire(drk_server* s, Request* r) {
+// ones, least recently used first).  Returns null when it cannot be admitted now; *never is then set
+// (with the error in *why) when it cannot be admitted at all: its workspace size is invalid or
+// exceeds the whole budget, or creating it fails while no other workspace is busy (nothing that
+// could free memory is running).
+WsEntry* acquire(drk_server* s, Request* r, bool* never, int* why) {
+  *never = false;
   const int W = r->cam.width, H = r->cam.height;
   for (WsEntry* e : s->pool)
     if (!e->busy && e->scene == r->scene && e->W == W && e->H == H) {
@@ -140,6 +145,20 @@ WsEntry* acquire(drk_server* s, Request* r) {
     }
   const int64_t cap = initial_capacity(s, r->scene, W, H);
   const size_t need = ws_size(s, r->scene, W, H, cap);
+  if (need == (size_t)-1) {
+    *never = true;
+    *why = DRK_EINVAL;
+    return nullptr;
+  }
+  if (need > (size_t)s->budget) {
+    *never = true;
+    *why = DRK_ENOMEM;
+    return nullptr;
+  }
+  size_t idle = 0;
+  for (WsEntry* e : s->pool)
+    if (!e->busy) idle += e->bytes;
+  if (s->ws_bytes - idle + need > (size_t)s->budget) return nullptr;   // not even after evicting every idle one
   while (s->ws_bytes + need > (size_t)s->budget) {
     WsEntry* victim = nullptr;
     for (WsEntry* e : s->pool)
@@ -149,7 +168,21 @@ WsEntry* acquire(drk_server* s, Request* r) {
   }
   const drk_scene& sc = s->scenes[r->scene].sc;
   drk_ws* ws = nullptr;
-  if (drk_ws_create(std::max<int64_t>(sc.n, 1), sc.K, 1, W, H, cap, &ws) != DRK_OK) return nullptr;
+  if (drk_ws_create(std::max<int64_t>(sc.n, 1), sc.K, 1, W, H, cap, &ws) != DRK_OK) {
+    bool any_busy = false;
+    for (WsEntry* e : s->pool) any_busy = any_busy || e->busy;
+    if (!any_busy) {
+      // free what is idle and try once more before giving up on the request
+      while (!s->pool.empty()) drop_entry(s, s->pool.front());
+      if (drk_ws_create(std::max<int64_t>(sc.n, 1), sc.K, 1, W, H, cap, &ws) != DRK_OK) {
+        *never = true;
+        *why = DRK_ENOMEM;
+        return nullptr;
+      }
+    } else {
+      return nullptr;
+    }
+  }
   WsEntry* e = new WsEntry();
   e->ws = ws;
   e->scene = r->scene; e->W = W; e->H = H; e->cap = cap;
@@ -232,6 +265,11 @@ void finish(drk_server* s, Slot& slot) {
   complete(s, r, (status & ST_INVALID) ? DRK_EINVAL : DRK_OK);
 }
 
+// Requests behind the head that may be admitted while the head waits for memory, and how many
+// times the head may be passed over before the scheduler waits for it.
+constexpr int kLookahead = 16;
+constexpr int kMaxBypass = 8;
+
 void scheduler(drk_server* s) {
   hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
@@ -239,11 +277,39 @@ void scheduler(drk_server* s) {
     for (Slot& sl : s->slots)
       if (sl.req && hipEventQuery(sl.ev) == hipSuccess) finish(s, sl);
     for (Slot& sl : s->slots) {
-      if (sl.req || s->pending.empty()) continue;
-      Request* r = s->pending.front();
-      WsEntry* e = acquire(s, r);
-      if (!e) break;                       // waits for memory to free up (arrival order kept)
-      s->pending.pop_front();
+      if (sl.req) continue;
+      // the head if it fits now; else a later request that fits, while the head has been passed
+      // over fewer than kMaxBypass times
+      Request* r = nullptr;
+      WsEntry* e = nullptr;
+      Request* head = nullptr;
+      int scanned = 0;
+      for (auto it = s->pending.begin(); it != s->pending.end() && scanned < kLookahead;) {
+        Request* q = *it;
+        bool never = false;
+        int why = DRK_OK;
+        WsEntry* got = acquire(s, q, &never, &why);
+        if (never) {
+          it = s->pending.erase(it);
+          q->start_us = now_us();
+          complete(s, q, why);
+          continue;
+        }
+        if (got) {
+          s->pending.erase(it);
+          r = q;
+          e = got;
+          break;
+        }
+        if (!head) {
+          head = q;
+          if (q->bypassed >= kMaxBypass) break;   // the head has waited long enough: keep arrival order
+        }
+        ++scanned;
+        ++it;
+      }
+      if (r && head) ++head->bypassed;
+      if (!r) break;                       // nothing fits now: wait for memory to free up
       r->ws = e;
       r->start_us = now_us();
       sl.req = r;

@@ -88,14 +88,16 @@ def camera_struct(cam) -> _lib.Camera:
 
 
 def make_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, near=0.2, lowpass_sl=math.sqrt(0.5),
-              cache_len=8, cull_mode=0, validate=0, key_mode=0, launch_order=0) -> _lib.Opts:
+              cache_len=8, cull_mode=0, validate=0, key_mode=0, launch_order=0, counters=0) -> _lib.Opts:
     """key_mode: 0 / "centre", 1 / "centric", 2 / "nearest" (pre-sort key of the tile lists);
-    launch_order: 0 longest tile lists first, 1 row-major (see drk_opts)."""
+    launch_order: 0 longest tile lists first, 1 row-major; counters: 1 = the forward also writes the
+    per-pixel work counters (exports emitted, consumed, contributors, hits, kernels) (see drk_opts)."""
     o = _lib.Opts()
     o.alpha_min, o.alpha_max, o.T_min, o.near_plane, o.lowpass_sl = alpha_min, alpha_max, T_min, near, lowpass_sl
     o.cache_len, o.cull_mode, o.validate = cache_len, cull_mode, validate
     o.key_mode = KEY_MODES[key_mode] if isinstance(key_mode, str) else int(key_mode)
     o.launch_order = int(launch_order)
+    o.counters = int(counters)
     return o
 
 
@@ -192,6 +194,12 @@ class Rasterizer:
               "drk_render_bwd")
         return g
 
+    def generation(self) -> int:
+        """drk_preprocess calls made on this workspace (identifies the frame its lists belong to)."""
+        g = C.c_uint64()
+        check(lib().drk_ws_generation(self._ws, C.byref(g)), "drk_ws_generation")
+        return int(g.value)
+
     def status(self):
         need = C.c_int64()
         code = lib().drk_ws_status(self._ws, C.c_void_p(_stream_handle()), C.byref(need))
@@ -246,6 +254,7 @@ class DRKRenderFunction(torch.autograd.Function):
                          opacity.detach().contiguous(), color.detach().contiguous(), sh_degree)
         rgb, T = ras.forward(scene, cams, opts)
         ctx.ras = ras
+        ctx.generation = ras.generation()
         ctx.scene = scene
         ctx.save_for_backward(rgb)
         ctx.mark_non_differentiable(T)
@@ -254,6 +263,9 @@ class DRKRenderFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_rgb, g_T):
         rgb, = ctx.saved_tensors
+        if ctx.ras.generation() != ctx.generation:
+            raise RuntimeError("the rasterizer rendered another frame after this forward pass: its lists no "
+                               "longer belong to this output (use one Rasterizer per pending backward)")
         g = ctx.ras.render_bwd(rgb.reshape(-1), g_rgb.contiguous().reshape(-1))
         return (None, None, None, None, *g.tensors())
 

@@ -10,7 +10,7 @@ import torch
 from drk_synth import (Camera, Scene, camera_lookat, config_c3, config_c5, draw_angles, intrinsics_hfov,
                        scene_uniform_box)
 from oracle import drk_oracle as O
-from tests._gpu_util import IMG_TOL, compare_image, gpu_opts, log, need_gpu, oracle_opts
+from tests._gpu_util import IMG_TOL, compare_image, compare_pixels, gpu_opts, log, need_gpu, oracle_opts
 
 pytestmark = pytest.mark.gpu
 
@@ -121,11 +121,7 @@ def _sampled_check(scene, cam, g, prims, n_px, seed, label):
     idx = np.concatenate([idx, [cam.width * cam.height - 1, (cam.height - 1) * cam.width, cam.width - 1]])
     px, py = idx % cam.width, idx // cam.width
     orc = O.render_pixels(scene, cam, oracle_opts(), px, py, prims=prims)
-    err = np.abs(g[:, py, px].T.astype(np.float64) - orc.rgb).max(axis=1)
-    worst = float(err[~orc.knife].max())
-    log(f"{label}: {idx.size} px, max err {worst:.3e}, knife {int(orc.knife.sum())}, mean emitted {orc.n_emit.mean():.1f}")
-    assert worst <= IMG_TOL
-    assert orc.knife.sum() <= max(2, idx.size // 100)
+    compare_pixels(g, orc, px, py, label)
 
 
 def _tile_sample(ras, scene, cam, view, n, seed):
@@ -141,10 +137,10 @@ def _tile_sample(ras, scene, cam, view, n, seed):
         assert keys[j] == okey[j]
 
 
-@pytest.mark.timeout(300)
+@pytest.mark.timeout(600)
 def test_headline_1m_1080p_sampled():
     """1M DRKs (K=8, SH3) at 1920x1080 from inside the cluster box, in the launch configuration the
-    benchmark times: 256 seeded pixels (and the image corners) against the oracle, 60 listed DRKs'
+    benchmark times: 4096 seeded pixels (and the image corners) against the oracle, 60 listed DRKs'
     tile sets and keys bit-exact."""
     need_gpu()
     from paper_2412_11752_amd import DRKScene
@@ -155,7 +151,7 @@ def test_headline_1m_1080p_sampled():
     g = rgb[0].cpu().numpy()
     log("1M 1080p rendered")
     prims = O.Prims.from_scene(scene)
-    _sampled_check(scene, cam, g, prims, 256, 31, "1M 1080p")
+    _sampled_check(scene, cam, g, prims, 4096, 31, "1M 1080p")
     _tile_sample(ras, scene, cam, 0, 60, 32)
 
 
@@ -192,7 +188,7 @@ def test_launch_orders_give_identical_images():
     ds = DRKScene.from_host(scene)
     out = []
     for order in (0, 1):
-        rgb, T = ras.forward(ds, [cam], make_opts(launch_order=order))
+        rgb, T = ras.forward(ds, [cam], make_opts(launch_order=order, counters=1))
         out.append((rgb.clone(), T.clone(), ras.export("emitted").clone(), ras.export("consumed").clone()))
     log(f"800x800: launch orders compared over {out[0][0].numel()} values")
     for a, b in zip(*out):
@@ -216,7 +212,7 @@ def test_span_buffer_overflow_gives_the_same_lists(monkeypatch, key_mode):
         else:
             monkeypatch.setenv("DRK_SPAN_ROWS", rows)
         ras = _rasterizer(scene, [cam], 1 << 23)
-        rgb, T = ras.forward(ds, [cam], make_opts(key_mode=key_mode))
+        rgb, T = ras.forward(ds, [cam], make_opts(key_mode=key_mode, counters=1))
         out.append([rgb.clone(), T.clone()] + [ras.export(w).clone() for w in
                                                 ("pair_tiles", "pair_prims", "ranges", "emitted", "consumed")])
         ras.close()

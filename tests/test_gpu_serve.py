@@ -53,6 +53,7 @@ def test_mixed_requests_match_alone(scenes, use_graphs):
     assert all(st["status"] == 0 for st in stats)
     overlap = sum(1 for a, b in zip(stats, stats[1:]) if b["start_us"] < a["done_us"])
     log(f"graphs={use_graphs}: {len(stats)} requests, {overlap} started before the previous finished")
+    assert overlap >= 1        # the results below were produced in the mix, not one at a time
     torch.cuda.synchronize()
     for i, cam in enumerate(cams):
         h = hs[which[i]]
@@ -122,3 +123,71 @@ def test_overflow_is_retried_with_a_larger_workspace(scenes):
     alone, _ = ras.forward(ds[2], [cam_near], gpu_opts())
     assert torch.equal(alone.reshape(-1), out)
     srv.close()
+
+
+def test_overflow_past_the_budget_is_reported(scenes):
+    """A request whose first workspace fits the budget but whose pairs overflow it needs a larger
+    workspace than the whole budget: the request completes with DRK_ENOMEM instead of waiting
+    forever, and requests behind it still run."""
+    from paper_2412_11752_amd import Rasterizer
+    from paper_2412_11752_amd._lib import DRK_ENOMEM
+    from paper_2412_11752_amd.serving import Server
+    hs, ds = scenes
+    cam_near = camera_lookat((0, 0, -1.6), (0, 0, 0), (0, 1, 0), 800, 800, 90.0)
+    small = Rasterizer.size_query(hs[2].n, hs[2].K, 800, 800, 1, 1000)
+    big = Rasterizer.size_query(hs[2].n, hs[2].K, 800, 800, 1, 200_000)
+    assert big > small
+    srv = Server(hbm_budget_bytes=(small + big) // 2, max_inflight=1, opts=gpu_opts(), initial_pairs=1000)
+    sid = srv.add_scene(ds[2])
+    out = torch.empty(3 * 800 * 800, device="cuda")
+    st = srv.wait(srv.submit(sid, cam_near, out))
+    log(f"overflowing request past the budget: status {st['status']}, pairs needed {st['pairs']}")
+    assert st["status"] == DRK_ENOMEM and st["pairs"] > 200_000
+    sid1 = srv.add_scene(ds[1])
+    cam = _cams(5, [(64, 64)], 1)[0]
+    out1 = torch.empty(3 * 64 * 64, device="cuda")
+    assert srv.wait(srv.submit(sid1, cam, out1))["status"] == 0
+    srv.close()
+
+
+def test_small_requests_pass_a_waiting_large_one(scenes):
+    """The budget holds one 800x800 workspace and a few small ones.  A second 800x800 request of the
+    same scene needs a second such workspace and waits for the first request to finish; small
+    requests submitted after it are admitted meanwhile (the waiting one is passed a bounded number
+    of times), and every result equals the request rendered alone."""
+    from paper_2412_11752_amd import Rasterizer
+    from paper_2412_11752_amd.serving import Server
+    hs, ds = scenes
+    big_cam = camera_lookat((0, 0, -3.0), (0, 0, 0), (0, 1, 0), 800, 800, 60.0)
+    small_cam = _cams(6, [(64, 64)], 1)[0]
+    probe = Rasterizer(hs[2].n, hs[2].K, 800, 800, pair_capacity=1 << 24)
+    probe.forward(ds[2], [big_cam], gpu_opts())
+    need = probe.status()[1]
+    probe.close()
+    # a request that overflows is rerun with 25% (+1024) more pairs than it needed
+    ws_big = Rasterizer.size_query(hs[2].n, hs[2].K, 800, 800, 1, need + need // 4 + 1024)
+    ws_small = Rasterizer.size_query(hs[1].n, hs[1].K, 64, 64, 1, 1 << 17)
+    budget = ws_big + 3 * ws_small + (1 << 20)
+    assert 2 * ws_big > budget, (ws_big, ws_small)     # a second 800x800 workspace cannot fit beside the first
+    srv = Server(hbm_budget_bytes=budget, max_inflight=4, opts=gpu_opts(), initial_pairs=0)
+    sid = [srv.add_scene(d) for d in ds]
+    warm = torch.empty(3 * 800 * 800, device="cuda")
+    assert srv.wait(srv.submit(sid[2], big_cam, warm))["status"] == 0   # learns the 800x800 capacity
+    jobs = [(2, big_cam), (2, big_cam)] + [(1, small_cam)] * 3
+    outs, rids = [], []
+    for s_i, cam in jobs:
+        out = torch.empty(3 * cam.width * cam.height, device="cuda")
+        outs.append(out)
+        rids.append(srv.submit(sid[s_i], cam, out))
+    stats = [srv.wait(r) for r in rids]
+    assert all(st["status"] == 0 for st in stats)
+    passed = sum(1 for st in stats[2:] if st["start_us"] < stats[1]["start_us"])
+    log(f"budget {budget / 2**20:.1f} MiB (800x800 workspace {ws_big / 2**20:.1f}, 64x64 {ws_small / 2**20:.1f}): "
+        f"{passed} of 3 small requests admitted before the waiting 800x800 one")
+    assert stats[1]["start_us"] >= stats[0]["done_us"] - 1.0   # the second large request waited
+    assert passed >= 1
+    srv.close()
+    for (s_i, cam), out in zip(jobs, outs):
+        ras = Rasterizer(hs[s_i].n, hs[s_i].K, cam.width, cam.height, pair_capacity=need + 4096)
+        alone, _ = ras.forward(ds[s_i], [cam], gpu_opts())
+        assert torch.equal(alone.reshape(-1), out)
