@@ -260,6 +260,22 @@ drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, 
  * that it is unchanged before calling drk_render_bwd.                                          */
 drk_status drk_ws_generation(drk_ws* ws, uint64_t* generation);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): drk_preprocess -> drk_bin_sort -> drk_render_fwd of ONE
+ * view without a workspace.  Every intermediate lives in a fixed device array of the library
+ * (128 MiB per GPU, reserved from the first call on that GPU until the process ends); the pair
+ * capacity is whatever that array holds beyond the scene- and image-sized parts.
+ *   scene, cam, opts  as for drk_preprocess (one camera; opts->counters must be 0)
+ *   rgb [3][H][W], T_final [H][W] (may be NULL): device, caller-owned, written
+ * The call synchronises `stream` and returns the frame's final status: DRK_ENOMEM (nothing
+ * enqueued) when the scene and image alone do not fit the array, DRK_EOVERFLOW when the frame's
+ * tile pairs do not (the image is then incomplete), DRK_EINVAL for invalid arguments or (validate
+ * mode) invalid primitives.  Allocates no memory of any kind.  Calls on one GPU share its array
+ * and keep its last contents: calls that overlap on the same GPU (several host threads or
+ * streams) race and must be serialised by the caller.                                          */
+drk_status drk_render_fwd_noalloc(const drk_scene* scene, const drk_camera* cam, const drk_opts* opts, float* rgb,
+                                  float* T_final, void* stream);
+
 /* Synchronises `stream` and reports the status word: DRK_OK, or DRK_EOVERFLOW with
  * *pairs_needed set to the largest pair count any view of the last drk_bin_sort needed.      */
 drk_status drk_ws_status(drk_ws* ws, void* stream, int64_t* pairs_needed);

@@ -16,7 +16,7 @@ EXPORTED = [
     "drk_preprocess", "drk_bin_sort", "drk_render_fwd", "drk_render_trace", "drk_trace_metrics",
     "drk_render_depth_normal", "drk_mesh_to_drk", "drk_activate", "drk_activate_bwd", "drk_adam_step",
     "drk_render_bwd",
-    "drk_ws_generation", "drk_ws_status", "drk_ws_export",
+    "drk_render_fwd_noalloc", "drk_ws_generation", "drk_ws_status", "drk_ws_export",
     "drk_serve_create", "drk_serve_destroy", "drk_serve_add_scene", "drk_serve_submit", "drk_serve_poll",
 ]
 
@@ -97,6 +97,7 @@ def lib() -> C.CDLL:
         "drk_activate_bwd": [C.POINTER(Scene), C.POINTER(SceneGrad), C.POINTER(SceneOut), vp],
         "drk_adam_step": [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp],
         "drk_render_bwd": [vp, C.POINTER(Scene), vp, vp, C.POINTER(SceneGrad), vp],
+        "drk_render_fwd_noalloc": [C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Opts), vp, vp, vp],
         "drk_ws_generation": [vp, C.POINTER(C.c_uint64)],
         "drk_ws_status": [vp, vp, C.POINTER(i64)],
         "drk_ws_export": [vp, i32, i32, vp, i64, C.POINTER(i64), vp],

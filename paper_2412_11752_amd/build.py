@@ -28,7 +28,7 @@ FLAGS = [
     "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
 SOURCES = ["api.cpp", "preprocess.hip", "binning.hip", "render_fwd.hip", "render_bwd.hip", "trace_metrics.hip",
-           "mesh.hip", "train.hip", "serve.cpp"]
+           "mesh.hip", "train.hip", "serve.cpp", "noalloc.hip"]
 
 
 def hipcc() -> str:

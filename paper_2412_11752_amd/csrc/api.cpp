@@ -759,3 +759,61 @@ drk_status drk_ws_export(drk_ws* ws, int32_t view, int32_t what, void* dst, int6
 }
 
 }  // extern "C"
+
+namespace drk {
+
+// One forward render of one view whose workspace is placed in the caller-given device memory
+// [base, base + bytes) with the forward-only layout; the pair capacity is whatever the rest of that
+// memory holds.  Enqueued on s, then s is synchronised and the status word read into host stack
+// memory, so the call returns the frame's final status.  Allocates nothing.
+drk_status render_placed(void* base, size_t bytes, const drk_scene* scene, const drk_camera* cam,
+                         const drk_opts* opts, float* rgb, float* T_final, hipStream_t s) {
+  if (!scene || !cam || !opts || !rgb) { set_error("null argument"); return DRK_EINVAL; }
+  if (scene->n < 0 || scene->K < 3 || scene->K > kMaxK) { set_error("scene: n >= 0 and 3 <= K <= %d", kMaxK); return DRK_EINVAL; }
+  drk_ws ws;                       // host bookkeeping on the stack; the device memory is base
+  ws.max_n = std::max<int64_t>(scene->n, 1);
+  ws.K = scene->K;
+  ws.RF = rec_floats(scene->K);
+  ws.max_views = 1;
+  ws.max_w = cam->width;
+  ws.max_h = cam->height;
+  if (!valid_ws_args(ws.max_n, ws.K, 1, ws.max_w, ws.max_h, 1)) return DRK_EINVAL;
+  ws.max_tiles = ((ws.max_w + kTile - 1) / kTile) * ((ws.max_h + kTile - 1) / kTile);
+  ws.row_cap = span_row_capacity(ws.max_n);
+  ws.lean = true;
+  ws.lean_keys = opts->key_mode != 0;
+  ws.cap = 1;
+  const size_t fixed = layout(&ws, false, nullptr);
+  // six u32 arrays per pair (two ping-pong key/value pairs and the final tile and primitive lists)
+  const size_t per_pair = 6 * sizeof(uint32_t), slack = 16 * 256;
+  if (fixed + slack + 1024 * per_pair > bytes) {
+    set_error("scene of %lld DRKs (K = %d) at %dx%d needs %zu bytes before any tile pair; the fixed device array "
+              "holds %zu", (long long)scene->n, scene->K, cam->width, cam->height, fixed, bytes);
+    return DRK_ENOMEM;
+  }
+  int64_t cap = (int64_t)((bytes - fixed - slack) / per_pair);
+  cap = std::min<int64_t>(cap, (int64_t)0xFFFFFF00);
+  ws.cap = cap;
+  while (layout(&ws, false, nullptr) > bytes) ws.cap -= 256;
+  layout(&ws, true, static_cast<char*>(base));
+  ws.bytes = bytes;
+  drk_status st = ws_set_cameras(&ws, cam, 1, s);
+  if (st) return st;
+  if ((st = ws_preprocess_core(&ws, scene, opts, s))) return st;
+  if ((st = drk_bin_sort(&ws, s))) return st;
+  if ((st = drk_render_fwd(&ws, rgb, T_final, s))) return st;
+  if ((st = check_hip(hipStreamSynchronize(s), "stream sync"))) return st;
+  uint32_t status = 0;
+  uint64_t total = 0;
+  if ((st = check_hip(hipMemcpy(&status, ws.status, sizeof(status), hipMemcpyDeviceToHost), "read status"))) return st;
+  if ((st = check_hip(hipMemcpy(&total, ws.totals, sizeof(total), hipMemcpyDeviceToHost), "read pair count"))) return st;
+  if (status & ST_INVALID) { set_error("invalid primitive parameters (validate mode)"); return DRK_EINVAL; }
+  if (status & ST_OVERFLOW) {
+    set_error("the frame needs %llu tile pairs; the fixed device array holds %lld at this scene and image size "
+              "(the image is incomplete)", (unsigned long long)total, (long long)ws.cap);
+    return DRK_EOVERFLOW;
+  }
+  return DRK_OK;
+}
+
+}  // namespace drk

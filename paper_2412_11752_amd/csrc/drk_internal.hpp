@@ -123,6 +123,11 @@ drk_status ws_set_cameras(drk_ws* ws, const drk_camera* cams, int32_t n_views, h
 drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts* opts, hipStream_t s);
 drk_status ws_read_status(drk_ws* ws, int64_t* pairs_needed);
 float* ws_out_rgb(drk_ws* ws);
+// One forward render of one view with its workspace placed in [base, base + bytes) of device memory
+// (forward-only layout, pair capacity from what the rest holds); synchronises s and returns the
+// frame's final status.  Allocates nothing.
+drk_status render_placed(void* base, size_t bytes, const drk_scene* scene, const drk_camera* cam,
+                         const drk_opts* opts, float* rgb, float* T_final, hipStream_t s);
 size_t ws_bytes(drk_ws* ws);
 int64_t ws_capacity(drk_ws* ws);
 }
