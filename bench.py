@@ -310,8 +310,9 @@ def ksweep_phase(args, opts, W, H):
 def sortacc_phase(args, lanes, ds, frames, W, H):
     """Sorting accuracy of the pre-sort keys (supplement, cache-sorting evaluation): randomly placed
     and oriented kernels (1500 DRKs, K = 8, scales 0.05-0.5 in a 2-unit box) rendered at 512x512
-    with each key and cache length, traced front to back and measured by drk_trace_metrics; plus
-    the cost of each key on the headline workload (same frames as the fwd phase)."""
+    with each key and cache length, traced front to back and measured by drk_trace_metrics, and
+    each image compared with the exact per-pixel order's; plus the cost of each key on the headline
+    workload (same frames as the fwd phase)."""
     import torch
     from drk_synth import camera_lookat, scene_uniform_box
     from paper_2412_11752_amd import DRKScene, Rasterizer, make_opts, trace_metrics
@@ -322,17 +323,36 @@ def sortacc_phase(args, lanes, ds, frames, W, H):
     sd = DRKScene.from_host(host, device="cuda")
     r2 = Rasterizer(host.n, host.K, 512, 512, pair_capacity=1 << 22)
     names = {0: "centre", 1: "centric", 2: "nearest"}
+    # the exact per-pixel order (cache_len >= 2^30) as the reference image
+    exact_opts = make_opts(cache_len=1 << 30)
+    r2.preprocess(sd, [cam], exact_opts)
+    r2.bin_sort()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(torch.cuda.current_stream())
+    ref, _ = r2.render_fwd()
+    e1.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    out["exact_ms"] = round(e0.elapsed_time(e1), 3)
+    out["image_vs_exact"] = {}
     for mode in (0, 1, 2):
-        row = {}
+        row, img = {}, {}
         for L in (1, 2, 4, 8):
             r2.preprocess(sd, [cam], make_opts(cache_len=L, key_mode=mode))
             r2.bin_sort()
             _, _, tn, ti, tz = r2.render_trace(64)
             m = trace_metrics(tn, tz, 64)
             row[str(L)] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in m.items()}
+            rgb, _ = r2.render_fwd()
+            d = (rgb - ref).abs()
+            mse = float((d * d).mean())
+            img[str(L)] = {"mean_abs": round(float(d.mean()), 6), "max_abs": round(float(d.max()), 5),
+                           "psnr_db": round(10 * math.log10(1.0 / mse), 2) if mse > 0 else None}
         out["metrics"][names[mode]] = row
+        out["image_vs_exact"][names[mode]] = img
         log(f"sortacc {names[mode]}: " + ", ".join(f"L={L} acc {v['accuracy']:.3f} tau {v['kendall_tau']:.3f} "
-                                                  f"mae {v['mae']:.4f}" for L, v in row.items()))
+                                                  f"mae {v['mae']:.4f} psnr-vs-exact {img[L]['psnr_db']}"
+                                                  for L, v in row.items()))
     r2.close()
     for mode in (0, 1, 2):
         t_total, ms = timed(lanes[:1], ds, frames, make_opts(key_mode=mode), args)   # one frame in flight

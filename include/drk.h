@@ -106,7 +106,9 @@ typedef struct drk_camera {
 
 /* Rasterization options.  Defaults (drk_opts_default): alpha_min 1/255, alpha_max 0.99,
  * T_min 1e-4, near 0.2, lowpass_sl sqrt(2)/2 px (Sec. 4.4 low-pass; 0 disables it),
- * cache_len 8 (Sec. 4.4 cache sorting; 1..8, 1 = pre-sort order only),
+ * cache_len 8 (Sec. 4.4 cache sorting; 1..8, 1 = pre-sort order only; any value >= 2^30 = the
+ * exact per-pixel order: every contribution composited by its hit depth, ties by index, the
+ * ideal the cache approximates; drk_render_fwd only, several list passes per frame),
  * cull_mode 0 (0 = conservative support polygon, 1 = the paper's endpoint polygon (lossy),
  * 2 = every tile), validate 0 (1 = return DRK_EINVAL for invalid primitives),
  * key_mode 0: the pre-sort key of the tile lists (supplement, cache-sorting evaluation):

@@ -265,11 +265,12 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   }
   if (!(opts->alpha_min > 0.0f && opts->alpha_min < 1.0f) || !(opts->alpha_max > 0.0f && opts->alpha_max < 1.0f) ||
       !(opts->T_min > 0.0f && opts->T_min < 1.0f) || !(opts->near_plane > 0.0f) || !(opts->lowpass_sl >= 0.0f) ||
-      opts->cache_len < 1 || opts->cache_len > kMaxCache || opts->cull_mode < 0 || opts->cull_mode > 2 ||
+      opts->cache_len < 1 || (opts->cache_len > kMaxCache && opts->cache_len < kExactOrder) || opts->cull_mode < 0 ||
+      opts->cull_mode > 2 ||
       opts->key_mode < 0 || opts->key_mode > 2 || opts->launch_order < 0 || opts->launch_order > 1 ||
       opts->counters < 0 || opts->counters > 1) {
-    set_error("invalid drk_opts (cache_len must be in [1, %d], key_mode in [0, 2], launch_order and counters 0 or 1)",
-              kMaxCache);
+    set_error("invalid drk_opts (cache_len must be in [1, %d] or at least 2^30 for the exact order, key_mode in "
+              "[0, 2], launch_order and counters 0 or 1)", kMaxCache);
     return DRK_EINVAL;
   }
   SceneDev sc;
@@ -529,7 +530,7 @@ drk_status render_views(drk_ws* ws, float* rgb, float* T_final, int mode, int32_
     if (st) return st;
     off += npx;
   }
-  ws->counted = mode != 0 || ws->opts.counters != 0;
+  ws->counted = ws->opts.cache_len < kExactOrder && (mode != 0 || ws->opts.counters != 0);
   return DRK_OK;
 }
 
@@ -544,6 +545,7 @@ drk_status drk_render_fwd(drk_ws* ws, float* rgb, float* T_final, void* stream) 
 drk_status drk_render_depth_normal(drk_ws* ws, float* rgb, float* T_final, float* depth, float* normal, void* stream) {
   if (!ws || !rgb || !depth || !normal) { set_error("null argument"); return DRK_EINVAL; }
   if (!ws->have_bins) { set_error("drk_render_depth_normal before drk_bin_sort"); return DRK_EINVAL; }
+  if (ws->opts.cache_len >= kExactOrder) { set_error("the exact order renders colour only"); return DRK_EINVAL; }
   return render_views(ws, rgb, T_final, 2, 0, depth, nullptr, normal, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -627,6 +629,7 @@ drk_status drk_render_trace(drk_ws* ws, float* rgb, float* T_final, int32_t cap,
                             int32_t* trace_idx, float* trace_z, void* stream) {
   if (!ws || !rgb || !trace_n || !trace_idx || !trace_z) { set_error("null argument"); return DRK_EINVAL; }
   if (!ws->have_bins) { set_error("drk_render_trace before drk_bin_sort"); return DRK_EINVAL; }
+  if (ws->opts.cache_len >= kExactOrder) { set_error("the exact order renders colour only"); return DRK_EINVAL; }
   if (cap < 1 || cap > 1024) { set_error("trace cap %d outside [1, 1024]", cap); return DRK_EINVAL; }
   return render_views(ws, rgb, T_final, 1, cap, trace_n, trace_idx, trace_z, reinterpret_cast<hipStream_t>(stream));
 }
@@ -643,6 +646,7 @@ drk_status drk_render_bwd(drk_ws* ws, const drk_scene* scene, const float* rgb, 
                           const drk_scene_grad* grads, void* stream) {
   if (!ws || !scene || !rgb || !dL_drgb || !grads) { set_error("null argument"); return DRK_EINVAL; }
   if (!ws->have_bins) { set_error("drk_render_bwd before drk_bin_sort"); return DRK_EINVAL; }
+  if (ws->opts.cache_len >= kExactOrder) { set_error("no backward for the exact order"); return DRK_EINVAL; }
   if (scene->n != ws->scene.n || scene->mu != ws->scene.mu || scene->q != ws->scene.q) {
     set_error("drk_render_bwd: scene differs from the one preprocessed");
     return DRK_EINVAL;

@@ -13,6 +13,7 @@ constexpr int kMaxK = 16;            // radial bases per primitive
 constexpr int kMaxViews = 8;         // views per launch
 constexpr int kMaxTileRows = 136;    // tile rows per view (image height <= 2176)
 constexpr int kMaxCache = 8;         // cache slots (Sec. 4.4 Cache Sorting uses 8)
+constexpr int32_t kExactOrder = 1 << 30;   // cache_len at or above this: exact per-pixel depth order
 constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
 constexpr double kGrazing = 1e-6;    // |r_d . n| below this is a grazing ray (no hit)
 

@@ -178,11 +178,126 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   }
 }
 
+// Exact per-pixel order (cache_len >= 2^30): every contribution of the tile's list composited in
+// the order of its hit depth Z (ties by primitive index), with the same stop rule, i.e. the ideal
+// order the cache of Algorithm 1 approximates.  Each pass over the list gathers, per pixel, the
+// kExactChunk contributions nearest behind the last one composited, in a sorted register buffer of
+// (Z, index, alpha) that keeps the smallest, and composites them; passes repeat until every pixel of
+// the tile has stopped or has no contribution left.  A pass cannot end early, so the cost is about
+// one full list scan per kExactChunk composited contributions.
+constexpr int kExactChunk = 8;
+
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_render_exact(const float* __restrict__ records,
+                                                         const uint32_t* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ prims,
+                                                         const CamDev* __restrict__ camp,
+                                                         const uint32_t* __restrict__ tile_order, OptsDev opt,
+                                                         float* __restrict__ rgb, float* __restrict__ T_out) {
+  constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
+  constexpr int RF4 = RF / 4;
+  __shared__ float4 lds[kBatch * RF4];
+  __shared__ uint32_t lidx[kBatch];
+  const CamDev& cam = *camp;
+  const int tile = tile_order ? (int)tile_order[blockIdx.x] : (int)blockIdx.x;
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const int tid = threadIdx.x;
+  const int x = tx * kTile + (tid & (kTile - 1));
+  const int y = ty * kTile + (tid >> 4);
+  const bool inside = x < cam.W && y < cam.H;
+  const RasterParams rp = make_params(opt);
+  const Pix pix = make_pix(cam, x, y);
+  const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + (float)(kTile - 1);
+  const float wy0 = (float)(ty * kTile + (tid >> 6) * 4) + 0.5f, wy1 = wy0 + 3.0f;
+  const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  bool done = !inside;
+  float last_z = -INFINITY;         // (Z, index) of the last composited contribution
+  uint32_t last_j = 0;
+  bool have_last = false;
+  while (__syncthreads_count(!done) != 0) {
+    float bz[kExactChunk], ba[kExactChunk];
+    uint32_t bj[kExactChunk];
+#pragma unroll
+    for (int s = 0; s < kExactChunk; ++s) { bz[s] = INFINITY; bj[s] = 0xFFFFFFFFu; ba[s] = 0.0f; }
+    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+      const int nb = (int)min((uint32_t)kBatch, end - b0);
+      for (int q = tid; q < nb * RF4; q += kBlock) {
+        const int ri = q / RF4, c = q - ri * RF4;
+        lds[q] = reinterpret_cast<const float4*>(records + (size_t)prims[b0 + ri] * RF)[c];
+      }
+      if (tid < nb) lidx[tid] = prims[b0 + tid];
+      __syncthreads();
+      const uint64_t mask = batch_box_mask<RF4>(lds, nb, wx0, wx1, wy0, wy1);
+      if (!done) {
+        for (uint64_t m = mask; m; m &= m - 1) {
+          const int i = __builtin_ctzll(m);
+          float at, Z;
+          if (!drk_eval<K>(reinterpret_cast<const float*>(lds + i * RF4), pix, rp, at, Z)) continue;
+          if (!(at >= rp.alpha_min)) continue;
+          const uint32_t j = lidx[i];
+          if (have_last && !(Z > last_z || (Z == last_z && j > last_j))) continue;   // already composited
+          // lt[s]: the newcomer goes before slot s (monotone in s, the buffer being sorted)
+          bool lt[kExactChunk];
+#pragma unroll
+          for (int s = 0; s < kExactChunk; ++s) lt[s] = Z < bz[s] || (Z == bz[s] && j < bj[s]);
+          if (!lt[kExactChunk - 1]) continue;
+#pragma unroll
+          for (int s = kExactChunk - 1; s > 0; --s) {
+            bz[s] = lt[s - 1] ? bz[s - 1] : (lt[s] ? Z : bz[s]);
+            bj[s] = lt[s - 1] ? bj[s - 1] : (lt[s] ? j : bj[s]);
+            ba[s] = lt[s - 1] ? ba[s - 1] : (lt[s] ? at : ba[s]);
+          }
+          bz[0] = lt[0] ? Z : bz[0];
+          bj[0] = lt[0] ? j : bj[0];
+          ba[0] = lt[0] ? at : ba[0];
+        }
+      }
+      __syncthreads();
+    }
+    int got = 0;
+#pragma unroll
+    for (int s = 0; s < kExactChunk; ++s) {
+      if (!done && bj[s] != 0xFFFFFFFFu) {
+        ++got;
+        const float a = ba[s];
+        const float test = T * (1.0f - a);
+        if (test < rp.T_min) {
+          done = true;
+        } else {
+          const float* c = records + (size_t)bj[s] * RF + R_RGB;
+          const float w = a * T;
+          C0 = fmaf(w, c[0], C0);
+          C1 = fmaf(w, c[1], C1);
+          C2 = fmaf(w, c[2], C2);
+          T = test;
+          last_z = bz[s];
+          last_j = bj[s];
+          have_last = true;
+        }
+      }
+    }
+    if (got < kExactChunk) done = true;   // nothing behind: the list is exhausted for this pixel
+  }
+  if (inside) {
+    const size_t plane = (size_t)cam.W * cam.H;
+    const size_t pidx = (size_t)y * cam.W + x;
+    rgb[pidx] = fmaf(T, cam.bg[0], C0);
+    rgb[plane + pidx] = fmaf(T, cam.bg[1], C1);
+    rgb[2 * plane + pidx] = fmaf(T, cam.bg[2], C2);
+    if (T_out) T_out[pidx] = T;
+  }
+}
+
 template <int K>
 static hipError_t launch_fwd_k(const float* records, const uint32_t* ranges, const uint32_t* prims, const CamDev* cam,
                                int ntiles, const uint32_t* order, const OptsDev& opt, float* rgb, float* T, int32_t* ne, int32_t* cons, int32_t* nc,
                                int32_t* wk, int mode, void* a0, int32_t* a1, float* a2, int cap, hipStream_t s) {
-  if (mode == kFwdTrace)
+  if (opt.cache_len >= kExactOrder) {
+    if (mode != kFwdPlain) return hipErrorInvalidValue;   // exact order: colour and transmittance only
+    hipLaunchKernelGGL((k_render_exact<K>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, order, opt,
+                       rgb, T);
+  } else if (mode == kFwdTrace)
     hipLaunchKernelGGL((k_render_fwd<K, kFwdTrace, true>), dim3(ntiles), dim3(kBlock), 0, s, records, ranges, prims, cam, order,
                        opt, rgb, T, ne, cons, nc, wk, a0, a1, a2, cap);
   else if (mode == kFwdDepthNormal)

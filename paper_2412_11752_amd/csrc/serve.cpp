@@ -346,7 +346,7 @@ drk_status drk_serve_create(const drk_serve_cfg* cfg, drk_server** out) {
   if (cfg->hbm_budget_bytes < 0) { set_error("hbm_budget_bytes must be >= 0"); return DRK_EINVAL; }
   if (cfg->initial_pairs < 0) { set_error("initial_pairs must be >= 0"); return DRK_EINVAL; }
   const drk_opts& o = cfg->opts;
-  if (o.cache_len < 1 || o.cache_len > kMaxCache || o.cull_mode < 0 || o.cull_mode > 2 || o.key_mode < 0 ||
+  if (o.cache_len < 1 || (o.cache_len > kMaxCache && o.cache_len < kExactOrder) || o.cull_mode < 0 || o.cull_mode > 2 || o.key_mode < 0 ||
       o.key_mode > 2 || o.launch_order < 0 || o.launch_order > 1 || !(o.alpha_min > 0.0f)) {
     set_error("invalid drk_opts in serve config");
     return DRK_EINVAL;

@@ -303,3 +303,68 @@ def test_largest_image_three_pass_tile_sort():
     px, py = np.concatenate([px, [8191, 0]]), np.concatenate([py, [2175, 2175]])
     orc = O.render_pixels(scene, cam, oracle_opts(), px, py)
     compare_pixels(g, orc, px, py, "8192x2176")
+
+
+EXACT = 1 << 30
+
+
+def test_exact_order_matches_oracle(c1):
+    """cache_len >= 2^30: every contribution composited by hit depth (Sec. 4.4 Cache Sorting's ideal
+    order), against the oracle's exact mode, on the 64x64 scene and on a dense 96x80 scene of
+    intersecting primitives where the 8-slot cache gives a different image."""
+    from paper_2412_11752_amd import DRKScene
+    ras, ds, cam, scene = c1["ras"], c1["ds"], c1["cam"], c1["scene"]
+    a, T = ras.forward(ds, [cam], gpu_opts(cache_len=EXACT))
+    orc = O.render_image(scene, cam, oracle_opts(cache_len=O.EXACT))
+    worst, nk, _, _ = compare_image(a[0].cpu().numpy(), orc, cam.height, cam.width)
+    log(f"exact order 64x64: max err {worst:.2e}, knife {nk}")
+    assert worst <= IMG_TOL
+    np.testing.assert_allclose(T[0].cpu().numpy().ravel()[~orc.knife], orc.T[~orc.knife], atol=IMG_TOL)
+    from drk_synth import camera_lookat
+    dense = scene_uniform_box(44, 1500, K=8, half=0.7, s_lo=0.05, s_hi=0.35)
+    cam2 = camera_lookat((0.3, -0.2, -3.0), (0, 0, 0), (0, 1, 0), 96, 80, 60.0, bg=(0.1, 0.2, 0.3))
+    r2 = _ras(dense, [cam2])
+    d2 = DRKScene.from_host(dense)
+    ex, _ = r2.forward(d2, [cam2], gpu_opts(cache_len=EXACT))
+    c8, _ = r2.forward(d2, [cam2], gpu_opts(cache_len=8))
+    oe = O.render_image(dense, cam2, oracle_opts(cache_len=O.EXACT))
+    o8 = O.render_image(dense, cam2, oracle_opts(cache_len=8))
+    we, nke, _, _ = compare_image(ex[0].cpu().numpy(), oe, cam2.height, cam2.width)
+    w8, nk8, _, _ = compare_image(c8[0].cpu().numpy(), o8, cam2.height, cam2.width)
+    gap = float(np.abs(oe.rgb - o8.rgb).max())
+    log(f"exact order 96x80 dense: max err {we:.2e} (knife {nke}); cache-8 {w8:.2e} (knife {nk8}); "
+        f"exact vs cache-8 differ by up to {gap:.3f}")
+    assert we <= IMG_TOL and w8 <= IMG_TOL
+    assert gap > 1e-3 and float((ex - c8).abs().max()) > 1e-3
+
+
+def test_exact_order_equals_cache_on_fronto_parallel_planes():
+    """Every plane parallel to the image: the centre-depth pre-sort is already the hit-depth order, so
+    the cache emits in exact order and both images are bitwise equal (the fronto-parallel pin)."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene = scene_uniform_box(45, 600, K=8, half=0.8, s_lo=0.05, s_hi=0.3)
+    scene.q[:] = 0.0
+    scene.q[0] = 1.0
+    fx, fy, cx, cy = intrinsics_hfov(80, 64, 60.0)
+    cam = Camera(80, 64, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.array([0, 0, 3.0], np.float32),
+                 np.array([0.1, 0.1, 0.1], np.float32))
+    ras = _ras(scene, [cam])
+    ds = DRKScene.from_host(scene)
+    ex, Te = ras.forward(ds, [cam], gpu_opts(cache_len=EXACT))
+    c8, T8 = ras.forward(ds, [cam], gpu_opts(cache_len=8))
+    assert torch.equal(ex, c8) and torch.equal(Te, T8)
+    orc = O.render_image(scene, cam, oracle_opts(cache_len=O.EXACT))
+    worst, nk, _, _ = compare_image(ex[0].cpu().numpy(), orc, cam.height, cam.width)
+    assert worst <= IMG_TOL
+
+
+def test_exact_order_refuses_other_outputs(c1):
+    from paper_2412_11752_amd._lib import DRK_EINVAL, DrkError
+    ras, ds, cam = c1["ras"], c1["ds"], c1["cam"]
+    ras.preprocess(ds, [cam], gpu_opts(cache_len=EXACT))
+    ras.bin_sort()
+    for call in (lambda: ras.render_trace(8), lambda: ras.render_depth_normal()):
+        with pytest.raises(DrkError) as e:
+            call()
+        assert e.value.code == DRK_EINVAL
