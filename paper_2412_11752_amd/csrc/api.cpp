@@ -92,7 +92,7 @@ struct drk_ws {
   float* grad_rec = nullptr;
   Views* views_dev = nullptr;     // cameras read by every kernel (set by a one-thread kernel)
   uint32_t* work = nullptr;       // per view: primitives that may touch the view
-  uint32_t* counters = nullptr;   // per view: [work count, rows used]
+  uint32_t* counters = nullptr;   // work count per view, then kSpanPools span-row pool fills per view
   uint2* span_meta = nullptr;     // per view and primitive: row-span offset, first row | rows << 16
   uint32_t* span_rows = nullptr;  // per view: tile columns i0 | i1 << 16 of each spanned row
   int64_t row_cap = 0;
@@ -170,7 +170,7 @@ size_t layout(drk_ws* ws, bool assign, char* base) {
   SLOT(grad_rec, float, ws->lean ? 0 : V * N * grad_fields(ws->K))
   SLOT(views_dev, Views, 1)
   SLOT(work, uint32_t, V * N)
-  SLOT(counters, uint32_t, 2 * V)
+  SLOT(counters, uint32_t, (1 + kSpanPools) * V)
   SLOT(span_meta, uint2, V * N)
   SLOT(span_rows, uint32_t, V * (size_t)ws->row_cap)
   SLOT(out_rgb, float, ws->lean ? 0 : 3 * px)
@@ -287,7 +287,7 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   od.counters = opts->counters;
   drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
   if (st) return st;
-  if ((st = check_hip(fill_u32(ws->counters, 0u, 2 * ws->max_views, s), "clear counters"))) return st;
+  if ((st = check_hip(fill_u32(ws->counters, 0u, (1 + kSpanPools) * ws->max_views, s), "clear counters"))) return st;
   const int V = ws->max_views;
   st = check_hip(launch_preprocess(sc, ws->views_dev, ws->views.nv, od, ws->records, ws->depth_keys, ws->tile_counts,
                                    ws->work, ws->counters, ws->span_meta, ws->span_rows, ws->counters + V,

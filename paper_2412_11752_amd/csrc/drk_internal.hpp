@@ -12,6 +12,7 @@ constexpr int kTile = 16;            // 16x16 screen tiles (Sec. 4.4 Kernel Cull
 constexpr int kMaxK = 16;            // radial bases per primitive
 constexpr int kMaxViews = 8;         // views per launch
 constexpr int kMaxTileRows = 136;    // tile rows per view (image height <= 2176)
+constexpr int kSpanPools = 64;       // span-row pools per view (one fill counter each)
 constexpr int kMaxCache = 8;         // cache slots (Sec. 4.4 Cache Sorting uses 8)
 constexpr int32_t kExactOrder = 1 << 30;   // cache_len at or above this: exact per-pixel depth order
 constexpr uint32_t kCulledKey = 0xFFFFFFFFu;

@@ -10,6 +10,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace drk {
 
 constexpr double kPi = 3.141592653589793;
@@ -80,20 +82,27 @@ __device__ inline void real_sh(int deg, double x, double y, double z, double Y[1
 }
 
 // ---------------------------------------------------------------------------------------------
-// Per-primitive geometry in float64.
-struct Geo {
+// Per-primitive geometry in float64.  GeoBase holds no per-basis arrays (kernels that need the
+// bases read them from the scene), so that it lives in registers; Geo adds them for the sequential
+// polygon walk of the duplication rebuild.
+struct GeoBase {
   double tu[3], tv[3];      // world tangent axes (columns of R(q))
   double mu[3];
   double muc[3];            // camera-frame centre
   double o, tau;
   double c;                 // calibrated radius: {E <= c^2} == {o Psi(g) >= alpha_min}
-  double s[kMaxK], th[kMaxK];
+  double smax;              // max_k s_k
   int K;
 };
+struct Geo : GeoBase {
+  double s[kMaxK], th[kMaxK];
+};
 
-// Loads and validates primitive j.  Returns false when it can never contribute.
-__device__ inline bool load_geo(const SceneDev& sc, int64_t j, const CamDev& cam, const OptsDev& opt, Geo& g,
-                                bool* invalid) {
+// Loads and validates primitive j (the bases streamed from the scene; stored in s_out / th_out when
+// given).  Returns false when it can never contribute.
+template <typename T>
+__device__ inline bool load_geo_core(const SceneDev& sc, int64_t j, const CamDev& cam, const OptsDev& opt, GeoBase& g,
+                                     bool* invalid, T* s_out, T* th_out) {
   const int64_t n = sc.n;
   const int K = sc.K;
   g.K = K;
@@ -106,17 +115,21 @@ __device__ inline bool load_geo(const SceneDev& sc, int64_t j, const CamDev& cam
   for (int i = 0; i < 4; ++i) { q[i] = (double)sc.q[i * n + j]; bad |= !isfinite(q[i]); }
   double qq = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
   bad |= !(qq > 0.0);
+  double smax = 0.0;
+  const double th0 = (double)sc.theta[j];
+  double thk = th0;
   for (int k = 0; k < K; ++k) {
-    g.s[k] = (double)sc.scale[k * n + j];
-    g.th[k] = (double)sc.theta[k * n + j];
-    bad |= !(g.s[k] > 0.0) || !isfinite(g.s[k]);
-    bad |= !(g.th[k] >= 0.0) || !(g.th[k] < kTwoPi);
-  }
-  for (int k = 0; k < K; ++k) {
-    double nxt = (k + 1 < K) ? g.th[k + 1] : g.th[0] + kTwoPi;
-    double gap = nxt - g.th[k];
+    const double sk = (double)sc.scale[k * n + j];
+    const double nxt = (k + 1 < K) ? (double)sc.theta[(k + 1) * n + j] : th0 + kTwoPi;
+    if (s_out) { s_out[k] = (T)sk; th_out[k] = (T)thk; }
+    bad |= !(sk > 0.0) || !isfinite(sk);
+    bad |= !(thk >= 0.0) || !(thk < kTwoPi);
+    const double gap = nxt - thk;
     bad |= !(gap > 0.0) || !(gap < kPi);
+    smax = fmax(smax, sk);
+    thk = nxt;
   }
+  g.smax = smax;
   g.o = (double)sc.opacity[j];
   g.tau = (double)sc.tau[j];
   double eta = (double)sc.eta[j];
@@ -133,6 +146,11 @@ __device__ inline bool load_geo(const SceneDev& sc, int64_t j, const CamDev& cam
   double gmin = psi_inv((double)opt.alpha_min / g.o, g.tau);
   g.c = sqrt(-2.0 * log(gmin));
   return true;
+}
+
+__device__ inline bool load_geo(const SceneDev& sc, int64_t j, const CamDev& cam, const OptsDev& opt, Geo& g,
+                                bool* invalid) {
+  return load_geo_core(sc, j, cam, opt, g, invalid, g.s, g.th);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -263,7 +281,7 @@ __device__ inline void close_polygon(Spans& sp, const CamDev& cam, double nearp)
 }
 
 // tangent-plane (x, y) -> camera frame
-__device__ inline void lift(const Geo& g, const CamDev& cam, double x, double y, double out[3]) {
+__device__ inline void lift(const GeoBase& g, const CamDev& cam, double x, double y, double out[3]) {
   double w[3];
   for (int i = 0; i < 3; ++i) w[i] = (g.mu[i] + x * g.tu[i]) + y * g.tv[i];
   to_cam(cam, w, out);
@@ -373,21 +391,41 @@ __device__ inline float diamond_angle(float c, float s) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Conservative frustum test.  The support polygon lies in the disc of radius sqrt(2) c max_k s_k
-// around the centre (its half-sector quads reach rho / cos(h) with rho <= c max s_k, h < pi/4); if
-// that ball is entirely outside one side plane of the view (pixel x = 0 or W, y = 0 or H) no part of
-// the near-clipped polygon can reach a pixel centre (0.5 px inside those planes), and the low-pass
-// square is tested directly.  Culling here never removes a tile the polygon would produce.
-__device__ inline bool outside_view(const Geo& g, const CamDev& cam, const OptsDev& opt) {
-  double smax = 0.0;
-  for (int k = 0; k < g.K; ++k) smax = fmax(smax, g.s[k]);
-  const double R = 1.4142135623730951 * g.c * smax * (1.0 + 1e-9) + 1e-12;
+// Conservative frustum test.  The support polygon lies in the tangent-plane disc of radius
+// sqrt(2) c max_k s_k around the centre (its half-sector quads reach rho / cos(h) with
+// rho <= c max s_k, h < pi/4); the endpoint polygon of cull mode 1 in that of radius f max_k s_k.  Over that disc a side plane's linear form a . x (pixel x = 0 or W,
+// y = 0 or H) ranges over a . mu_c +- R |a - (a . n) n|, n the disc's unit normal; if the whole range
+// is on the outer side, no part of the near-clipped polygon can reach a pixel centre (0.5 px inside
+// those planes).  The extent carries a margin of 1e-6 |a| (rounding of |a|^2 - (a . n)^2 near zero,
+// and of n's length) and R one of 1e-9 relative.  The low-pass square is tested directly.  Culling
+// here never removes a tile the polygon would produce.
+__device__ inline double disc_extent(double ax, double ay, double az, const double n[3]) {
+  const double aa = (ax * ax + ay * ay) + az * az;
+  const double an = (ax * n[0] + ay * n[1]) + az * n[2];
+  return sqrt(fmax(aa - an * an, 0.0) + 1e-12 * aa);
+}
+
+__device__ inline bool outside_view(const GeoBase& g, const CamDev& cam, const OptsDev& opt) {
+  // disc radius: sqrt(2) c max_k s_k for the support polygon; for the paper's endpoint polygon
+  // (cull mode 1, vertices at s_k f) f max_k s_k
+  double rad = 1.4142135623730951 * g.c;
+  if (opt.cull_mode == 1) {
+    const double y = exp(-9.0) / g.o;
+    const double gm = psi_inv(y < 1.0 ? y : 1.0, g.tau);
+    const double ml = -log(gm);
+    rad = sqrt(ml > 0.0 ? ml : 0.0);
+  }
+  const double R = rad * g.smax * (1.0 + 1e-9) + 1e-12;
   const double X = g.muc[0], Y = g.muc[1], Z = g.muc[2];
   const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy, W = cam.W, H = cam.H;
-  bool out = (fx * X + cx * Z) < -R * sqrt(fx * fx + cx * cx) ||
-             (fx * X + (cx - W) * Z) > R * sqrt(fx * fx + (cx - W) * (cx - W)) ||
-             (fy * Y + cy * Z) < -R * sqrt(fy * fy + cy * cy) ||
-             (fy * Y + (cy - H) * Z) > R * sqrt(fy * fy + (cy - H) * (cy - H));
+  const double nw[3] = {g.tu[1] * g.tv[2] - g.tu[2] * g.tv[1], g.tu[2] * g.tv[0] - g.tu[0] * g.tv[2],
+                        g.tu[0] * g.tv[1] - g.tu[1] * g.tv[0]};
+  double n[3];
+  rot_cam(cam, nw, n);
+  bool out = (fx * X + cx * Z) < -R * disc_extent(fx, 0.0, cx, n) ||
+             (fx * X + (cx - W) * Z) > R * disc_extent(fx, 0.0, cx - W, n) ||
+             (fy * Y + cy * Z) < -R * disc_extent(0.0, fy, cy, n) ||
+             (fy * Y + (cy - H) * Z) > R * disc_extent(0.0, fy, cy - H, n);
   if (out && opt.lowpass_sl > 0.0f) {
     const double ratio = g.o / (double)opt.alpha_min;
     const double r = (double)opt.lowpass_sl * sqrt(2.0 * log(ratio > 1.0 ? ratio : 1.0));
@@ -397,21 +435,6 @@ __device__ inline bool outside_view(const Geo& g, const CamDev& cam, const OptsD
     out = sq_out;
   }
   return out;
-}
-
-// Per-lane offsets from one atomic per wave (all lanes of the wave must call it).
-__device__ inline uint32_t wave_alloc(uint32_t* ctr, uint32_t n) {
-  const int lane = threadIdx.x & 63;
-  uint32_t inc = n;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += y;
-  }
-  const uint32_t total = __shfl(inc, 63, 64);
-  uint32_t base = 0;
-  if (lane == 0 && total) base = atomicAdd(ctr, total);
-  base = __shfl(base, 0, 64);
-  return base + inc - n;
 }
 
 // Per-thread offsets from one atomic per workgroup of NWAVES waves (every thread of the block must
@@ -442,9 +465,11 @@ __device__ inline uint32_t block_alloc(uint32_t* ctr, uint32_t n) {
   return s_part[NWAVES] + s_part[wv] + inc - n;
 }
 
-// Render record of a visible primitive (layout: RecField / SecField).
-__device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const CamDev& cam, const OptsDev& opt,
-                             const double box[4], float* rec, double* kg) {
+// Render record of a visible primitive (layout: RecField / SecField), and its per-tile key data when
+// kg is given; the support polygon's box (R_BOX, KG_BOX) is written by the polygon kernel.  The
+// bases are read from the scene.
+__device__ void write_record(const GeoBase& g, const SceneDev& sc, int64_t j, const CamDev& cam, const OptsDev& opt,
+                             float* rec, double* kg) {
   const int64_t n = sc.n;
   const int K = sc.K;
   // homography: adjugate rows of N = [t_u^c | t_v^c | mu_c]
@@ -457,8 +482,7 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
   double a2[3] = {tuc[1] * tvc[2] - tuc[2] * tvc[1], tuc[2] * tvc[0] - tuc[0] * tvc[2],
                   tuc[0] * tvc[1] - tuc[1] * tvc[0]};
   double dN = a2[0] * m[0] + a2[1] * m[1] + a2[2] * m[2];
-  double smax = 0.0;
-  for (int k = 0; k < K; ++k) smax = fmax(smax, g.s[k]);
+  const double smax = g.smax;
   if (kg) {
     // per-tile key data: the plane, and the depth range of the disc of radius sqrt(2) c max_k s_k
     // around the centre, which holds the support polygon (its half-sector quads reach rho / cos(h)
@@ -469,7 +493,6 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
     kg[KG_ZC] = m[2];
     kg[KG_ZLO] = fmax(m[2] - zr, (double)opt.near_plane);
     kg[KG_ZHI] = m[2] + zr;
-    for (int i = 0; i < 4; ++i) kg[KG_BOX + i] = box[i];
   }
   double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
   double pxc = (fx * m[0]) / m[2] + cx, pyc = (fy * m[1]) / m[2] + cy;
@@ -515,10 +538,6 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
     const double sgn = dN > 0.0 ? -1.0 : 1.0;
     for (int i = 0; i < 3; ++i) rec[R_NRM + i] = (float)(sgn * a2[i] / na);
   }
-  rec[R_BOX + 0] = (float)(box[0] - 0.01);
-  rec[R_BOX + 1] = (float)(box[1] + 0.01);
-  rec[R_BOX + 2] = (float)(box[2] - 0.01);
-  rec[R_BOX + 3] = (float)(box[3] + 0.01);
   if (sc.color_mode == 0) {
     for (int c = 0; c < 3; ++c) rec[R_RGB + c] = sc.color[c * n + j];
   } else {
@@ -539,10 +558,10 @@ __device__ void write_record(const Geo& g, const SceneDev& sc, int64_t j, const 
   }
   for (int k = 0; k < K; ++k) {
     int kn = (k + 1 < K) ? k + 1 : 0;
-    double thk = g.th[k];
-    double thn = (k + 1 < K) ? g.th[k + 1] : g.th[0] + kTwoPi;
+    double thk = (double)sc.theta[k * n + j];
+    double thn = (k + 1 < K) ? (double)sc.theta[(k + 1) * n + j] : (double)sc.theta[j] + kTwoPi;
     double dl = thn - thk;
-    double sk = g.s[k], sn = g.s[kn];
+    double sk = (double)sc.scale[k * n + j], sn = (double)sc.scale[kn * n + j];
     float cf = (float)cos(thk), sf = (float)sin(thk);
     rec[R_SEC + S_PA * K + k] = diamond_angle(cf, sf);
     rec[R_SEC + S_C * K + k] = cf;
@@ -572,9 +591,9 @@ __global__ void __launch_bounds__(kPreBlock) k_preprocess(SceneDev sc, const Vie
   const CamDev& cam = views->cam[v];
   bool maybe = false;
   if (j < sc.n) {
-    Geo g;
+    GeoBase g;
     bool invalid = false;
-    const bool alive = load_geo(sc, j, cam, opt, g, &invalid);
+    const bool alive = load_geo_core<double>(sc, j, cam, opt, g, &invalid, nullptr, nullptr);
     if (invalid && opt.validate) atomicOr(status + v, (uint32_t)ST_INVALID);
     maybe = alive && (opt.cull_mode == 2 || !outside_view(g, cam, opt));
     depth_keys[(int64_t)v * stride + j] = maybe ? __float_as_uint((float)g.muc[2]) : kCulledKey;
@@ -584,73 +603,411 @@ __global__ void __launch_bounds__(kPreBlock) k_preprocess(SceneDev sc, const Vie
   if (maybe) work[(int64_t)v * stride + slot] = (uint32_t)j;
 }
 
-// Pass 2, one thread per listed primitive: support polygon -> tile-row spans -> tile count, the
-// spans kept for the duplication pass (rows of one primitive contiguous; kNoSpans when the row
-// buffer is full, then the duplication recomputes them), and the render record.
-__global__ void __launch_bounds__(128) k_polygon(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
-                                                 float* __restrict__ records, uint32_t* __restrict__ depth_keys,
-                                                 uint32_t* __restrict__ tile_counts,
-                                                 const uint32_t* __restrict__ work,
-                                                 const uint32_t* __restrict__ work_count,
-                                                 uint2* __restrict__ span_meta, uint32_t* __restrict__ span_rows,
-                                                 uint32_t* __restrict__ rows_used, int64_t row_cap, int64_t stride,
-                                                 double* __restrict__ keygeo) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// ---------------------------------------------------------------------------------------------
+// Pass 2: the support polygon of each listed primitive, wave-parallel.  A wave takes a batch of
+// work items, loads their geometry one item per lane, then builds the tile-row spans of one item at
+// a time with all its lanes: the lanes take the polygon's vertices, then its edges (each clipped to
+// the near plane and cut into tile-row slabs with the float64 expressions of the sequential walk
+// above), and the rows' x-extents meet in LDS through exact 64-bit min / max on an order-preserving
+// encoding of the doubles.  A minimum or a maximum does not depend on the order of its operands, so
+// the spans, tile counts and box equal the sequential walk's bit for bit.  Outputs: the tile count,
+// the row spans for the duplication pass (kNoSpans when the item's row pool is full, then the
+// duplication re-derives them), and the record's box; the rest of the record is written by k_record.
+constexpr int kPolyWaves = 4;           // waves per workgroup
+constexpr int kPolyBatch = 8;           // work items per wave batch
+constexpr int kMaxPolyV = 6 * kMaxK;    // support polygon vertices (cull mode 0: six per sector)
+constexpr int kFixedRows = 8;           // span rows reserved per work-list position
+static_assert(kMaxPolyV <= 128, "edge exit masks cover two 64-edge chunks");
+
+// Order-preserving encoding: unsigned order of the codes is the order of the (non-NaN) doubles.
+__device__ inline uint64_t ord_enc(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ inline double ord_dec(uint64_t e) {
+  return __longlong_as_double((long long)((e >> 63) ? (e & 0x7FFFFFFFFFFFFFFFull) : ~e));
+}
+constexpr uint64_t kEncPosInf = 0xFFF0000000000000ull;   // ord_enc(+inf)
+constexpr uint64_t kEncNegInf = 0x000FFFFFFFFFFFFFull;   // ord_enc(-inf)
+
+// Orders this lane's LDS accesses before and after against the other lanes of its wave.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct PolyLds {
+  uint64_t lo[kMaxTileRows], hi[kMaxTileRows];       // encoded x-extent of each tile row
+  double vx[kMaxPolyV], vy[kMaxPolyV], vz[kMaxPolyV];  // camera-frame vertices
+  double px[kMaxPolyV], py[kMaxPolyV];                 // their pixel coordinates (in front of the near plane)
+  double ix[kMaxPolyV], iy[kMaxPolyV];                 // pixel coordinates of edge e's near-plane crossing
+  GeoBase geo[kPolyBatch];                             // the batch's geometry
+  float s[kPolyBatch][kMaxK], th[kPolyBatch][kMaxK];   // and its bases (the scene's float32 values)
+  uint32_t item[kPolyBatch];                           // the batch's primitive indices
+  double lp[kPolyBatch][3];                            // low-pass square: projected centre, half-width
+  double f1[kPolyBatch];                               // cull mode 1: endpoint polygon factor
+  uint64_t box[4];                                     // encoded box (x0, -x1, y0, -y1: all minima)
+  int rows[2];                                         // touched rows [rows[0], -rows[1]] (minima)
+  uint32_t cnt;                                        // tile count
+};
+
+// Per-lane part of the spans: box of the lane's segments and the rows they touched.
+struct LaneSpans {
+  double bx0, bx1, by0, by1;
+  int r0, r1;
+};
+
+// One screen segment (x0,y0)-(x1,y1) against the tile-row slabs it may cross (the expressions of
+// spans_segment; the row extents go to LDS).
+__device__ inline void lane_segment(PolyLds& L, LaneSpans& a, int ty, int H, double x0, double y0, double x1,
+                                    double y1) {
+  const double ymin = fmin(y0, y1), ymax = fmax(y0, y1);
+  a.bx0 = fmin(a.bx0, fmin(x0, x1));
+  a.bx1 = fmax(a.bx1, fmax(x0, x1));
+  a.by0 = fmin(a.by0, ymin);
+  a.by1 = fmax(a.by1, ymax);
+  const double fa = floor((ymin - 15.5) / 16.0), fb = ceil((ymax - 0.5) / 16.0);
+  if (!(fb >= 0.0) || !(fa <= (double)(ty - 1))) return;
+  const int ra = fa < 0.0 ? 0 : (int)fa;
+  const int rb = fb > (double)(ty - 1) ? ty - 1 : (int)fb;
+  for (int r = ra; r <= rb; ++r) {
+    const double ya = 16.0 * r + 0.5;
+    const double yb = fmin(16.0 * r + 15.5, H - 0.5);
+    if (ymax < ya || ymin > yb) continue;
+    double xa, xb;
+    if (y0 == y1) {
+      xa = x0; xb = x1;
+    } else {
+      const double ta = (ya - y0) / (y1 - y0);
+      const double tb = (yb - y0) / (y1 - y0);
+      const double tlo = fmax(0.0, fmin(ta, tb));
+      const double thi = fmin(1.0, fmax(ta, tb));
+      xa = x0 + tlo * (x1 - x0);
+      xb = x0 + thi * (x1 - x0);
+    }
+    a.r0 = min(a.r0, r);
+    a.r1 = max(a.r1, r);
+    const double xl = fmin(xa, xb), xh = fmax(xa, xb);
+    if (xl == xl) atomicMin(&L.lo[r], ord_enc(xl));   // fmin ignores a NaN operand; so does this
+    if (xh == xh) atomicMax(&L.hi[r], ord_enc(xh));
+  }
+}
+
+// Index of the exit edge that precedes edge e around the polygon (exit edges: bits of m0 for edges
+// 0-63, of m1 for edges 64-127; at least one is set).
+__device__ inline int prev_exit(uint64_t m0, uint64_t m1, int e) {
+  if (e >= 64) {
+    const int b = e - 64;
+    const uint64_t below = b ? (m1 & ((1ull << b) - 1ull)) : 0ull;
+    if (below) return 64 + 63 - __clzll((long long)below);
+    if (m0) return 63 - __clzll((long long)m0);
+    return 64 + 63 - __clzll((long long)m1);
+  }
+  const uint64_t below = e ? (m0 & ((1ull << e) - 1ull)) : 0ull;
+  if (below) return 63 - __clzll((long long)below);
+  if (m1) return 64 + 63 - __clzll((long long)m1);
+  return 63 - __clzll((long long)m0);
+}
+
+__global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_per_eu(3))) k_polygon(SceneDev sc, const Views* __restrict__ views,
+                                                            OptsDev opt, float* __restrict__ records,
+                                                            uint32_t* __restrict__ depth_keys,
+                                                            uint32_t* __restrict__ tile_counts,
+                                                            const uint32_t* __restrict__ work,
+                                                            const uint32_t* __restrict__ work_count,
+                                                            uint2* __restrict__ span_meta,
+                                                            uint32_t* __restrict__ span_rows,
+                                                            uint32_t* __restrict__ pool_used, int64_t row_cap,
+                                                            int64_t stride, double* __restrict__ keygeo) {
+  __shared__ PolyLds s_lds[kPolyWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  PolyLds& L = s_lds[wv];
   const int v = blockIdx.y;
   const CamDev& cam = views->cam[v];
-  const bool active = i < (int64_t)work_count[v];
-  const int64_t j = active ? (int64_t)work[(int64_t)v * stride + i] : 0;
-  Geo g;
-  Spans sp;
-  uint32_t count = 0, nrows = 0;
-  bool ok = false;
-  if (active) {
-    bool invalid;
-    ok = load_geo(sc, j, cam, opt, g, &invalid);
-    if (ok) {
+  const int64_t wc = (int64_t)work_count[v];
+  const int64_t n = sc.n;
+  const int K = sc.K;
+  const int ty = cam.tiles_y, tx = cam.tiles_x, W = cam.W, H = cam.H;
+  const double nearp = (double)opt.near_plane;
+  const int V = opt.cull_mode == 1 ? K : 6 * K;
+  // row buffer: kFixedRows rows per work-list position when it holds them (no allocation for items
+  // of at most that many rows), then kSpanPools pools filled by atomic counters
+  const int64_t fixed_rows =
+      row_cap >= (int64_t)kFixedRows * stride + (int64_t)kSpanPools * 64 ? (int64_t)kFixedRows * stride : 0;
+  const int64_t pool_rows = (row_cap - fixed_rows) / kSpanPools;
+  for (int r = lane; r < kMaxTileRows; r += 64) { L.lo[r] = kEncPosInf; L.hi[r] = kEncNegInf; }
+  if (lane < 4) L.box[lane] = kEncPosInf;
+  if (lane < 2) L.rows[lane] = kMaxTileRows;
+  if (lane == 0) L.cnt = 0;
+  for (int64_t b = (int64_t)blockIdx.x * kPolyWaves + wv; b * kPolyBatch < wc; b += (int64_t)gridDim.x * kPolyWaves) {
+    const int64_t first = b * kPolyBatch;
+    const int nb = (int)min((int64_t)kPolyBatch, wc - first);
+    wave_sync();   // the previous batch's geometry has been read
+    bool mine_ok = false;
+    if (lane < nb) {
+      const uint32_t mine_j = work[(int64_t)v * stride + first + lane];
+      bool invalid;
+      GeoBase mine;
+      mine_ok = load_geo_core<float>(sc, mine_j, cam, opt, mine, &invalid, L.s[lane], L.th[lane]);
+      L.geo[lane] = mine;
+      L.item[lane] = mine_j;
+      if (opt.lowpass_sl > 0.0f) {
+        const double ratio = mine.o / (double)opt.alpha_min;
+        project(cam, mine.muc, L.lp[lane][0], L.lp[lane][1]);
+        L.lp[lane][2] = (double)opt.lowpass_sl * sqrt(2.0 * log(ratio > 1.0 ? ratio : 1.0));
+      }
+      if (opt.cull_mode == 1) {
+        const double y = exp(-9.0) / mine.o;
+        const double gm = psi_inv(y < 1.0 ? y : 1.0, mine.tau);
+        const double ml = -log(gm);
+        L.f1[lane] = sqrt(ml > 0.0 ? ml : 0.0);
+      }
+    }
+    const uint64_t ok_mask = __ballot(mine_ok);
+    const uint32_t pool = (uint32_t)(b % kSpanPools);
+    wave_sync();
+    for (int it = 0; it < nb; ++it) {
+      if (!((ok_mask >> it) & 1ull)) continue;
+      const int64_t j = (int64_t)L.item[it];
+      const GeoBase& g = L.geo[it];
+      const int64_t o = (int64_t)v * stride + j;
       if (opt.cull_mode == 2) {
-        count = (uint32_t)(cam.tiles_x * cam.tiles_y);
-      } else {
-        build_spans(g, cam, opt, sp);
-        for (int r = sp.r0; r <= sp.r1; ++r) {
-          int i0, i1;
-          if (row_tiles(sp, r, i0, i1)) count += (uint32_t)(i1 - i0 + 1);
+        if (lane == 0) {
+          tile_counts[o] = (uint32_t)(tx * ty);
+          float* rec = records + o * rec_floats(K);
+          rec[R_BOX + 0] = (float)(-1e30 - 0.01); rec[R_BOX + 1] = (float)(1e30 + 0.01);
+          rec[R_BOX + 2] = (float)(-1e30 - 0.01); rec[R_BOX + 3] = (float)(1e30 + 0.01);
+          if (opt.key_mode != 0) {
+            double* kg = keygeo + o * KG_N;
+            kg[KG_BOX + 0] = -1e30; kg[KG_BOX + 1] = 1e30; kg[KG_BOX + 2] = -1e30; kg[KG_BOX + 3] = 1e30;
+          }
         }
-        if (count) nrows = (uint32_t)(sp.r1 - sp.r0 + 1);
+        continue;
+      }
+      wave_sync();   // the previous item's LDS reads are done
+      // vertices (lanes over the polygon's vertices), camera frame, and projected when in front
+      const double f1 = opt.cull_mode == 1 ? L.f1[it] : 0.0;
+      for (int q = lane; q < V; q += 64) {
+        double x, y;
+        if (opt.cull_mode == 1) {
+          const double s1 = (double)L.s[it][q] * f1;
+          const double th = (double)L.th[it][q];
+          x = s1 * cos(th);
+          y = s1 * sin(th);
+        } else {
+          // half-sector quads of sector k (the sequential walk's expressions)
+          const int k = q / 6, m = q - 6 * k;
+          const double thk = (double)L.th[it][k];
+          const double thn = (k + 1 < K) ? (double)L.th[it][k + 1] : (double)L.th[it][0] + kTwoPi;
+          const double sk = (double)L.s[it][k], sn = (double)L.s[it][(k + 1) % K];
+          const double dl = thn - thk;
+          const double sbar_mid = 1.0 / sqrt(0.5 * (1.0 / (sk * sk) + 1.0 / (sn * sn)));
+          const double chord_mid = 2.0 * cos(0.5 * dl) / (1.0 / sk + 1.0 / sn);
+          const double r_mid = fmax(sbar_mid, chord_mid);
+          double rad = g.c * fmax(m < 3 ? sk : sn, r_mid);
+          if (m == 1 || m == 4) rad = rad * (1.0 / cos(0.25 * dl));
+          const double ang = m == 0 ? thk : m == 1 ? thk + 0.25 * dl : m == 4 ? thk + 0.75 * dl : m == 5 ? thn
+                                                                                                  : thk + 0.5 * dl;
+          x = rad * cos(ang);
+          y = rad * sin(ang);
+        }
+        double w[3], p[3];
+        for (int i = 0; i < 3; ++i) w[i] = (g.mu[i] + x * g.tu[i]) + y * g.tv[i];
+        to_cam(cam, w, p);
+        L.vx[q] = p[0]; L.vy[q] = p[1]; L.vz[q] = p[2];
+        double pxy[2] = {0.0, 0.0};
+        if (p[2] >= nearp) project(cam, p, pxy[0], pxy[1]);
+        L.px[q] = pxy[0]; L.py[q] = pxy[1];
+      }
+      wave_sync();
+      // edges: near-plane crossings, and the exit edges as masks
+      uint64_t exits[2] = {0ull, 0ull};
+      for (int c = 0; c * 64 < V; ++c) {
+        const int e = c * 64 + lane;
+        bool is_exit = false;
+        if (e < V) {
+          const int f = e + 1 < V ? e + 1 : 0;
+          const double az = L.vz[e], bz = L.vz[f];
+          const bool ain = az >= nearp, bin = bz >= nearp;
+          if (ain != bin) {
+            const double t = (nearp - az) / (bz - az);
+            double I[3];
+            I[0] = L.vx[e] + t * (L.vx[f] - L.vx[e]);
+            I[1] = L.vy[e] + t * (L.vy[f] - L.vy[e]);
+            I[2] = az + t * (bz - az);
+            double ix, iy;
+            project(cam, I, ix, iy);
+            L.ix[e] = ix; L.iy[e] = iy;
+          }
+          is_exit = ain && !bin;
+        }
+        exits[c] = __ballot(is_exit);
+      }
+      wave_sync();
+      // segments: the kept part of each edge, and from each entry back to the preceding exit
+      LaneSpans a;
+      a.bx0 = a.by0 = INFINITY;
+      a.bx1 = a.by1 = -INFINITY;
+      a.r0 = kMaxTileRows; a.r1 = -1;
+      for (int e = lane; e < V; e += 64) {
+        const int f = e + 1 < V ? e + 1 : 0;
+        const bool ain = L.vz[e] >= nearp, bin = L.vz[f] >= nearp;
+        // up to two segments per edge, walked through one call site
+        const int nseg = ain ? 1 : (bin ? 2 : 0);
+        const int x = (!ain && bin) ? prev_exit(exits[0], exits[1], e) : e;
+        for (int k = 0; k < nseg; ++k) {
+          double x0, y0, x1, y1;
+          if (ain) {                      // kept edge, or its part up to the exit
+            x0 = L.px[e]; y0 = L.py[e];
+            x1 = bin ? L.px[f] : L.ix[e];
+            y1 = bin ? L.py[f] : L.iy[e];
+          } else if (k == 0) {            // from the preceding exit to this entry
+            x0 = L.ix[x]; y0 = L.iy[x]; x1 = L.ix[e]; y1 = L.iy[e];
+          } else {                        // from this entry on
+            x0 = L.ix[e]; y0 = L.iy[e]; x1 = L.px[f]; y1 = L.py[f];
+          }
+          lane_segment(L, a, ty, H, x0, y0, x1, y1);
+        }
+      }
+      // low-pass support: square of half-width s_l sqrt(2 ln(o / alpha_min)) around the projected centre
+      if (opt.lowpass_sl > 0.0f) {
+        const double dcx = L.lp[it][0], dcy = L.lp[it][1], r = L.lp[it][2];
+        if (lane == 0) {
+          a.bx0 = fmin(a.bx0, dcx - r);
+          a.bx1 = fmax(a.bx1, dcx + r);
+          a.by0 = fmin(a.by0, dcy - r);
+          a.by1 = fmax(a.by1, dcy + r);
+        }
+        for (int row = lane; row < ty; row += 64) {
+          const double ya = 16.0 * row + 0.5;
+          const double yb = fmin(16.0 * row + 15.5, H - 0.5);
+          if (dcy + r >= ya && dcy - r <= yb) {
+            a.r0 = min(a.r0, row);
+            a.r1 = max(a.r1, row);
+            const double xl = dcx - r, xh = dcx + r;
+            if (xl == xl) atomicMin(&L.lo[row], ord_enc(xl));
+            if (xh == xh) atomicMax(&L.hi[row], ord_enc(xh));
+          }
+        }
+      }
+      // the lanes' boxes and row ranges meet in LDS (a lane with no segment holds the neutral values;
+      // its box is never NaN: fmin / fmax above drop NaN operands)
+      if (a.r0 <= a.r1) {
+        atomicMin(&L.rows[0], a.r0);
+        atomicMin(&L.rows[1], -a.r1);
+      }
+      if (a.bx0 <= a.bx1 || a.by0 <= a.by1) {
+        atomicMin(&L.box[0], ord_enc(a.bx0));
+        atomicMin(&L.box[1], ord_enc(-a.bx1));
+        atomicMin(&L.box[2], ord_enc(a.by0));
+        atomicMin(&L.box[3], ord_enc(-a.by1));
+      }
+      wave_sync();
+      const int r0 = L.rows[0], r1 = -L.rows[1];
+      // tile columns of each touched row (row_tiles), the count, and the rows reset for the next item
+      constexpr int kRowIters = (kMaxTileRows + 63) / 64;
+      uint32_t ent[kRowIters];
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int c = 0; c < kRowIters; ++c) {
+        const int r = r0 + c * 64 + lane;
+        ent[c] = 0xFFFFFFFFu;
+        if (r <= r1) {
+          const double lo = fmax(ord_dec(L.lo[r]), 0.5);
+          const double hi = fmin(ord_dec(L.hi[r]), W - 0.5);
+          L.lo[r] = kEncPosInf;
+          L.hi[r] = kEncNegInf;
+          if (!(lo > hi)) {
+            const double ca = ceil((lo - 15.5) / 16.0);
+            const double cb = floor((hi - 0.5) / 16.0);
+            const int i0 = ca < 0.0 ? 0 : (int)ca;
+            const int i1 = cb > (double)(tx - 1) ? tx - 1 : (int)cb;
+            if (i0 <= i1) {
+              cnt += (uint32_t)(i1 - i0 + 1);
+              ent[c] = (uint32_t)i0 | ((uint32_t)i1 << 16);
+            }
+          }
+        }
+      }
+      if (cnt) atomicAdd(&L.cnt, cnt);
+      wave_sync();
+      cnt = L.cnt;
+      const double bx0 = ord_dec(L.box[0]), bx1 = -ord_dec(L.box[1]);
+      const double by0 = ord_dec(L.box[2]), by1 = -ord_dec(L.box[3]);
+      wave_sync();
+      if (lane < 4) L.box[lane] = kEncPosInf;
+      if (lane < 2) L.rows[lane] = kMaxTileRows;
+      if (lane == 0) L.cnt = 0;
+      if (cnt == 0) {
+        if (lane == 0) {
+          tile_counts[o] = 0;
+          depth_keys[o] = kCulledKey;
+        }
+        continue;
+      }
+      const uint32_t nrows = (uint32_t)(r1 - r0 + 1);
+      int64_t at;
+      bool fits;
+      if (fixed_rows != 0 && nrows <= (uint32_t)kFixedRows) {
+        at = (first + it) * kFixedRows;
+        fits = true;
+      } else {
+        uint32_t off = 0;
+        if (lane == 0) off = atomicAdd(pool_used + (int64_t)v * kSpanPools + pool, nrows);
+        off = (uint32_t)__builtin_amdgcn_readlane((int)off, 0);
+        at = fixed_rows + (int64_t)pool * pool_rows + off;
+        fits = (int64_t)off + nrows <= pool_rows;
+      }
+      fits = fits && at + nrows < (int64_t)kNoSpans;   // offsets are stored in 32 bits
+      if (fits) {
+        uint32_t* out = span_rows + (int64_t)v * row_cap + at;
+#pragma unroll
+        for (int c = 0; c < kRowIters; ++c) {
+          const int r = r0 + c * 64 + lane;
+          if (r <= r1) out[r - r0] = ent[c];
+        }
+      }
+      if (lane == 0) {
+        tile_counts[o] = cnt;
+        uint2 meta;
+        meta.x = fits ? (uint32_t)at : kNoSpans;
+        meta.y = fits ? ((uint32_t)r0 | (nrows << 16)) : 0u;
+        span_meta[o] = meta;
+        // only the conservative polygon bounds the support
+        const double box[4] = {opt.cull_mode == 0 ? bx0 : -1e30, opt.cull_mode == 0 ? bx1 : 1e30,
+                               opt.cull_mode == 0 ? by0 : -1e30, opt.cull_mode == 0 ? by1 : 1e30};
+        float* rec = records + o * rec_floats(K);
+        rec[R_BOX + 0] = (float)(box[0] - 0.01);
+        rec[R_BOX + 1] = (float)(box[1] + 0.01);
+        rec[R_BOX + 2] = (float)(box[2] - 0.01);
+        rec[R_BOX + 3] = (float)(box[3] + 0.01);
+        if (opt.key_mode != 0) {
+          double* kg = keygeo + o * KG_N;
+          for (int i = 0; i < 4; ++i) kg[KG_BOX + i] = box[i];
+        }
       }
     }
   }
-  const uint32_t off = block_alloc<2>(rows_used + v, nrows);
-  if (!active) return;
-  tile_counts[(int64_t)v * stride + j] = count;
-  if (count == 0) {
-    depth_keys[(int64_t)v * stride + j] = kCulledKey;
-    return;
-  }
-  if (nrows) {
-    uint2 meta;
-    if ((int64_t)off + nrows <= row_cap) {
-      meta.x = off;
-      meta.y = (uint32_t)sp.r0 | (nrows << 16);
-      uint32_t* out = span_rows + (int64_t)v * row_cap + off;
-      for (int r = sp.r0; r <= sp.r1; ++r) {
-        int i0, i1;
-        out[r - sp.r0] = row_tiles(sp, r, i0, i1) ? ((uint32_t)i0 | ((uint32_t)i1 << 16)) : 0xFFFFFFFFu;
-      }
-    } else {
-      meta.x = kNoSpans;
-      meta.y = 0;
-    }
-    span_meta[(int64_t)v * stride + j] = meta;
-  }
-  double box[4];
-  if (opt.cull_mode != 0) {   // only the conservative polygon bounds the support
-    box[0] = -1e30; box[1] = 1e30; box[2] = -1e30; box[3] = 1e30;
-  } else {
-    box[0] = sp.bx0; box[1] = sp.bx1; box[2] = sp.by0; box[3] = sp.by1;
-  }
-  write_record(g, sc, j, cam, opt, box, records + ((int64_t)v * stride + j) * rec_floats(sc.K),
-               opt.key_mode != 0 ? keygeo + ((int64_t)v * stride + j) * KG_N : nullptr);
+}
+
+// Pass 3, one thread per listed primitive with tiles: the rest of its render record.
+__global__ void __launch_bounds__(128) k_record(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
+                                                float* __restrict__ records, const uint32_t* __restrict__ tile_counts,
+                                                const uint32_t* __restrict__ work,
+                                                const uint32_t* __restrict__ work_count, int64_t stride,
+                                                double* __restrict__ keygeo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (i >= (int64_t)work_count[v]) return;
+  const int64_t j = (int64_t)work[(int64_t)v * stride + i];
+  const int64_t o = (int64_t)v * stride + j;
+  if (tile_counts[o] == 0) return;
+  const CamDev& cam = views->cam[v];
+  GeoBase g;
+  bool invalid;
+  if (!load_geo_core<double>(sc, j, cam, opt, g, &invalid, nullptr, nullptr)) return;
+  write_record(g, sc, j, cam, opt, records + o * rec_floats(sc.K), opt.key_mode != 0 ? keygeo + o * KG_N : nullptr);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -899,15 +1256,19 @@ hipError_t set_views(Views* d_views, const Views& views, hipStream_t s) {
 
 hipError_t launch_preprocess(const SceneDev& sc, const Views* views, int nv, const OptsDev& opt, float* records,
                              uint32_t* depth_keys, uint32_t* tile_counts, uint32_t* work, uint32_t* work_count,
-                             uint2* span_meta, uint32_t* span_rows, uint32_t* rows_used, int64_t row_cap,
+                             uint2* span_meta, uint32_t* span_rows, uint32_t* pool_used, int64_t row_cap,
                              uint32_t* status, int64_t stride, double* keygeo, hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
   dim3 grid((unsigned)((sc.n + 127) / 128), (unsigned)nv);
   dim3 grid_pre((unsigned)((sc.n + kPreBlock - 1) / kPreBlock), (unsigned)nv);
   hipLaunchKernelGGL(k_preprocess, grid_pre, dim3(kPreBlock), 0, s, sc, views, opt, depth_keys, tile_counts, work,
                      work_count, status, stride);
-  hipLaunchKernelGGL(k_polygon, grid, dim3(128), 0, s, sc, views, opt, records, depth_keys, tile_counts, work,
-                     work_count, span_meta, span_rows, rows_used, row_cap, stride, keygeo);
+  const int64_t batches = (sc.n + kPolyBatch - 1) / kPolyBatch;
+  dim3 grid_poly((unsigned)std::min<int64_t>((batches + kPolyWaves - 1) / kPolyWaves, 2048), (unsigned)nv);
+  hipLaunchKernelGGL(k_polygon, grid_poly, dim3(64 * kPolyWaves), 0, s, sc, views, opt, records, depth_keys,
+                     tile_counts, work, work_count, span_meta, span_rows, pool_used, row_cap, stride, keygeo);
+  hipLaunchKernelGGL(k_record, grid, dim3(128), 0, s, sc, views, opt, records, tile_counts, work, work_count, stride,
+                     keygeo);
   return hipGetLastError();
 }
 
