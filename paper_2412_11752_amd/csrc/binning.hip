@@ -61,14 +61,31 @@ __global__ void __launch_bounds__(1024) k_rs_scan_rows(uint32_t* __restrict__ hi
   hist[(size_t)d * kRsBlocks + tid] = inc - x + wsum[w];
 }
 
+// Stable scatter of one pass.  A block walks its chunk in tiles of kRsTile keys.  Wave w of a tile
+// takes its kRsItems * 64 consecutive keys in rounds of 64 and ranks each key among the equal digits
+// of its wave (ballots over the digit bits, a running per-digit count in LDS that the wave alone
+// updates), so a key's rank follows input order: wave, then round, then lane.  The tile's digit
+// counts are then scanned, the keys are placed in LDS in digit order, and written out from there:
+// consecutive threads write consecutive slots of a digit's run, instead of one scattered word each.
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+__device__ inline void rs_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                            uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                            const uint64_t* __restrict__ d_n, int shift, int bits,
                                                            const uint32_t* __restrict__ hist,
                                                            const uint32_t* __restrict__ tot) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[kRsWaves][256];
+  __shared__ uint32_t base[256];              // global slot of each digit's next key from this block
+  __shared__ uint32_t wrun[kRsWaves][256];    // per wave: keys of each digit ranked so far in the tile
+  __shared__ uint32_t tstart[256];            // start of each digit's run in the tile
   __shared__ uint32_t part[kRsWaves];
+  __shared__ uint32_t sk[kRsTile], sv[kRsTile];
   const int tid = threadIdx.x, b = blockIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const uint32_t mask = (bits >= 32) ? 0xFFFFFFFFu : ((1u << bits) - 1u);
@@ -85,43 +102,86 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const uint32_t* __res
     uint32_t pre = 0;
     for (int i = 0; i < w; ++i) pre += part[i];
     base[tid] = pre + inc - x + hist[(size_t)tid * kRsBlocks + b];
-    for (int i = 0; i < kRsWaves; ++i) wcnt[i][tid] = 0;
+    for (int i = 0; i < kRsWaves; ++i) wrun[i][tid] = 0;
   }
   __syncthreads();
   const uint64_t n = *d_n;
   const uint64_t s = chunk_begin(n, b), e = chunk_begin(n, b + 1);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (uint64_t r0 = s; r0 < e; r0 += kRsThreads) {
-    const uint64_t i = r0 + tid;
-    const bool valid = i < e;
-    uint32_t k = 0, v = 0;
-    if (valid) {
-      k = kin[i];
-      v = vin ? vin[i] : (uint32_t)i;
+  for (uint64_t t0 = s; t0 < e; t0 += kRsTile) {
+    const uint32_t tn = (uint32_t)((e - t0) < (uint64_t)kRsTile ? (e - t0) : (uint64_t)kRsTile);
+    uint32_t key[kRsItems], val[kRsItems], pos[kRsItems];
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+      const uint32_t li = (uint32_t)(w * kRsItems + k) * 64u + (uint32_t)lane;   // slot in the tile
+      const bool valid = li < tn;
+      key[k] = 0;
+      val[k] = 0;
+      pos[k] = 0;
+      if ((uint32_t)(w * kRsItems + k) * 64u >= tn) continue;   // the wave's round is past the tile's end
+      if (valid) {
+        key[k] = kin[t0 + li];
+        val[k] = vin ? vin[t0 + li] : (uint32_t)(t0 + li);
+      }
+      const uint32_t d = (key[k] >> shift) & mask;
+      uint64_t peers = __ballot(valid);
+      for (int bb = 0; bb < bits; ++bb) {
+        const bool set = (d >> bb) & 1u;
+        const uint64_t m = __ballot(set);
+        peers &= set ? m : ~m;
+      }
+      const uint32_t rank = (uint32_t)__popcll(peers & lt);
+      if (valid) pos[k] = wrun[w][d] + rank;
+      rs_wave_sync();
+      if (valid && rank == 0) wrun[w][d] += (uint32_t)__popcll(peers);
+      rs_wave_sync();
     }
-    const uint32_t d = (k >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-    for (int bb = 0; bb < bits; ++bb) {
-      const bool set = (d >> bb) & 1u;
-      const uint64_t m = __ballot(set);
-      peers &= set ? m : ~m;
-    }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
-    if (valid) {
-      uint32_t pos = base[d] + rank;
-      for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][d];
-      kout[pos] = k;
-      vout[pos] = v;
+    // per digit (thread tid = digit): the waves' offsets and the tile's run starts
+    {
+      uint32_t c = 0;
+      for (int i = 0; i < kRsWaves; ++i) {
+        const uint32_t x = wrun[i][tid];
+        wrun[i][tid] = c;        // now the exclusive prefix over the waves
+        c += x;
+      }
+      uint32_t inc = c;
+      for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+      }
+      if (lane == 63) part[w] = inc;
+      __syncthreads();
+      uint32_t pre = 0;
+      for (int i = 0; i < w; ++i) pre += part[i];
+      tstart[tid] = pre + inc - c;
     }
     __syncthreads();
-    uint32_t add = 0;
-    for (int ww = 0; ww < kRsWaves; ++ww) {
-      add += wcnt[ww][tid];
-      wcnt[ww][tid] = 0;
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+      const uint32_t li = (uint32_t)(w * kRsItems + k) * 64u + (uint32_t)lane;
+      if (li < tn) {
+        const uint32_t d = (key[k] >> shift) & mask;
+        const uint32_t at = tstart[d] + wrun[w][d] + pos[k];
+        sk[at] = key[k];
+        sv[at] = val[k];
+      }
     }
-    base[tid] += add;
+    __syncthreads();
+    for (uint32_t i = (uint32_t)tid; i < tn; i += kRsThreads) {
+      const uint32_t k = sk[i];
+      const uint32_t d = (k >> shift) & mask;
+      const uint32_t at = base[d] + (i - tstart[d]);
+      kout[at] = k;
+      vout[at] = sv[i];
+    }
+    __syncthreads();
+    {
+      // advance the digit bases by the tile's counts (next run start minus this one)
+      const uint32_t next = (tid + 1 < 256) ? tstart[tid + 1] : tn;
+      base[tid] += next - tstart[tid];
+      for (int i = 0; i < kRsWaves; ++i) wrun[i][tid] = 0;
+    }
     __syncthreads();
   }
 }

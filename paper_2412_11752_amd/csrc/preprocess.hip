@@ -1289,7 +1289,7 @@ hipError_t launch_duplicate(const SceneDev& sc, const Views* views, const OptsDe
   hipLaunchKernelGGL(k_duplicate, grid, dim3(128), 0, s, sc, views, opt, v, sorted_prims, offsets, tile_counts,
                      span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, n_sorted, big_list, sc.n,
                      big_count, keygeo, pair_keys);
-  hipLaunchKernelGGL(k_duplicate_big, dim3(1024), dim3(kDupBigBlock), 0, s, views, opt, v, sorted_prims, offsets,
+  hipLaunchKernelGGL(k_duplicate_big, dim3(4096), dim3(kDupBigBlock), 0, s, views, opt, v, sorted_prims, offsets,
                      tile_counts, span_meta, span_rows, pair_tiles, pair_prims, total_ptr, capacity, big_list, big_count,
                      keygeo, pair_keys);
   hipLaunchKernelGGL(k_duplicate_rebuild, dim3(512), dim3(128), 0, s, sc, views, opt, v, sorted_prims, offsets,
