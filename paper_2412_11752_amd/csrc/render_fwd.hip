@@ -1,11 +1,12 @@
 // Forward DRK raster (Eq. 1; Sec. 3.3; Sec. 4.1-4.4; Algorithm 1 of the supplement).
 //
 // One 256-lane workgroup (four wave64s) per 16x16 tile; lane = pixel.  The tile's primitive list
-// (ordered by centre depth) is streamed through LDS in batches of kBatch records loaded with
-// coalesced float4 reads.  Every lane evaluates every staged primitive at its pixel; contributors
-// enter the per-pixel sorted cache held in VGPRs, the popped head is composited front to back,
-// and a pixel stops when its transmittance would drop below T_min.  The workgroup leaves the list
-// as soon as all 256 pixels are done.
+// (ordered by centre depth) is streamed through LDS in rounds of kFwdBatch records loaded with
+// coalesced float4 reads.  Every lane evaluates every staged primitive at its pixel whose box
+// reaches its wave's pixels; contributors enter the per-pixel sorted cache (keys in VGPRs,
+// payloads in LDS slots), the popped head is composited front to back, and a pixel stops when its
+// transmittance would drop below T_min.  The workgroup leaves the list as soon as all 256 pixels
+// are done.  The exact-order kernel below keeps rounds of kBatch records.
 #include "raster_common.hpp"
 
 namespace drk {
@@ -19,6 +20,68 @@ constexpr int kFwdPlain = 0, kFwdTrace = 1, kFwdDepthNormal = 2;
 
 // COUNT: also write the per-pixel work counters (instrumentation; the production launch of MODE 0
 // leaves them out).
+// Records staged per round by the forward raster.  Small rounds keep the block's LDS (records plus
+// the cache slots below) at about 20 KB, so that 8 waves fit on each SIMD.
+constexpr int kFwdBatch = 8;
+
+// Cache of the forward raster (Sec. 4.4 Cache Sorting, Algorithm 1) with its payloads in LDS.
+// Registers hold the kMaxCache keys in order and one word of 4-bit slot ids: nibble j names the LDS
+// slot that holds the (alpha, primitive index) of the entry at order position j.  An insertion
+// moves keys and one id word instead of keys and two payload arrays, and writes the newcomer's
+// payload into the slot of the popped head.  The head's payload is also kept in registers, so an
+// emission reads no LDS.  Same entries, same order and same ties as Cache<2>.
+struct CacheSlots {
+  float key[kMaxCache];
+  uint32_t ids;
+  float head_a;
+  uint32_t head_i;
+  uint2* slots;       // this lane's slots, kBlock apart
+
+  __device__ __forceinline__ void init(int cache_len, uint2* lds_slots, int tid) {
+#pragma unroll
+    for (int s = 0; s < kMaxCache; ++s) key[s] = (s < cache_len) ? -INFINITY : INFINITY;
+    ids = 0x76543210u;
+    head_a = 0.0f;
+    head_i = 0u;
+    slots = lds_slots + tid;
+#pragma unroll
+    for (int s = 0; s < kMaxCache; ++s) slots[s * kBlock] = make_uint2(0u, 0u);
+  }
+  __device__ __forceinline__ uint2 at_position(int j) const {
+    return slots[((ids >> (4 * j)) & 0xFu) * kBlock];
+  }
+  // Drops position 0 and inserts (z; a, idx) after every key <= z (the caller has read the head).
+  __device__ __forceinline__ void pop_insert(float z, float a, uint32_t idx) {
+    static_assert(kMaxCache == 8, "eight 4-bit slot ids in one word");
+    bool b[kMaxCache - 1];
+    uint32_t p = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxCache - 1; ++j) {
+      b[j] = key[j + 1] <= z;
+      p += b[j] ? 1u : 0u;
+    }
+    key[0] = b[0] ? key[1] : z;
+#pragma unroll
+    for (int j = 1; j < kMaxCache - 1; ++j) key[j] = b[j] ? key[j + 1] : (b[j - 1] ? z : key[j]);
+    key[kMaxCache - 1] = b[kMaxCache - 2] ? z : key[kMaxCache - 1];
+    // positions < p take the ids of positions 1..p, position p the freed slot, the rest stay
+    const uint32_t freed = ids & 0xFu;
+    slots[freed * kBlock] = make_uint2(__float_as_uint(a), idx);
+    const uint32_t sh = 4u * p;
+    const uint32_t low = (1u << sh) - 1u;
+    const uint32_t t = (ids & ~(0xFu << sh)) | (freed << sh);
+    ids = (t & ~low) | ((ids >> 4) & low);
+    if (p == 0) {
+      head_a = a;
+      head_i = idx;
+    } else {
+      const uint2 h = slots[(ids & 0xFu) * kBlock];
+      head_a = __uint_as_float(h.x);
+      head_i = h.y;
+    }
+  }
+};
+
 template <int K, int MODE, bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp,
@@ -37,8 +100,9 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   float* trace_z = aux2;
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
-  __shared__ float4 lds[kBatch * RF4];
-  __shared__ uint32_t lidx[kBatch];
+  __shared__ float4 lds[kFwdBatch * RF4];
+  __shared__ uint32_t lidx[kFwdBatch];
+  __shared__ uint2 s_slots[kMaxCache * kBlock];
   const CamDev& cam = *camp;
   const int tile = tile_order ? (int)tile_order[blockIdx.x] : (int)blockIdx.x;   // launch order
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -60,12 +124,12 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   int consumed = (int)(end - start);
   bool done = !inside;
   // cache payload: (alpha, primitive index); the colour is gathered from the record at emission
-  Cache<2> cache;
-  cache.init(rp.cache_len);
+  CacheSlots cache;
+  cache.init(rp.cache_len, s_slots, tid);
 
-  for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+  for (uint32_t b0 = start; b0 < end; b0 += kFwdBatch) {
     if (__syncthreads_count(!done) == 0) break;
-    const int nb = (int)min((uint32_t)kBatch, end - b0);
+    const int nb = (int)min((uint32_t)kFwdBatch, end - b0);
     for (int q = tid; q < nb * RF4; q += kBlock) {
       const int ri = q / RF4, c = q - ri * RF4;
       const uint32_t j = prims[b0 + ri];
@@ -85,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
         if (at >= rp.alpha_min) {
           if constexpr (COUNT) ++n_contrib;
           // pop the head (emit it), then insert the newcomer
-          const float a = cache.pay[0][0];
+          const float a = cache.head_a;
           if (a > 0.0f) {
             const float test = T * (1.0f - a);
             if (test < rp.T_min) {
@@ -93,7 +157,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
               if constexpr (COUNT) consumed = (int)(b0 - start) + i + 1;
               break;
             }
-            const float* c = records + (size_t)__float_as_uint(cache.pay[1][0]) * RF + R_RGB;
+            const float* c = records + (size_t)cache.head_i * RF + R_RGB;
             const float w = a * T;
             C0 = fmaf(w, c[0], C0);
             C1 = fmaf(w, c[1], C1);
@@ -101,7 +165,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
             T = test;
             if constexpr (TRACE) {
               if (n_emit < trace_cap) {
-                trace_idx[trace_base + n_emit] = (int32_t)__float_as_uint(cache.pay[1][0]);
+                trace_idx[trace_base + n_emit] = (int32_t)cache.head_i;
                 trace_z[trace_base + n_emit] = cache.key[0];
               }
             }
@@ -114,8 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
             }
             ++n_emit;
           }
-          const float x2[2] = {at, __uint_as_float(lidx[i])};
-          cache.pop_insert(Z, x2);
+          cache.pop_insert(Z, at, lidx[i]);
         }
       }
     }
@@ -124,13 +187,14 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   if (!done) {
 #pragma unroll
     for (int s = 0; s < kMaxCache; ++s) {
-      const float a = cache.pay[0][s];
+      const uint2 e = cache.at_position(s);
+      const float a = __uint_as_float(e.x);
       if (!done && a > 0.0f) {
         const float test = T * (1.0f - a);
         if (test < rp.T_min) {
           done = true;
         } else {
-          const float* c = records + (size_t)__float_as_uint(cache.pay[1][s]) * RF + R_RGB;
+          const float* c = records + (size_t)e.y * RF + R_RGB;
           const float w = a * T;
           C0 = fmaf(w, c[0], C0);
           C1 = fmaf(w, c[1], C1);
@@ -138,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
           T = test;
           if constexpr (TRACE) {
             if (n_emit < trace_cap) {
-              trace_idx[trace_base + n_emit] = (int32_t)__float_as_uint(cache.pay[1][s]);
+              trace_idx[trace_base + n_emit] = (int32_t)e.y;
               trace_z[trace_base + n_emit] = cache.key[s];
             }
           }
