@@ -991,23 +991,47 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
   }
 }
 
-// Pass 3, one thread per listed primitive with tiles: the rest of its render record.
-__global__ void __launch_bounds__(128) k_record(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
-                                                float* __restrict__ records, const uint32_t* __restrict__ tile_counts,
-                                                const uint32_t* __restrict__ work,
-                                                const uint32_t* __restrict__ work_count, int64_t stride,
-                                                double* __restrict__ keygeo) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Pass 3, one thread per listed primitive with tiles: the rest of its render record.  A thread's
+// record fields are written one float at a time, so the wave's records are built in LDS and then
+// copied out as float4 rows (each record's 16-byte groups side by side), except the group that
+// holds the box (written by k_polygon).
+constexpr int kRecWave = 64;
+static_assert(R_BOX % 4 == 0, "the box is one float4 group of the record");
+
+__global__ void __launch_bounds__(kRecWave) k_record(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
+                                                     float* __restrict__ records,
+                                                     const uint32_t* __restrict__ tile_counts,
+                                                     const uint32_t* __restrict__ work,
+                                                     const uint32_t* __restrict__ work_count, int64_t stride,
+                                                     double* __restrict__ keygeo) {
+  extern __shared__ float4 s_rec[];   // kRecWave records of rec_floats(K) floats
+  const int lane = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kRecWave + lane;
   const int v = blockIdx.y;
-  if (i >= (int64_t)work_count[v]) return;
-  const int64_t j = (int64_t)work[(int64_t)v * stride + i];
-  const int64_t o = (int64_t)v * stride + j;
-  if (tile_counts[o] == 0) return;
-  const CamDev& cam = views->cam[v];
-  GeoBase g;
-  bool invalid;
-  if (!load_geo_core<double>(sc, j, cam, opt, g, &invalid, nullptr, nullptr)) return;
-  write_record(g, sc, j, cam, opt, records + o * rec_floats(sc.K), opt.key_mode != 0 ? keygeo + o * KG_N : nullptr);
+  const int64_t wc = (int64_t)work_count[v];
+  if ((int64_t)blockIdx.x * kRecWave >= wc) return;
+  const int RF = rec_floats(sc.K), RF4 = RF / 4;
+  int64_t o = -1;
+  if (i < wc) {
+    const int64_t j = (int64_t)work[(int64_t)v * stride + i];
+    if (tile_counts[(int64_t)v * stride + j] != 0) {
+      const CamDev& cam = views->cam[v];
+      GeoBase g;
+      bool invalid;
+      if (load_geo_core<double>(sc, j, cam, opt, g, &invalid, nullptr, nullptr)) {
+        o = (int64_t)v * stride + j;
+        write_record(g, sc, j, cam, opt, reinterpret_cast<float*>(s_rec + lane * RF4),
+                     opt.key_mode != 0 ? keygeo + o * KG_N : nullptr);
+      }
+    }
+  }
+  const uint64_t has = __ballot(o >= 0);
+  __syncthreads();
+  for (int q = lane; q < kRecWave * RF4; q += kRecWave) {   // the same trip count in every lane
+    const int r = q / RF4, c = q - r * RF4;
+    const int64_t orow = __shfl(o, r, 64);
+    if (((has >> r) & 1ull) && c != R_BOX / 4) reinterpret_cast<float4*>(records + orow * RF)[c] = s_rec[q];
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1267,7 +1291,10 @@ hipError_t launch_preprocess(const SceneDev& sc, const Views* views, int nv, con
   dim3 grid_poly((unsigned)std::min<int64_t>((batches + kPolyWaves - 1) / kPolyWaves, 2048), (unsigned)nv);
   hipLaunchKernelGGL(k_polygon, grid_poly, dim3(64 * kPolyWaves), 0, s, sc, views, opt, records, depth_keys,
                      tile_counts, work, work_count, span_meta, span_rows, pool_used, row_cap, stride, keygeo);
-  hipLaunchKernelGGL(k_record, grid, dim3(128), 0, s, sc, views, opt, records, tile_counts, work, work_count, stride,
+  dim3 grid_rec((unsigned)((sc.n + kRecWave - 1) / kRecWave), (unsigned)nv);
+  const size_t rec_lds = (size_t)kRecWave * rec_floats(sc.K) * sizeof(float);
+  hipLaunchKernelGGL(k_record, grid_rec, dim3(kRecWave), rec_lds, s, sc, views, opt, records, tile_counts, work,
+                     work_count, stride,
                      keygeo);
   return hipGetLastError();
 }
