@@ -305,7 +305,9 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
     for (int k = 0; k < K; ++k) {
       double sc = g.s[k] * f;
       double p[3];
-      lift(g, cam, sc * cos(g.th[k]), sc * sin(g.th[k]), p);
+      double sn_, cs_;
+      sincos(g.th[k], &sn_, &cs_);
+      lift(g, cam, sc * cs_, sc * sn_, p);
       push_vertex(sp, cam, nearp, p);
     }
   } else {
@@ -315,7 +317,8 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
     // they equal s_k, s_{k+1} or the bisector values below; each half is covered by the quad of its
     // circular sector (half-angle delta/4 < pi/4).
     // cos / sin of theta_k: the previous sector's end angle is this sector's start angle
-    double cth = cos(g.th[0]), sth = sin(g.th[0]);
+    double cth, sth;
+    sincos(g.th[0], &sth, &cth);
     for (int k = 0; k < K; ++k) {
       const double thk = g.th[k];
       const double thn = (k + 1 < K) ? g.th[k + 1] : g.th[0] + kTwoPi;
@@ -328,17 +331,20 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
       const double rho1 = g.c * fmax(sn, r_mid);
       const double sec = 1.0 / cos(0.25 * dl);
       const double a1 = thk + 0.5 * dl, m0 = thk + 0.25 * dl, m1 = thk + 0.75 * dl;
-      const double ca1 = cos(a1), sa1 = sin(a1);
+      double ca1, sa1;
+      sincos(a1, &sa1, &ca1);
       // the six vertices in the tangent plane, then pushed through one call site (one inlined copy
       // of the clip and row walk instead of six keeps the kernel at 3 waves per SIMD)
       double vx[6], vy[6];
       vx[0] = rho0 * cth; vy[0] = rho0 * sth;
-      vx[1] = rho0 * sec * cos(m0); vy[1] = rho0 * sec * sin(m0);
+      double cm0, sm0, cm1, sm1;
+      sincos(m0, &sm0, &cm0);
+      sincos(m1, &sm1, &cm1);
+      vx[1] = rho0 * sec * cm0; vy[1] = rho0 * sec * sm0;
       vx[2] = rho0 * ca1; vy[2] = rho0 * sa1;
       vx[3] = rho1 * ca1; vy[3] = rho1 * sa1;
-      vx[4] = rho1 * sec * cos(m1); vy[4] = rho1 * sec * sin(m1);
-      cth = cos(thn);
-      sth = sin(thn);
+      vx[4] = rho1 * sec * cm1; vy[4] = rho1 * sec * sm1;
+      sincos(thn, &sth, &cth);
       vx[5] = rho1 * cth; vy[5] = rho1 * sth;
 #pragma unroll 1
       for (int q = 0; q < 6; ++q) {
@@ -793,8 +799,10 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
         if (opt.cull_mode == 1) {
           const double s1 = (double)L.s[it][q] * f1;
           const double th = (double)L.th[it][q];
-          x = s1 * cos(th);
-          y = s1 * sin(th);
+          double sn_, cs_;
+          sincos(th, &sn_, &cs_);
+          x = s1 * cs_;
+          y = s1 * sn_;
         } else {
           // half-sector quads of sector k (the sequential walk's expressions)
           const int k = q / 6, m = q - 6 * k;
@@ -809,8 +817,10 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
           if (m == 1 || m == 4) rad = rad * (1.0 / cos(0.25 * dl));
           const double ang = m == 0 ? thk : m == 1 ? thk + 0.25 * dl : m == 4 ? thk + 0.75 * dl : m == 5 ? thn
                                                                                                   : thk + 0.5 * dl;
-          x = rad * cos(ang);
-          y = rad * sin(ang);
+          double sn_, cs_;
+          sincos(ang, &sn_, &cs_);
+          x = rad * cs_;
+          y = rad * sn_;
         }
         double w[3], p[3];
         for (int i = 0; i < 3; ++i) w[i] = (g.mu[i] + x * g.tu[i]) + y * g.tv[i];
