@@ -250,3 +250,60 @@ def test_large_primitives_full_lists_match_oracle(cull_mode):
     worst, nk, _, _ = compare_image(rgb[0].cpu().numpy(), orc, cam.height, cam.width)
     log(f"cull mode {cull_mode}: max err {worst:.2e}, knife {nk}")
     assert worst <= IMG_TOL and nk <= 8
+
+
+def _frustum_edge_scene(seed, n, K, W, H, fx, fy, cx, cy):
+    """DRKs centred near the four side planes of a camera at the origin looking along +z, from
+    2 max_k s_k inside to 4 max_k s_k outside, in random orientations (a third nearly edge-on)."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(0.6, 5.0, n)
+    side = rng.integers(0, 4, n)
+    s = np.exp(rng.uniform(math.log(0.05), math.log(0.6), (K, n)))
+    off = rng.uniform(-2.0, 4.0, n) * s.max(0)
+    px = np.where(side == 0, 0.0, np.where(side == 1, float(W), rng.uniform(0, W, n)))
+    py = np.where(side == 2, 0.0, np.where(side == 3, float(H), rng.uniform(0, H, n)))
+    X = (px - cx) / fx * z + np.where(side == 0, -off, np.where(side == 1, off, 0.0))
+    Y = (py - cy) / fy * z + np.where(side == 2, -off, np.where(side == 3, off, 0.0))
+    mu = np.stack([X, Y, z]).astype(np.float32)
+    q = rng.normal(size=(4, n))
+    # a third nearly edge-on: a quarter turn about x (the normal leaves the view axis), then a turn
+    # about the view axis, so that the tangent plane holds the view axis; slightly perturbed
+    edge = rng.random(n) < 1 / 3
+    a = rng.uniform(0, 2 * np.pi, n)
+    h = math.sqrt(0.5)
+    qe = np.stack([np.cos(a / 2) * h, np.cos(a / 2) * h, np.sin(a / 2) * h, np.sin(a / 2) * h])
+    qe = qe + rng.normal(0, 0.01, (4, n))
+    q = np.where(edge[None, :], qe, q).astype(np.float32)
+    col = rng.normal(0, 0.1, (48, n)).astype(np.float32)
+    col[:3] = rng.uniform(0, 1, (3, n))
+    return Scene(mu, q, s.astype(np.float32), draw_angles(rng, K, n), rng.uniform(0, 1, n).astype(np.float32),
+                 rng.uniform(0, 0.9, n).astype(np.float32), rng.uniform(0.05, 0.95, n).astype(np.float32), col, 3)
+
+
+@pytest.mark.parametrize("cull_mode,lowpass", [(0, True), (0, False), (1, True), (1, False)])
+def test_frustum_edge_primitives_keep_their_tiles(cull_mode, lowpass):
+    """The frustum test before the polygon only drops DRKs that reach no pixel centre: for DRKs around
+    the view's side planes, the GPU's per-DRK tile sets equal the oracle's, which has no frustum test
+    (its polygon decides), for the conservative polygon and the paper's endpoint polygon."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    W, H, K, n = 160, 120, 8, 600
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 70.0)
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.zeros(3, np.float32),
+                 np.array([0.1, 0.1, 0.1], np.float32))
+    scene = _frustum_edge_scene(21 + cull_mode, n, K, W, H, fx, fy, cx, cy)
+    ras = _rasterizer(scene, [cam], 1 << 18)
+    ras.forward(DRKScene.from_host(scene), [cam], gpu_opts(cull_mode=cull_mode, lowpass=lowpass))
+    gc = _u32(ras.export("tile_counts"))
+    gt, gp = _u32(ras.export("pair_tiles")), _u32(ras.export("pair_prims"))
+    g_sets = [set() for _ in range(n)]
+    for t, j in zip(gt.tolist(), gp.tolist()):
+        g_sets[j].add(t)
+    oo = oracle_opts(cull_mode=cull_mode, lowpass=lowpass)
+    o_sets = [set(O.primitive_tiles(scene, cam, oo, j)) for j in range(n)]
+    oc = np.array([len(x) for x in o_sets])
+    log(f"cull mode {cull_mode}, low-pass {lowpass}: {int((oc > 0).sum())} of {n} DRKs with tiles, "
+        f"{int((oc == 0).sum())} without")
+    assert (oc > 0).sum() >= n // 5 and (oc == 0).sum() >= n // 5
+    assert np.array_equal(gc, oc)
+    assert all(g == o for g, o in zip(g_sets, o_sets))
