@@ -28,8 +28,8 @@ void set_error(const char* fmt, ...) {
 // kernels in other translation units
 hipError_t set_views(Views*, const Views&, hipStream_t);
 hipError_t launch_preprocess(const SceneDev&, const Views*, int, const OptsDev&, float*, uint32_t*, uint32_t*,
-                             uint32_t*, uint32_t*, uint2*, uint32_t*, uint32_t*, int64_t, uint32_t*, int64_t,
-                             double*, hipStream_t);
+                             uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint2*, uint32_t*, uint32_t*, int64_t,
+                             uint32_t*, int64_t, double*, hipStream_t);
 hipError_t launch_duplicate(const SceneDev&, const Views*, const OptsDev&, int, const uint32_t*, const uint32_t*,
                             const uint32_t*, const uint2*, const uint32_t*, uint32_t*, uint32_t*, const uint64_t*,
                             int64_t, const uint64_t*, uint32_t*, uint32_t*, const double*, uint32_t*, hipStream_t);
@@ -91,8 +91,8 @@ struct drk_ws {
   uint32_t *hist = nullptr, *tot = nullptr;
   float* grad_rec = nullptr;
   Views* views_dev = nullptr;     // cameras read by every kernel (set by a one-thread kernel)
-  uint32_t* work = nullptr;       // per view: primitives that may touch the view
-  uint32_t* counters = nullptr;   // work count per view, then kSpanPools span-row pool fills per view
+  uint32_t* work = nullptr;       // per view: primitives that may touch the view (small list), then per view the big list
+  uint32_t* counters = nullptr;   // small and big list counts per view, then kSpanPools span-row pool fills per view
   uint2* span_meta = nullptr;     // per view and primitive: row-span offset, first row | rows << 16
   uint32_t* span_rows = nullptr;  // per view: tile columns i0 | i1 << 16 of each spanned row
   int64_t row_cap = 0;
@@ -169,8 +169,8 @@ size_t layout(drk_ws* ws, bool assign, char* base) {
   SLOT(tot, uint32_t, 256)
   SLOT(grad_rec, float, ws->lean ? 0 : V * N * grad_fields(ws->K))
   SLOT(views_dev, Views, 1)
-  SLOT(work, uint32_t, V * N)
-  SLOT(counters, uint32_t, (1 + kSpanPools) * V)
+  SLOT(work, uint32_t, 2 * V * N)
+  SLOT(counters, uint32_t, (2 + kSpanPools) * V)
   SLOT(span_meta, uint2, V * N)
   SLOT(span_rows, uint32_t, V * (size_t)ws->row_cap)
   SLOT(out_rgb, float, ws->lean ? 0 : 3 * px)
@@ -287,11 +287,12 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   od.counters = opts->counters;
   drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
   if (st) return st;
-  if ((st = check_hip(fill_u32(ws->counters, 0u, (1 + kSpanPools) * ws->max_views, s), "clear counters"))) return st;
+  if ((st = check_hip(fill_u32(ws->counters, 0u, (2 + kSpanPools) * ws->max_views, s), "clear counters"))) return st;
   const int V = ws->max_views;
   st = check_hip(launch_preprocess(sc, ws->views_dev, ws->views.nv, od, ws->records, ws->depth_keys, ws->tile_counts,
-                                   ws->work, ws->counters, ws->span_meta, ws->span_rows, ws->counters + V,
-                                   ws->row_cap, ws->status, ws->max_n, ws->keygeo, s),
+                                   ws->work, ws->counters, ws->work + (size_t)V * ws->max_n, ws->counters + V,
+                                   ws->span_meta, ws->span_rows, ws->counters + 2 * V, ws->row_cap, ws->status,
+                                   ws->max_n, ws->keygeo, s),
                  "preprocess launch");
   if (st) return st;
   ws->scene = sc;

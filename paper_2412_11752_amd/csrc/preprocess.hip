@@ -11,6 +11,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace drk {
 
@@ -154,14 +155,60 @@ __device__ inline bool load_geo(const SceneDev& sc, int64_t j, const CamDev& cam
 }
 
 // ---------------------------------------------------------------------------------------------
-// Tile-row spans of the projected support.  Edges of the near-clipped projected polygon are
-// streamed in order; each updates the x-extent of the tile rows whose pixel-centre slab it crosses.
-// lo/hi are indexed by the row relative to the primitive's centre row (wrapping), so that the
-// lanes of a wave, whose primitives mostly cover a row or two around their centres, touch the same
-// private-memory slots instead of slots spread over every tile row of the view.
-struct Spans {
+// Tile-row spans of the projected support, sequential walk.  Edges of the near-clipped projected
+// polygon are streamed in order; each updates the x-extent of the tile rows whose pixel-centre slab
+// it crosses.  The row extents live in one of two stores:
+//  * RowsAll: every tile row of the view in private memory, indexed relative to the primitive's
+//    centre row (wrapping), so that a wave's lanes touch the same slots;
+//  * RowsWin: kWinRows rows from `base` on in registers; touching a row outside them sets
+//    `overflow` (the caller then takes the primitive to the wave-parallel kernel).
+constexpr int kWinRows = 4;
+
+struct RowsAll {
   double lo[kMaxTileRows], hi[kMaxTileRows];
   int base;                         // tile row stored in slot 0
+  bool overflow;                    // never set
+  __device__ int slot(int r) const {
+    const int x = r - base;
+    return x < 0 ? x + kMaxTileRows : x;
+  }
+  __device__ bool holds(int) const { return true; }
+  __device__ void clear(int r) { lo[slot(r)] = INFINITY; hi[slot(r)] = -INFINITY; }
+  __device__ void fold(int r, double l, double h) {
+    const int q = slot(r);
+    lo[q] = fmin(lo[q], l);
+    hi[q] = fmax(hi[q], h);
+  }
+  __device__ void get(int r, double& l, double& h) const { l = lo[slot(r)]; h = hi[slot(r)]; }
+};
+
+struct RowsWin {
+  double lo[kWinRows], hi[kWinRows];
+  int base;
+  bool overflow;
+  __device__ bool holds(int r) const { return r >= base && r < base + kWinRows; }
+  __device__ void clear(int r) {
+#pragma unroll
+    for (int i = 0; i < kWinRows; ++i)
+      if (r - base == i) { lo[i] = INFINITY; hi[i] = -INFINITY; }
+  }
+  __device__ void fold(int r, double l, double h) {
+#pragma unroll
+    for (int i = 0; i < kWinRows; ++i)
+      if (r - base == i) { lo[i] = fmin(lo[i], l); hi[i] = fmax(hi[i], h); }
+  }
+  __device__ void get(int r, double& l, double& h) const {
+    l = INFINITY;
+    h = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < kWinRows; ++i)
+      if (r - base == i) { l = lo[i]; h = hi[i]; }
+  }
+};
+
+template <class Rows>
+struct SpansT {
+  Rows rows;
   double bx0, bx1, by0, by1;        // box of every projected segment and the low-pass square
   int r0, r1;                       // initialised rows [r0, r1]
   int W, H, tx, ty;
@@ -172,28 +219,35 @@ struct Spans {
   bool pending_exit, have_first_entry;
   double exit_xy[2], first_entry_xy[2];
 };
+using Spans = SpansT<RowsAll>;
 
-__device__ inline void spans_init(Spans& sp, const CamDev& cam) {
+template <class S>
+__device__ inline void spans_init(S& sp, const CamDev& cam) {
   sp.r0 = 1; sp.r1 = 0;
   sp.bx0 = sp.by0 = INFINITY;
   sp.bx1 = sp.by1 = -INFINITY;
   sp.W = cam.W; sp.H = cam.H; sp.tx = cam.tiles_x; sp.ty = cam.tiles_y;
   sp.have_prev = false; sp.have_first = false; sp.pending_exit = false; sp.have_first_entry = false;
+  sp.rows.overflow = false;
 }
 
-__device__ inline int slot(const Spans& sp, int r) {
-  int x = r - sp.base;
-  return x < 0 ? x + kMaxTileRows : x;
-}
-
-__device__ inline void spans_touch(Spans& sp, int r) {
-  if (sp.r0 > sp.r1) { sp.r0 = sp.r1 = r; sp.lo[slot(sp, r)] = INFINITY; sp.hi[slot(sp, r)] = -INFINITY; return; }
-  while (r < sp.r0) { --sp.r0; sp.lo[slot(sp, sp.r0)] = INFINITY; sp.hi[slot(sp, sp.r0)] = -INFINITY; }
-  while (r > sp.r1) { ++sp.r1; sp.lo[slot(sp, sp.r1)] = INFINITY; sp.hi[slot(sp, sp.r1)] = -INFINITY; }
+// Row r takes the x-extent [l, h]: the rows [r0, r1] grow to hold it (new rows start empty).
+template <class S>
+__device__ inline void spans_row(S& sp, int r, double l, double h) {
+  if (!sp.rows.holds(r)) { sp.rows.overflow = true; return; }
+  if (sp.r0 > sp.r1) {
+    sp.r0 = sp.r1 = r;
+    sp.rows.clear(r);
+  } else {
+    while (r < sp.r0) { --sp.r0; sp.rows.clear(sp.r0); }
+    while (r > sp.r1) { ++sp.r1; sp.rows.clear(sp.r1); }
+  }
+  sp.rows.fold(r, l, h);
 }
 
 // Screen segment (x0,y0)-(x1,y1) against every tile row slab it may cross.
-__device__ inline void spans_segment(Spans& sp, double x0, double y0, double x1, double y1) {
+template <class S>
+__device__ inline void spans_segment(S& sp, double x0, double y0, double x1, double y1) {
   double ymin = fmin(y0, y1), ymax = fmax(y0, y1);
   sp.bx0 = fmin(sp.bx0, fmin(x0, x1));
   sp.bx1 = fmax(sp.bx1, fmax(x0, x1));
@@ -218,10 +272,7 @@ __device__ inline void spans_segment(Spans& sp, double x0, double y0, double x1,
       xa = x0 + tlo * (x1 - x0);
       xb = x0 + thi * (x1 - x0);
     }
-    spans_touch(sp, r);
-    const int q = slot(sp, r);
-    sp.lo[q] = fmin(sp.lo[q], fmin(xa, xb));
-    sp.hi[q] = fmax(sp.hi[q], fmax(xa, xb));
+    spans_row(sp, r, fmin(xa, xb), fmax(xa, xb));
   }
 }
 
@@ -232,7 +283,8 @@ __device__ inline void project(const CamDev& cam, const double p[3], double& x, 
 
 // Camera-space polygon vertex stream, clipped to z >= near in Sutherland-Hodgman order.  axy / bxy
 // are the pixel coordinates of a / b (used only when the point is in front of the near plane).
-__device__ inline void clip_edge(Spans& sp, const CamDev& cam, double nearp, const double a[3], const double axy[2],
+template <class S>
+__device__ inline void clip_edge(S& sp, const CamDev& cam, double nearp, const double a[3], const double axy[2],
                                  const double b[3], const double bxy[2]) {
   bool ain = a[2] >= nearp, bin = b[2] >= nearp;
   double Ixy[2] = {0.0, 0.0};
@@ -260,7 +312,8 @@ __device__ inline void clip_edge(Spans& sp, const CamDev& cam, double nearp, con
   }
 }
 
-__device__ inline void push_vertex(Spans& sp, const CamDev& cam, double nearp, const double p[3]) {
+template <class S>
+__device__ inline void push_vertex(S& sp, const CamDev& cam, double nearp, const double p[3]) {
   double pxy[2] = {0.0, 0.0};
   if (p[2] >= nearp) project(cam, p, pxy[0], pxy[1]);
   if (!sp.have_first) {
@@ -274,7 +327,8 @@ __device__ inline void push_vertex(Spans& sp, const CamDev& cam, double nearp, c
   sp.prev_xy[0] = pxy[0]; sp.prev_xy[1] = pxy[1];
 }
 
-__device__ inline void close_polygon(Spans& sp, const CamDev& cam, double nearp) {
+template <class S>
+__device__ inline void close_polygon(S& sp, const CamDev& cam, double nearp) {
   if (sp.have_first) clip_edge(sp, cam, nearp, sp.prev, sp.prev_xy, sp.first, sp.first_xy);
   if (sp.pending_exit && sp.have_first_entry)
     spans_segment(sp, sp.exit_xy[0], sp.exit_xy[1], sp.first_entry_xy[0], sp.first_entry_xy[1]);
@@ -287,13 +341,28 @@ __device__ inline void lift(const GeoBase& g, const CamDev& cam, double x, doubl
   to_cam(cam, w, out);
 }
 
+// Bases of primitive j as float64: from a loaded Geo, or read from the scene (the same values).
+struct GeoBases {
+  const Geo& g;
+  __device__ double s(int k) const { return g.s[k]; }
+  __device__ double th(int k) const { return g.th[k]; }
+};
+struct SceneBases {
+  const SceneDev& sc;
+  int64_t j;
+  __device__ double s(int k) const { return (double)sc.scale[k * sc.n + j]; }
+  __device__ double th(int k) const { return (double)sc.theta[k * sc.n + j]; }
+};
+
 // Builds the tile-row spans of primitive g (cull_mode 0: conservative support polygon;
-// 1: the paper's endpoint polygon; 2 handled by the caller).
-__device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt, Spans& sp) {
+// 1: the paper's endpoint polygon; 2 handled by the caller).  The row store's base is set by the
+// caller for RowsWin; RowsAll's is set here.
+template <class Rows, class B>
+__device__ void build_spans(const GeoBase& g, const B& bs, const CamDev& cam, const OptsDev& opt, SpansT<Rows>& sp) {
   spans_init(sp, cam);
-  {
+  if constexpr (std::is_same<Rows, RowsAll>::value) {
     const double pyc = fmin(fmax((double)cam.fy * g.muc[1] / g.muc[2] + (double)cam.cy, -1e7), 1e7);
-    sp.base = min(max((int)floor(pyc / 16.0), 0), sp.ty - 1);
+    sp.rows.base = min(max((int)floor(pyc / 16.0), 0), sp.ty - 1);
   }
   const double nearp = (double)opt.near_plane;
   const int K = g.K;
@@ -303,10 +372,10 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
     double ml = -log(gm);
     double f = sqrt(ml > 0.0 ? ml : 0.0);
     for (int k = 0; k < K; ++k) {
-      double sc = g.s[k] * f;
+      double sc = bs.s(k) * f;
       double p[3];
       double sn_, cs_;
-      sincos(g.th[k], &sn_, &cs_);
+      sincos(bs.th(k), &sn_, &cs_);
       lift(g, cam, sc * cs_, sc * sn_, p);
       push_vertex(sp, cam, nearp, p);
     }
@@ -318,11 +387,11 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
     // circular sector (half-angle delta/4 < pi/4).
     // cos / sin of theta_k: the previous sector's end angle is this sector's start angle
     double cth, sth;
-    sincos(g.th[0], &sth, &cth);
+    sincos(bs.th(0), &sth, &cth);
     for (int k = 0; k < K; ++k) {
-      const double thk = g.th[k];
-      const double thn = (k + 1 < K) ? g.th[k + 1] : g.th[0] + kTwoPi;
-      const double sk = g.s[k], sn = g.s[(k + 1) % K];
+      const double thk = bs.th(k);
+      const double thn = (k + 1 < K) ? bs.th(k + 1) : bs.th(0) + kTwoPi;
+      const double sk = bs.s(k), sn = bs.s((k + 1) % K);
       const double dl = thn - thk;
       const double sbar_mid = 1.0 / sqrt(0.5 * (1.0 / (sk * sk) + 1.0 / (sn * sn)));
       const double chord_mid = 2.0 * cos(0.5 * dl) / (1.0 / sk + 1.0 / sn);
@@ -368,20 +437,18 @@ __device__ void build_spans(const Geo& g, const CamDev& cam, const OptsDev& opt,
     for (int row = 0; row < sp.ty; ++row) {
       double ya = 16.0 * row + 0.5;
       double yb = fmin(16.0 * row + 15.5, sp.H - 0.5);
-      if (dcy + r >= ya && dcy - r <= yb) {
-        spans_touch(sp, row);
-        const int q = slot(sp, row);
-        sp.lo[q] = fmin(sp.lo[q], dcx - r);
-        sp.hi[q] = fmax(sp.hi[q], dcx + r);
-      }
+      if (dcy + r >= ya && dcy - r <= yb) spans_row(sp, row, dcx - r, dcx + r);
     }
   }
 }
 
 // Tile columns [i0, i1] of row r (false when none).
-__device__ inline bool row_tiles(const Spans& sp, int r, int& i0, int& i1) {
-  double lo = fmax(sp.lo[slot(sp, r)], 0.5);
-  double hi = fmin(sp.hi[slot(sp, r)], sp.W - 0.5);
+template <class S>
+__device__ inline bool row_tiles(const S& sp, int r, int& i0, int& i1) {
+  double l, h;
+  sp.rows.get(r, l, h);
+  double lo = fmax(l, 0.5);
+  double hi = fmin(h, sp.W - 0.5);
   if (lo > hi) return false;
   double a = ceil((lo - 15.5) / 16.0);
   double b = floor((hi - 0.5) / 16.0);
@@ -586,32 +653,199 @@ __device__ void write_record(const GeoBase& g, const SceneDev& sc, int64_t j, co
 // that may touch the view are appended to the view's work list.  Per-view arrays are
 // [view][stride] with stride = the workspace capacity in primitives.
 constexpr int kPreBlock = 256;
+constexpr int kFixedRows = 8;           // span rows reserved per position of the small work list
+// The thread-per-primitive kernel pays off only when its primitives fill the GPU (2 waves per SIMD
+// of it at this count); below that the wave-parallel kernel, which spreads each primitive over a
+// wave's lanes, finishes sooner.
+constexpr int64_t kSmallMin = 2 * 1024 * 64;
+
+// Row buffer of a view (row_cap rows): kFixedRows rows per work-list position, then kSpanPools
+// pools filled by atomic counters for primitives with more rows (or for all of them when the buffer
+// cannot hold the fixed rows beside pools of at least 64 rows).  Position p of the small list owns
+// rows [p kFixedRows, (p + 1) kFixedRows); position p of the big list owns those of position
+// stride - 1 - p while that is past the small list's end (the two lists hold at most stride
+// primitives unless the small kernel moved some; then the pools).  A primitive whose rows fit
+// nowhere gets kNoSpans and is re-derived by the duplication.
+struct RowLayout {
+  bool fixed;
+  int64_t pool_base, pool_rows;
+};
+__device__ inline RowLayout row_layout(int64_t row_cap, int64_t stride) {
+  RowLayout L;
+  const int64_t f = (int64_t)kFixedRows * stride;
+  L.fixed = row_cap >= f + (int64_t)kSpanPools * 64;
+  L.pool_base = L.fixed ? f : 0;
+  L.pool_rows = (row_cap - L.pool_base) / kSpanPools;
+  return L;
+}
+constexpr uint32_t kNoItem = 0xFFFFFFFFu;   // a work-list entry taken over by the other list
+
+// Tile rows the support can touch, estimated from the ball of the support disc around the centre:
+// for a point (Y + dY, Z + dZ) with dY^2 + dZ^2 <= R^2 and Z - R > 0, |(Y + dY)/(Z + dZ) - Y/Z| <=
+// R sqrt(Y^2 + Z^2) / (Z (Z - R)).  True (and the window's first row) when the rows fit kWinRows and
+// no part of the ball is behind the near plane.  The window only chooses the kernel (a primitive
+// that touches a row outside it is handed to the wave-parallel one), so float32 is enough here.
+__device__ inline bool span_window(const GeoBase& g, const CamDev& cam, const OptsDev& opt, int& base) {
+  base = 0;
+  if (opt.cull_mode == 2) return true;
+  float rad = 1.4142135f * (float)g.c;
+  if (opt.cull_mode == 1) {
+    const double y = exp(-9.0) / g.o;
+    const double gm = psi_inv(y < 1.0 ? y : 1.0, g.tau);
+    const float ml = -logf((float)gm);
+    rad = sqrtf(ml > 0.0f ? ml : 0.0f);
+  }
+  const float R = rad * (float)g.smax * 1.001f + 1e-6f;
+  const float Y = (float)g.muc[1], Z = (float)g.muc[2];
+  if (!(Z - R > opt.near_plane)) return false;
+  const float dy = cam.fy * R * sqrtf(Z * Z + Y * Y) / (Z * (Z - R)) * 1.001f;
+  const float yc = (cam.fy * Y) / Z + cam.cy;
+  float ymin = yc - dy, ymax = yc + dy;
+  if (opt.lowpass_sl > 0.0f) {
+    const float ratio = (float)g.o / opt.alpha_min;
+    const float r = opt.lowpass_sl * sqrtf(2.0f * logf(ratio > 1.0f ? ratio : 1.0f)) * 1.001f;
+    ymin = fminf(ymin, yc - r);
+    ymax = fmaxf(ymax, yc + r);
+  }
+  const float last = (float)(cam.tiles_y - 1);
+  const float ra = fmaxf(ceilf((ymin - 15.5f) / 16.0f), 0.0f), rb = fminf(floorf((ymax - 0.5f) / 16.0f), last);
+  if (!(rb - ra + 1.0f <= (float)kWinRows)) return false;
+  base = (int)fminf(ra, last);
+  return true;
+}
 
 __global__ void __launch_bounds__(kPreBlock) k_preprocess(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
                                                     uint32_t* __restrict__ depth_keys,
                                                     uint32_t* __restrict__ tile_counts,
-                                                    uint32_t* __restrict__ work, uint32_t* __restrict__ work_count,
+                                                    uint32_t* __restrict__ work_small,
+                                                    uint32_t* __restrict__ count_small,
+                                                    uint32_t* __restrict__ work_big, uint32_t* __restrict__ count_big,
                                                     uint32_t* __restrict__ status, int64_t stride) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
   const CamDev& cam = views->cam[v];
-  bool maybe = false;
+  bool maybe = false, small = false;
   if (j < sc.n) {
     GeoBase g;
     bool invalid = false;
     const bool alive = load_geo_core<double>(sc, j, cam, opt, g, &invalid, nullptr, nullptr);
     if (invalid && opt.validate) atomicOr(status + v, (uint32_t)ST_INVALID);
     maybe = alive && (opt.cull_mode == 2 || !outside_view(g, cam, opt));
+    int base;
+    small = maybe && span_window(g, cam, opt, base);
     depth_keys[(int64_t)v * stride + j] = maybe ? __float_as_uint((float)g.muc[2]) : kCulledKey;
     tile_counts[(int64_t)v * stride + j] = 0;
   }
-  const uint32_t slot = block_alloc<kPreBlock / 64>(work_count + v, maybe ? 1u : 0u);
-  if (maybe) work[(int64_t)v * stride + slot] = (uint32_t)j;
+  const uint32_t slot_s = block_alloc<kPreBlock / 64>(count_small + v, small ? 1u : 0u);
+  __syncthreads();
+  const uint32_t slot_b = block_alloc<kPreBlock / 64>(count_big + v, maybe && !small ? 1u : 0u);
+  if (small) work_small[(int64_t)v * stride + slot_s] = (uint32_t)j;
+  if (maybe && !small) work_big[(int64_t)v * stride + slot_b] = (uint32_t)j;
+}
+
+// Pass 2a, one thread per primitive of the small list: the sequential polygon walk with the rows
+// of its window in registers (the same float64 expressions as the wave-parallel kernel, so the
+// same spans); a primitive that touches a row outside its window moves to the big list.
+__global__ void __launch_bounds__(128) k_polygon_small(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
+                                                       float* __restrict__ records, uint32_t* __restrict__ depth_keys,
+                                                       uint32_t* __restrict__ tile_counts,
+                                                       uint32_t* __restrict__ work_small,
+                                                       const uint32_t* __restrict__ count_small,
+                                                       uint32_t* __restrict__ work_big, uint32_t* __restrict__ count_big,
+                                                       uint2* __restrict__ span_meta, uint32_t* __restrict__ span_rows,
+                                                       uint32_t* __restrict__ pool_used, int64_t row_cap,
+                                                       int64_t stride, double* __restrict__ keygeo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  const CamDev& cam = views->cam[v];
+  const int K = sc.K;
+  const int64_t ns = (int64_t)count_small[v];
+  if (ns < kSmallMin) return;   // too few to fill the GPU: the wave-parallel kernel takes them
+  const bool active = i < ns;
+  const int64_t j = active ? (int64_t)work_small[(int64_t)v * stride + i] : 0;
+  const int64_t o = (int64_t)v * stride + j;
+  bool over = false, ok = false;
+  uint32_t count = 0;
+  SpansT<RowsWin> sp;
+  if (active) {
+    GeoBase g;
+    bool invalid;
+    ok = load_geo_core<double>(sc, j, cam, opt, g, &invalid, nullptr, nullptr);
+    if (ok) {
+      if (opt.cull_mode == 2) {
+        count = (uint32_t)(cam.tiles_x * cam.tiles_y);
+      } else {
+        int base;
+        over = !span_window(g, cam, opt, base);
+        if (!over) {
+          sp.rows.base = base;
+          build_spans(g, SceneBases{sc, j}, cam, opt, sp);
+          over = sp.rows.overflow;
+        }
+        if (!over) {
+          for (int r = sp.r0; r <= sp.r1; ++r) {
+            int i0, i1;
+            if (row_tiles(sp, r, i0, i1)) count += (uint32_t)(i1 - i0 + 1);
+          }
+        }
+      }
+    }
+  }
+  const uint32_t slot_b = block_alloc<2>(count_big + v, over ? 1u : 0u);
+  if (!active) return;
+  if (over) {
+    work_big[(int64_t)v * stride + slot_b] = (uint32_t)j;
+    work_small[(int64_t)v * stride + i] = kNoItem;
+    return;
+  }
+  tile_counts[o] = count;
+  if (count == 0) {
+    depth_keys[o] = kCulledKey;
+    return;
+  }
+  double box[4] = {-1e30, 1e30, -1e30, 1e30};   // only the conservative polygon bounds the support
+  if (opt.cull_mode != 2) {
+    const uint32_t nrows = (uint32_t)(sp.r1 - sp.r0 + 1);   // at most kWinRows <= kFixedRows
+    const RowLayout rl = row_layout(row_cap, stride);
+    int64_t at;
+    bool fits;
+    if (rl.fixed) {
+      at = i * kFixedRows;
+      fits = true;
+    } else {
+      const uint32_t pool = (uint32_t)(i % kSpanPools);
+      const uint32_t off = atomicAdd(pool_used + (int64_t)v * kSpanPools + pool, nrows);
+      at = rl.pool_base + (int64_t)pool * rl.pool_rows + off;
+      fits = (int64_t)off + nrows <= rl.pool_rows;
+    }
+    fits = fits && at + nrows < (int64_t)kNoSpans;
+    uint2 meta = make_uint2(kNoSpans, 0u);
+    if (fits) {
+      uint32_t* out = span_rows + (int64_t)v * row_cap + at;
+      for (int r = sp.r0; r <= sp.r1; ++r) {
+        int i0, i1;
+        out[r - sp.r0] = row_tiles(sp, r, i0, i1) ? ((uint32_t)i0 | ((uint32_t)i1 << 16)) : 0xFFFFFFFFu;
+      }
+      meta = make_uint2((uint32_t)at, (uint32_t)sp.r0 | (nrows << 16));
+    }
+    span_meta[o] = meta;
+    if (opt.cull_mode == 0) { box[0] = sp.bx0; box[1] = sp.bx1; box[2] = sp.by0; box[3] = sp.by1; }
+  }
+  float* rec = records + o * rec_floats(K);
+  rec[R_BOX + 0] = (float)(box[0] - 0.01);
+  rec[R_BOX + 1] = (float)(box[1] + 0.01);
+  rec[R_BOX + 2] = (float)(box[2] - 0.01);
+  rec[R_BOX + 3] = (float)(box[3] + 0.01);
+  if (opt.key_mode != 0) {
+    double* kg = keygeo + o * KG_N;
+    for (int q = 0; q < 4; ++q) kg[KG_BOX + q] = box[q];
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Pass 2: the support polygon of each listed primitive, wave-parallel.  A wave takes a batch of
-// work items, loads their geometry one item per lane, then builds the tile-row spans of one item at
+// Pass 2b: the support polygon of each primitive of the big list (supports that may span more than
+// kWinRows tile rows or reach the near plane, and those that left the small list), wave-parallel.
+// A wave takes a batch of work items, loads their geometry one item per lane, then builds the tile-row spans of one item at
 // a time with all its lanes: the lanes take the polygon's vertices, then its edges (each clipped to
 // the near plane and cut into tile-row slabs with the float64 expressions of the sequential walk
 // above), and the rows' x-extents meet in LDS through exact 64-bit min / max on an order-preserving
@@ -622,7 +856,6 @@ __global__ void __launch_bounds__(kPreBlock) k_preprocess(SceneDev sc, const Vie
 constexpr int kPolyWaves = 4;           // waves per workgroup
 constexpr int kPolyBatch = 8;           // work items per wave batch
 constexpr int kMaxPolyV = 6 * kMaxK;    // support polygon vertices (cull mode 0: six per sector)
-constexpr int kFixedRows = 8;           // span rows reserved per work-list position
 static_assert(kMaxPolyV <= 128, "edge exit masks cover two 64-edge chunks");
 
 // Order-preserving encoding: unsigned order of the codes is the order of the (non-NaN) doubles.
@@ -720,6 +953,8 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
                                                             OptsDev opt, float* __restrict__ records,
                                                             uint32_t* __restrict__ depth_keys,
                                                             uint32_t* __restrict__ tile_counts,
+                                                            const uint32_t* __restrict__ work_small,
+                                                            const uint32_t* __restrict__ count_small,
                                                             const uint32_t* __restrict__ work,
                                                             const uint32_t* __restrict__ work_count,
                                                             uint2* __restrict__ span_meta,
@@ -731,17 +966,18 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
   PolyLds& L = s_lds[wv];
   const int v = blockIdx.y;
   const CamDev& cam = views->cam[v];
-  const int64_t wc = (int64_t)work_count[v];
+  // the big list, then the small list too when k_polygon_small left it (fewer than kSmallMin items):
+  // the primitives that may span many rows come first, so that they do not finish last
+  const int64_t n_small_all = (int64_t)count_small[v];
+  const int64_t ns = n_small_all < kSmallMin ? n_small_all : 0;
+  const int64_t nbig = (int64_t)work_count[v];
+  const int64_t wc = nbig + ns;
   const int64_t n = sc.n;
   const int K = sc.K;
   const int ty = cam.tiles_y, tx = cam.tiles_x, W = cam.W, H = cam.H;
   const double nearp = (double)opt.near_plane;
   const int V = opt.cull_mode == 1 ? K : 6 * K;
-  // row buffer: kFixedRows rows per work-list position when it holds them (no allocation for items
-  // of at most that many rows), then kSpanPools pools filled by atomic counters
-  const int64_t fixed_rows =
-      row_cap >= (int64_t)kFixedRows * stride + (int64_t)kSpanPools * 64 ? (int64_t)kFixedRows * stride : 0;
-  const int64_t pool_rows = (row_cap - fixed_rows) / kSpanPools;
+  const RowLayout rl = row_layout(row_cap, stride);
   for (int r = lane; r < kMaxTileRows; r += 64) { L.lo[r] = kEncPosInf; L.hi[r] = kEncNegInf; }
   if (lane < 4) L.box[lane] = kEncPosInf;
   if (lane < 2) L.rows[lane] = kMaxTileRows;
@@ -752,7 +988,8 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
     wave_sync();   // the previous batch's geometry has been read
     bool mine_ok = false;
     if (lane < nb) {
-      const uint32_t mine_j = work[(int64_t)v * stride + first + lane];
+      const int64_t pos = first + lane;
+      const uint32_t mine_j = pos < nbig ? work[(int64_t)v * stride + pos] : work_small[(int64_t)v * stride + (pos - nbig)];
       bool invalid;
       GeoBase mine;
       mine_ok = load_geo_core<float>(sc, mine_j, cam, opt, mine, &invalid, L.s[lane], L.th[lane]);
@@ -774,7 +1011,10 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
     const uint32_t pool = (uint32_t)(b % kSpanPools);
     wave_sync();
     for (int it = 0; it < nb; ++it) {
-      if (!((ok_mask >> it) & 1ull)) continue;
+      if (!((ok_mask >> it) & 1ull)) {
+        if (lane == 0) depth_keys[(int64_t)v * stride + L.item[it]] = kCulledKey;
+        continue;
+      }
       const int64_t j = (int64_t)L.item[it];
       const GeoBase& g = L.geo[it];
       const int64_t o = (int64_t)v * stride + j;
@@ -957,17 +1197,20 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
         continue;
       }
       const uint32_t nrows = (uint32_t)(r1 - r0 + 1);
+      // a fixed slot by list position when it holds the rows, else a pool
+      const int64_t pos = first + it;
+      const int64_t slot = pos < nbig ? stride - 1 - pos : pos - nbig;   // small-list positions as they are
       int64_t at;
       bool fits;
-      if (fixed_rows != 0 && nrows <= (uint32_t)kFixedRows) {
-        at = (first + it) * kFixedRows;
+      if (nrows <= (uint32_t)kFixedRows && rl.fixed && (pos >= nbig || slot >= n_small_all)) {
+        at = slot * kFixedRows;
         fits = true;
       } else {
         uint32_t off = 0;
         if (lane == 0) off = atomicAdd(pool_used + (int64_t)v * kSpanPools + pool, nrows);
         off = (uint32_t)__builtin_amdgcn_readlane((int)off, 0);
-        at = fixed_rows + (int64_t)pool * pool_rows + off;
-        fits = (int64_t)off + nrows <= pool_rows;
+        at = rl.pool_base + (int64_t)pool * rl.pool_rows + off;
+        fits = (int64_t)off + nrows <= rl.pool_rows;
       }
       fits = fits && at + nrows < (int64_t)kNoSpans;   // offsets are stored in 32 bits
       if (fits) {
@@ -1011,36 +1254,43 @@ static_assert(R_BOX % 4 == 0, "the box is one float4 group of the record");
 __global__ void __launch_bounds__(kRecWave) k_record(SceneDev sc, const Views* __restrict__ views, OptsDev opt,
                                                      float* __restrict__ records,
                                                      const uint32_t* __restrict__ tile_counts,
-                                                     const uint32_t* __restrict__ work,
-                                                     const uint32_t* __restrict__ work_count, int64_t stride,
+                                                     const uint32_t* __restrict__ work_small,
+                                                     const uint32_t* __restrict__ count_small,
+                                                     const uint32_t* __restrict__ work_big,
+                                                     const uint32_t* __restrict__ count_big, int64_t stride,
                                                      double* __restrict__ keygeo) {
   extern __shared__ float4 s_rec[];   // kRecWave records of rec_floats(K) floats
   const int lane = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * kRecWave + lane;
   const int v = blockIdx.y;
-  const int64_t wc = (int64_t)work_count[v];
-  if ((int64_t)blockIdx.x * kRecWave >= wc) return;
+  const int64_t ns = (int64_t)count_small[v], total = ns + (int64_t)count_big[v];
   const int RF = rec_floats(sc.K), RF4 = RF / 4;
-  int64_t o = -1;
-  if (i < wc) {
-    const int64_t j = (int64_t)work[(int64_t)v * stride + i];
-    if (tile_counts[(int64_t)v * stride + j] != 0) {
-      const CamDev& cam = views->cam[v];
-      GeoBase g;
-      bool invalid;
-      if (load_geo_core<double>(sc, j, cam, opt, g, &invalid, nullptr, nullptr)) {
-        o = (int64_t)v * stride + j;
-        write_record(g, sc, j, cam, opt, reinterpret_cast<float*>(s_rec + lane * RF4),
-                     opt.key_mode != 0 ? keygeo + o * KG_N : nullptr);
+  const CamDev& cam = views->cam[v];
+  // positions [0, ns) of the small list, then those of the big list
+  const int64_t first = (int64_t)blockIdx.x * kRecWave;
+  if (first >= total) return;
+  {
+    const int64_t i = first + lane;
+    int64_t o = -1;
+    if (i < total) {
+      const uint32_t jj = i < ns ? work_small[(int64_t)v * stride + i] : work_big[(int64_t)v * stride + (i - ns)];
+      if (jj != kNoItem && tile_counts[(int64_t)v * stride + jj] != 0) {
+        const int64_t j = (int64_t)jj;
+        GeoBase g;
+        bool invalid;
+        if (load_geo_core<double>(sc, j, cam, opt, g, &invalid, nullptr, nullptr)) {
+          o = (int64_t)v * stride + j;
+          write_record(g, sc, j, cam, opt, reinterpret_cast<float*>(s_rec + lane * RF4),
+                       opt.key_mode != 0 ? keygeo + o * KG_N : nullptr);
+        }
       }
     }
-  }
-  const uint64_t has = __ballot(o >= 0);
-  __syncthreads();
-  for (int q = lane; q < kRecWave * RF4; q += kRecWave) {   // the same trip count in every lane
-    const int r = q / RF4, c = q - r * RF4;
-    const int64_t orow = __shfl(o, r, 64);
-    if (((has >> r) & 1ull) && c != R_BOX / 4) reinterpret_cast<float4*>(records + orow * RF)[c] = s_rec[q];
+    const uint64_t has = __ballot(o >= 0);
+    __syncthreads();
+    for (int q = lane; q < kRecWave * RF4; q += kRecWave) {   // the same trip count in every lane
+      const int r = q / RF4, c = q - r * RF4;
+      const int64_t orow = __shfl(o, r, 64);
+      if (((has >> r) & 1ull) && c != R_BOX / 4) reinterpret_cast<float4*>(records + orow * RF)[c] = s_rec[q];
+    }
   }
 }
 
@@ -1169,7 +1419,7 @@ __global__ void __launch_bounds__(128) k_duplicate_rebuild(SceneDev sc, const Vi
     bool invalid;
     if (!load_geo(sc, j, cam, opt, g, &invalid)) continue;
     Spans sp;
-    build_spans(g, cam, opt, sp);
+    build_spans(g, GeoBases{g}, cam, opt, sp);
     uint32_t w = 0;
     for (int r = sp.r0; r <= sp.r1 && w < cnt; ++r) {
       int i0, i1;
@@ -1288,24 +1538,32 @@ hipError_t set_views(Views* d_views, const Views& views, hipStream_t s) {
   return hipGetLastError();
 }
 
+// work_small / work_big: per view [view][stride] lists; counts: per view; pool_used: kSpanPools
+// counters per view.  The counts and pool counters must be zero.
 hipError_t launch_preprocess(const SceneDev& sc, const Views* views, int nv, const OptsDev& opt, float* records,
-                             uint32_t* depth_keys, uint32_t* tile_counts, uint32_t* work, uint32_t* work_count,
-                             uint2* span_meta, uint32_t* span_rows, uint32_t* pool_used, int64_t row_cap,
-                             uint32_t* status, int64_t stride, double* keygeo, hipStream_t s) {
+                             uint32_t* depth_keys, uint32_t* tile_counts, uint32_t* work_small, uint32_t* count_small,
+                             uint32_t* work_big, uint32_t* count_big, uint2* span_meta, uint32_t* span_rows,
+                             uint32_t* pool_used, int64_t row_cap, uint32_t* status, int64_t stride, double* keygeo,
+                             hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
   dim3 grid((unsigned)((sc.n + 127) / 128), (unsigned)nv);
   dim3 grid_pre((unsigned)((sc.n + kPreBlock - 1) / kPreBlock), (unsigned)nv);
-  hipLaunchKernelGGL(k_preprocess, grid_pre, dim3(kPreBlock), 0, s, sc, views, opt, depth_keys, tile_counts, work,
-                     work_count, status, stride);
+  hipLaunchKernelGGL(k_preprocess, grid_pre, dim3(kPreBlock), 0, s, sc, views, opt, depth_keys, tile_counts,
+                     work_small, count_small, work_big, count_big, status, stride);
+  hipLaunchKernelGGL(k_polygon_small, grid, dim3(128), 0, s, sc, views, opt, records, depth_keys, tile_counts,
+                     work_small, count_small, work_big, count_big, span_meta, span_rows, pool_used, row_cap, stride,
+                     keygeo);
   const int64_t batches = (sc.n + kPolyBatch - 1) / kPolyBatch;
   dim3 grid_poly((unsigned)std::min<int64_t>((batches + kPolyWaves - 1) / kPolyWaves, 2048), (unsigned)nv);
   hipLaunchKernelGGL(k_polygon, grid_poly, dim3(64 * kPolyWaves), 0, s, sc, views, opt, records, depth_keys,
-                     tile_counts, work, work_count, span_meta, span_rows, pool_used, row_cap, stride, keygeo);
-  dim3 grid_rec((unsigned)((sc.n + kRecWave - 1) / kRecWave), (unsigned)nv);
+                     tile_counts, work_small, count_small, work_big, count_big, span_meta, span_rows, pool_used,
+                     row_cap, stride, keygeo);
+  // the two lists hold at most 2 n entries (an entry that moved to the big list stays in the small
+  // one as kNoItem)
+  dim3 grid_rec((unsigned)((2 * sc.n + kRecWave - 1) / kRecWave), (unsigned)nv);
   const size_t rec_lds = (size_t)kRecWave * rec_floats(sc.K) * sizeof(float);
-  hipLaunchKernelGGL(k_record, grid_rec, dim3(kRecWave), rec_lds, s, sc, views, opt, records, tile_counts, work,
-                     work_count, stride,
-                     keygeo);
+  hipLaunchKernelGGL(k_record, grid_rec, dim3(kRecWave), rec_lds, s, sc, views, opt, records, tile_counts, work_small,
+                     count_small, work_big, count_big, stride, keygeo);
   return hipGetLastError();
 }
 
