@@ -9,6 +9,8 @@
 // are done.  The exact-order kernel below keeps rounds of kBatch records.
 #include "raster_common.hpp"
 
+#include <type_traits>
+
 namespace drk {
 
 // Output variants: MODE 0 colour only; MODE 1 (trace) also records, per pixel, the primitive index
@@ -50,6 +52,7 @@ struct CacheSlots {
   __device__ __forceinline__ uint2 at_position(int j) const {
     return slots[((ids >> (4 * j)) & 0xFu) * kBlock];
   }
+  __device__ __forceinline__ float key_at(int j) const { return key[j]; }
   // Drops position 0 and inserts (z; a, idx) after every key <= z (the caller has read the head).
   __device__ __forceinline__ void pop_insert(float z, float a, uint32_t idx) {
     static_assert(kMaxCache == 8, "eight 4-bit slot ids in one word");
@@ -82,6 +85,37 @@ struct CacheSlots {
   }
 };
 
+// The register cache (Cache<2>: keys, alphas and indices in VGPRs) behind the same interface, for
+// the depth / normal variant: it carries more per-pixel state, so its occupancy is bound by VGPRs
+// rather than LDS, and it keeps rounds of kBatch records.
+struct CacheRegs {
+  Cache<2> c;
+  float head_a;
+  uint32_t head_i;
+  __device__ __forceinline__ void init(int cache_len, uint2*, int) {
+    c.init(cache_len);
+    head_a = 0.0f;
+    head_i = 0u;
+  }
+  __device__ __forceinline__ uint2 at_position(int j) const {
+    return make_uint2(__float_as_uint(c.pay[0][j]), __float_as_uint(c.pay[1][j]));
+  }
+  __device__ __forceinline__ float key_at(int j) const { return c.key[j]; }
+  __device__ __forceinline__ void pop_insert(float z, float a, uint32_t idx) {
+    const float x2[2] = {a, __uint_as_float(idx)};
+    c.pop_insert(z, x2);
+    head_a = c.pay[0][0];
+    head_i = __float_as_uint(c.pay[1][0]);
+  }
+};
+
+template <int MODE>
+struct FwdCfg {
+  static constexpr bool kSlots = MODE != 2;
+  static constexpr int kRound = kSlots ? kFwdBatch : kBatch;
+  using CacheT = typename std::conditional<kSlots, CacheSlots, CacheRegs>::type;
+};
+
 template <int K, int MODE, bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp,
@@ -100,9 +134,10 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   float* trace_z = aux2;
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
-  __shared__ float4 lds[kFwdBatch * RF4];
-  __shared__ uint32_t lidx[kFwdBatch];
-  __shared__ uint2 s_slots[kMaxCache * kBlock];
+  constexpr int kRound = FwdCfg<MODE>::kRound;
+  __shared__ float4 lds[kRound * RF4];
+  __shared__ uint32_t lidx[kRound];
+  __shared__ uint2 s_slots[FwdCfg<MODE>::kSlots ? kMaxCache * kBlock : 1];
   const CamDev& cam = *camp;
   const int tile = tile_order ? (int)tile_order[blockIdx.x] : (int)blockIdx.x;   // launch order
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -124,12 +159,12 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   int consumed = (int)(end - start);
   bool done = !inside;
   // cache payload: (alpha, primitive index); the colour is gathered from the record at emission
-  CacheSlots cache;
+  typename FwdCfg<MODE>::CacheT cache;
   cache.init(rp.cache_len, s_slots, tid);
 
-  for (uint32_t b0 = start; b0 < end; b0 += kFwdBatch) {
+  for (uint32_t b0 = start; b0 < end; b0 += kRound) {
     if (__syncthreads_count(!done) == 0) break;
-    const int nb = (int)min((uint32_t)kFwdBatch, end - b0);
+    const int nb = (int)min((uint32_t)kRound, end - b0);
     for (int q = tid; q < nb * RF4; q += kBlock) {
       const int ri = q / RF4, c = q - ri * RF4;
       const uint32_t j = prims[b0 + ri];
@@ -166,12 +201,12 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
             if constexpr (TRACE) {
               if (n_emit < trace_cap) {
                 trace_idx[trace_base + n_emit] = (int32_t)cache.head_i;
-                trace_z[trace_base + n_emit] = cache.key[0];
+                trace_z[trace_base + n_emit] = cache.key_at(0);
               }
             }
             if constexpr (GEOM) {
               const float* nr = c - R_RGB + R_NRM;
-              Dz = fmaf(w, cache.key[0], Dz);
+              Dz = fmaf(w, cache.key_at(0), Dz);
               N0 = fmaf(w, nr[0], N0);
               N1 = fmaf(w, nr[1], N1);
               N2 = fmaf(w, nr[2], N2);
@@ -203,12 +238,12 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
           if constexpr (TRACE) {
             if (n_emit < trace_cap) {
               trace_idx[trace_base + n_emit] = (int32_t)e.y;
-              trace_z[trace_base + n_emit] = cache.key[s];
+              trace_z[trace_base + n_emit] = cache.key_at(s);
             }
           }
           if constexpr (GEOM) {
             const float* nr = c - R_RGB + R_NRM;
-            Dz = fmaf(w, cache.key[s], Dz);
+            Dz = fmaf(w, cache.key_at(s), Dz);
             N0 = fmaf(w, nr[0], N0);
             N1 = fmaf(w, nr[1], N1);
             N2 = fmaf(w, nr[2], N2);
