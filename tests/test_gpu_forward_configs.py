@@ -307,3 +307,42 @@ def test_frustum_edge_primitives_keep_their_tiles(cull_mode, lowpass):
     assert (oc > 0).sum() >= n // 5 and (oc == 0).sum() >= n // 5
     assert np.array_equal(gc, oc)
     assert all(g == o for g, o in zip(g_sets, o_sets))
+
+
+@pytest.mark.parametrize("cull_mode", [0, 1])
+def test_many_small_primitives_thread_walk(cull_mode):
+    """400k small DRKs (K = 8) seen whole at 1280x720: more than 131072 of them fit a 4-row window,
+    so their polygons take the thread-per-DRK walk with the rows in registers.  Sampled DRKs' tile
+    sets and depth keys are bit-exact against the oracle, and the lists are sorted.  With the paper's
+    endpoint polygon the sample includes DRK 223537, whose polygon reaches one tile although the
+    ball of radius sqrt(2) c max_k s_k around its centre lies outside the view (the frustum test
+    must use that polygon's own radius)."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene = scene_uniform_box(77, 400_000, K=8, s_lo=0.002, s_hi=0.02)
+    cam = camera_lookat((0.0, 0.3, -2.6), (0, 0, 0), (0, 1, 0), 1280, 720, 60.0)
+    ras = _rasterizer(scene, [cam], 1 << 23)
+    ras.forward(DRKScene.from_host(scene), [cam], gpu_opts(cull_mode=cull_mode))
+    gt, gp = _u32(ras.export("pair_tiles")), _u32(ras.export("pair_prims"))
+    keys = _u32(ras.export("depth_keys"))
+    gc = _u32(ras.export("tile_counts"))
+    assert np.array_equal(np.lexsort((gp, keys[gp], gt)), np.arange(gt.size))
+    okey = O.centre_depth_f32(scene.mu, cam).view(np.uint32)
+    rng = np.random.default_rng(5 + cull_mode)
+    listed = np.unique(gp)
+    sample = list(rng.choice(listed, 300, replace=False)) + list(rng.choice(scene.n, 300, replace=False))
+    if cull_mode == 1:
+        sample.append(223537)
+    oo = oracle_opts(cull_mode=cull_mode)
+    log(f"cull mode {cull_mode}: {listed.size} DRKs listed, {gt.size} pairs")
+    assert listed.size > 131072
+    order = np.argsort(gp, kind="stable")
+    starts = np.searchsorted(gp[order], np.arange(scene.n + 1))
+    for j in sample:
+        j = int(j)
+        ot = O.primitive_tiles(scene, cam, oo, j)
+        g = np.sort(gt[order[starts[j]:starts[j + 1]]])
+        assert np.array_equal(g, np.array(ot, np.int64)), (j, g[:8], ot[:8])
+        assert gc[j] == len(ot)
+        if ot:
+            assert keys[j] == okey[j]
