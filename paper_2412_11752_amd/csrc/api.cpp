@@ -251,6 +251,16 @@ drk_status ws_set_cameras(drk_ws* ws, const drk_camera* cams, int32_t n_views, h
   return DRK_OK;
 }
 
+// Integer from the environment variable `name`, or `def` when it is unset, malformed or out of
+// [lo, hi].
+static int64_t env_int(const char* name, int64_t def, int64_t lo, int64_t hi) {
+  const char* e = std::getenv(name);
+  if (!e) return def;
+  char* end = nullptr;
+  const long long v = std::strtoll(e, &end, 10);
+  return (end != e && *end == '\0' && v >= lo && v <= hi) ? (int64_t)v : def;
+}
+
 drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts* opts, hipStream_t s) {
   if (!ws || !scene || !opts) { set_error("null argument"); return DRK_EINVAL; }
   if (ws->views.nv < 1) { set_error("no cameras set"); return DRK_EINVAL; }
@@ -285,6 +295,10 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
   od.cull_mode = opts->cull_mode; od.validate = opts->validate; od.key_mode = opts->key_mode;
   od.launch_order = opts->launch_order;
   od.counters = opts->counters;
+  // the thread-per-primitive polygon walk runs from 131072 small primitives on (enough threads for
+  // 2 waves per SIMD of it); DRK_SMALL_MIN and DRK_WINDOW_ADMIT change that choice for tests
+  od.small_min = (int32_t)env_int("DRK_SMALL_MIN", 131072, 0, 1 << 30);
+  od.win_admit = (int32_t)env_int("DRK_WINDOW_ADMIT", 4, 1, 64);
   drk_status st = check_hip(fill_u32(ws->status, 0u, ws->max_views, s), "clear status");
   if (st) return st;
   if ((st = check_hip(fill_u32(ws->counters, 0u, (2 + kSpanPools) * ws->max_views, s), "clear counters"))) return st;

@@ -77,6 +77,9 @@ struct Views {
 struct OptsDev {
   float alpha_min, alpha_max, T_min, near_plane, lowpass_sl;
   int32_t cache_len, cull_mode, validate, key_mode, launch_order, counters;
+  // polygon kernel choice (results do not depend on it): the small-list length from which the
+  // thread-per-primitive walk runs, and the tile rows a primitive may span to join that list
+  int32_t small_min, win_admit;
 };
 
 // Per (view, primitive) float64 data of the per-tile pre-sort keys (key_mode 1, 2), written by the

@@ -654,10 +654,6 @@ __device__ void write_record(const GeoBase& g, const SceneDev& sc, int64_t j, co
 // [view][stride] with stride = the workspace capacity in primitives.
 constexpr int kPreBlock = 256;
 constexpr int kFixedRows = 8;           // span rows reserved per position of the small work list
-// The thread-per-primitive kernel pays off only when its primitives fill the GPU (2 waves per SIMD
-// of it at this count); below that the wave-parallel kernel, which spreads each primitive over a
-// wave's lanes, finishes sooner.
-constexpr int64_t kSmallMin = 2 * 1024 * 64;
 
 // Row buffer of a view (row_cap rows): kFixedRows rows per work-list position, then kSpanPools
 // pools filled by atomic counters for primitives with more rows (or for all of them when the buffer
@@ -682,7 +678,8 @@ constexpr uint32_t kNoItem = 0xFFFFFFFFu;   // a work-list entry taken over by t
 
 // Tile rows the support can touch, estimated from the ball of the support disc around the centre:
 // for a point (Y + dY, Z + dZ) with dY^2 + dZ^2 <= R^2 and Z - R > 0, |(Y + dY)/(Z + dZ) - Y/Z| <=
-// R sqrt(Y^2 + Z^2) / (Z (Z - R)).  True (and the window's first row) when the rows fit kWinRows and
+// R sqrt(Y^2 + Z^2) / (Z (Z - R)).  True (and the window's first row) when at most opt.win_admit rows
+// (kWinRows unless a test asks for more, to make primitives leave their window) are touched and
 // no part of the ball is behind the near plane.  The window only chooses the kernel (a primitive
 // that touches a row outside it is handed to the wave-parallel one), so float32 is enough here.
 __device__ inline bool span_window(const GeoBase& g, const CamDev& cam, const OptsDev& opt, int& base) {
@@ -709,7 +706,7 @@ __device__ inline bool span_window(const GeoBase& g, const CamDev& cam, const Op
   }
   const float last = (float)(cam.tiles_y - 1);
   const float ra = fmaxf(ceilf((ymin - 15.5f) / 16.0f), 0.0f), rb = fminf(floorf((ymax - 0.5f) / 16.0f), last);
-  if (!(rb - ra + 1.0f <= (float)kWinRows)) return false;
+  if (!(rb - ra + 1.0f <= (float)opt.win_admit)) return false;
   base = (int)fminf(ra, last);
   return true;
 }
@@ -760,7 +757,7 @@ __global__ void __launch_bounds__(128) k_polygon_small(SceneDev sc, const Views*
   const CamDev& cam = views->cam[v];
   const int K = sc.K;
   const int64_t ns = (int64_t)count_small[v];
-  if (ns < kSmallMin) return;   // too few to fill the GPU: the wave-parallel kernel takes them
+  if (ns < (int64_t)opt.small_min) return;   // too few to fill the GPU: the wave kernel takes them
   const bool active = i < ns;
   const int64_t j = active ? (int64_t)work_small[(int64_t)v * stride + i] : 0;
   const int64_t o = (int64_t)v * stride + j;
@@ -966,10 +963,10 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
   PolyLds& L = s_lds[wv];
   const int v = blockIdx.y;
   const CamDev& cam = views->cam[v];
-  // the big list, then the small list too when k_polygon_small left it (fewer than kSmallMin items):
+  // the big list, then the small list too when k_polygon_small left it (fewer than small_min items):
   // the primitives that may span many rows come first, so that they do not finish last
   const int64_t n_small_all = (int64_t)count_small[v];
-  const int64_t ns = n_small_all < kSmallMin ? n_small_all : 0;
+  const int64_t ns = n_small_all < (int64_t)opt.small_min ? n_small_all : 0;
   const int64_t nbig = (int64_t)work_count[v];
   const int64_t wc = nbig + ns;
   const int64_t n = sc.n;

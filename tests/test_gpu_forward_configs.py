@@ -346,3 +346,36 @@ def test_many_small_primitives_thread_walk(cull_mode):
         assert gc[j] == len(ot)
         if ot:
             assert keys[j] == okey[j]
+
+
+@pytest.mark.parametrize("cull_mode,key_mode", [(0, 0), (1, 2)])
+def test_polygon_paths_give_identical_lists(monkeypatch, cull_mode, key_mode):
+    """The polygon kernels differ only in speed: the wave-per-DRK kernel (the default below 131072
+    small DRKs), the thread-per-DRK walk (DRK_SMALL_MIN=0), the walk with DRKs admitted to the small
+    list that then leave their 4-row window for the big list (DRK_WINDOW_ADMIT=16), and the walk with
+    a 64-row span buffer (pools, and re-derivation in the duplication) give bitwise the same keys,
+    counts, sorted pairs, ranges and image."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene = scene_uniform_box(23, 30000, K=8, s_lo=0.01, s_hi=0.25)
+    cams = [camera_lookat((0.4, -0.3, -1.7), (0, 0, 0), (0, 1, 0), 640, 480, 75.0, bg=(0.1, 0.2, 0.3))]
+    ds = DRKScene.from_host(scene)
+    runs = {}
+    for label, env in (("wave", {}), ("thread", {"DRK_SMALL_MIN": "0"}),
+                       ("thread+leave", {"DRK_SMALL_MIN": "0", "DRK_WINDOW_ADMIT": "16"}),
+                       ("thread+pools", {"DRK_SMALL_MIN": "0", "DRK_WINDOW_ADMIT": "16", "DRK_SPAN_ROWS": "64"})):
+        for k in ("DRK_SMALL_MIN", "DRK_WINDOW_ADMIT", "DRK_SPAN_ROWS"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        ras = _rasterizer(scene, cams, 1 << 22)
+        rgb, _ = ras.forward(ds, cams, gpu_opts(cull_mode=cull_mode, key_mode=key_mode))
+        runs[label] = [rgb.cpu().numpy()] + [ras.export(w).cpu().numpy()
+                                             for w in ("depth_keys", "tile_counts", "pair_tiles", "pair_prims", "ranges")]
+        ras.close()
+    counts = runs["wave"][2].view(np.uint32)
+    log(f"cull mode {cull_mode}, key mode {key_mode}: {int((counts > 0).sum())} DRKs with tiles, "
+        f"{int(counts.astype(np.int64).sum())} pairs")
+    for label in ("thread", "thread+leave", "thread+pools"):
+        for a, b in zip(runs["wave"], runs[label]):
+            assert np.array_equal(a, b), label
