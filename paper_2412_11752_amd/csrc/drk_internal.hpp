@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "../../include/drk.h"
@@ -100,6 +101,27 @@ struct SceneDev {
   const float* opacity;
   const float* color;
 };
+
+// Structs passed by value as kernel arguments or copied to device memory are laid out alike by
+// the host and the device compilations (every translation unit checks these in each pass).
+static_assert(sizeof(CamDev) == 120 && offsetof(CamDev, fx) == 16 && offsetof(CamDev, R) == 32 &&
+                  offsetof(CamDev, t) == 68 && offsetof(CamDev, bg) == 80 && offsetof(CamDev, campos) == 96,
+              "CamDev layout");
+static_assert(sizeof(Views) == 968 && offsetof(Views, nv) == 960, "Views layout");
+static_assert(sizeof(OptsDev) == 52 && offsetof(OptsDev, cache_len) == 20 && offsetof(OptsDev, counters) == 40 &&
+                  offsetof(OptsDev, win_admit) == 48,
+              "OptsDev layout");
+static_assert(sizeof(SceneDev) == 88 && offsetof(SceneDev, K) == 8 && offsetof(SceneDev, ncol) == 20 &&
+                  offsetof(SceneDev, mu) == 24 && offsetof(SceneDev, color) == 80,
+              "SceneDev layout");
+static_assert(sizeof(drk_scene) == 88 && offsetof(drk_scene, mu) == 24 && offsetof(drk_scene, color) == 80,
+              "drk_scene layout");
+static_assert(sizeof(drk_scene_grad) == 64 && offsetof(drk_scene_grad, color) == 56, "drk_scene_grad layout");
+static_assert(sizeof(drk_scene_out) == 64 && offsetof(drk_scene_out, color) == 56, "drk_scene_out layout");
+static_assert(sizeof(drk_camera) == 84 && offsetof(drk_camera, R) == 24 && offsetof(drk_camera, bg) == 72,
+              "drk_camera layout");
+static_assert(sizeof(drk_opts) == 44 && offsetof(drk_opts, cache_len) == 20 && offsetof(drk_opts, counters) == 40,
+              "drk_opts layout");
 
 // Status word bits (device), read back by drk_ws_status.
 enum StatusBits : uint32_t { ST_OVERFLOW = 1u, ST_INVALID = 2u };

@@ -79,3 +79,34 @@ def test_serve_config_errors_without_gpu_work():
     assert L.drk_serve_create(C.byref(cfg), C.byref(srv)) == _lib.DRK_EINVAL       # cache too long
     assert L.drk_serve_submit(None, 0, None, None, None) == _lib.DRK_EINVAL
     assert L.drk_serve_poll(None, 1, 0, None) == _lib.DRK_EINVAL
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """The binding's ctypes structs have the sizes and field offsets that a C compiler gives the
+    header's structs (compiled here with the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = {"drk_scene": _lib.Scene, "drk_scene_grad": _lib.SceneGrad, "drk_scene_out": _lib.SceneOut,
+             "drk_camera": _lib.Camera, "drk_opts": _lib.Opts, "drk_serve_cfg": _lib.ServeCfg,
+             "drk_req_stats": _lib.ReqStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-o", str(exe), str(src)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = ln.split()
+        got[(cname, field)] = int(val)
+    for cname, py in pairs.items():
+        assert C.sizeof(py) == got[(cname, "size")], cname
+        for fname, _ in py._fields_:
+            assert getattr(py, fname).offset == got[(cname, fname)], (cname, fname)
