@@ -717,9 +717,11 @@ __global__ void __launch_bounds__(kPreBlock) k_preprocess(SceneDev sc, const Vie
                                                     uint32_t* __restrict__ work_small,
                                                     uint32_t* __restrict__ count_small,
                                                     uint32_t* __restrict__ work_big, uint32_t* __restrict__ count_big,
-                                                    uint32_t* __restrict__ status, int64_t stride) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y;
+                                                    uint32_t* __restrict__ status, int64_t stride, int nv) {
+  // consecutive workgroups take the same primitives for each view in turn, so that with several
+  // views a primitive's parameters are read from memory once and then from the caches
+  const int v = (int)(blockIdx.x % (unsigned)nv);
+  const int64_t j = (int64_t)(blockIdx.x / (unsigned)nv) * blockDim.x + threadIdx.x;
   const CamDev& cam = views->cam[v];
   bool maybe = false, small = false;
   if (j < sc.n) {
@@ -1544,9 +1546,9 @@ hipError_t launch_preprocess(const SceneDev& sc, const Views* views, int nv, con
                              hipStream_t s) {
   if (sc.n == 0) return hipSuccess;
   dim3 grid((unsigned)((sc.n + 127) / 128), (unsigned)nv);
-  dim3 grid_pre((unsigned)((sc.n + kPreBlock - 1) / kPreBlock), (unsigned)nv);
+  dim3 grid_pre((unsigned)((sc.n + kPreBlock - 1) / kPreBlock * nv));
   hipLaunchKernelGGL(k_preprocess, grid_pre, dim3(kPreBlock), 0, s, sc, views, opt, depth_keys, tile_counts,
-                     work_small, count_small, work_big, count_big, status, stride);
+                     work_small, count_small, work_big, count_big, status, stride, nv);
   hipLaunchKernelGGL(k_polygon_small, grid, dim3(128), 0, s, sc, views, opt, records, depth_keys, tile_counts,
                      work_small, count_small, work_big, count_big, span_meta, span_rows, pool_used, row_cap, stride,
                      keygeo);
