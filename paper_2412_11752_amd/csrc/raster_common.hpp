@@ -97,22 +97,25 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
   const float V = fmaf(r[R_H + 3], dx, fmaf(r[R_H + 4], dy, r[R_H + 5]));
   const float W = fmaf(r[R_H + 6], dx, fmaf(r[R_H + 7], dy, r[R_H + 8]));
   const float W2 = W * W;
-  if (!(W2 >= 1e-12f * p.rd2)) return false;          // |r_d . n| < 1e-6
   const float iW = rcpf(W);
   Z = r[R_DN] * iW;
-  if (!(Z > rp.near_plane)) return false;
   const float u = U * iW, v = V * iW;
   const float r2 = fmaf(u, u, v * v);
   const float ex = dx - r[R_OX], ey = dy - r[R_OY];
   const float d2 = fmaf(ex, ex, ey * ey);
   // the low-pass term can reach alpha_min (R_LPCUT < 0 when the filter is off)
   const bool lp_in = d2 * p.rd2 <= r[R_LPCUT] * W2;
-  if (r2 > r[R_R2CUT] && !lp_in) return false;
+  // grazing ray (|r_d . n| < 1e-6), hit at or behind the near plane, or beyond the radius cut, in one
+  // branch (the values computed for a grazing ray are discarded): divergent branches cost the wave
+  // more than the few operations they would skip
+  const bool miss = !(W2 >= 1e-12f * p.rd2) | !(Z > rp.near_plane) | ((r2 > r[R_R2CUT]) & !lp_in);
+  if (miss) return false;
   float E = 0.0f;
   int k = 0;
   float A = 0.f, B = 0.f, D = 0.f, phi = 0.f, t = 0.f, ch = 1.f, sh = 0.f, ws = 0.f, r1 = 0.f;
-  if (r2 > 0.0f) {
-    // sector: largest k with pa_k < pa (wrapping to K-1)
+  {
+    // sector: largest k with pa_k < pa (wrapping to K-1).  No branch on r2 > 0: at the centre
+    // (r2 = 0) pa is NaN, the count gives k = K-1, A = B = D = 0 and E = 0
     const float pa = diamond_pa(u, v);
     int cnt = 0;
 #pragma unroll
@@ -162,18 +165,18 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
   return true;
 }
 
-// True when the wave's pixel rectangle [x0, x1] x [y0, y1] (pixel centres) misses the record's box.
-__device__ __forceinline__ bool box_misses(const float* __restrict__ r, float x0, float x1, float y0, float y1) {
-  return x1 < r[R_BOX + 0] || x0 > r[R_BOX + 1] || y1 < r[R_BOX + 2] || y0 > r[R_BOX + 3];
-}
-
 // Bit i set when staged record i (i < nb) may touch the wave's pixel rectangle.  Lane i tests record
 // i; called by every lane of the wave.
 template <int RF4>
 __device__ __forceinline__ uint64_t batch_box_mask(const float4* lds, int nb, float x0, float x1, float y0, float y1) {
   const int lane = threadIdx.x & 63;
   bool hit = false;
-  if (lane < nb) hit = !box_misses(reinterpret_cast<const float*>(lds + lane * RF4), x0, x1, y0, y1);
+  if (lane < nb) {
+    // record i's box (x0, x1, y0, y1) reaches the wave's pixel-centre rectangle; the four tests
+    // without short-circuit branches, NaN bounds counting as reaching
+    const float4 b = lds[lane * RF4 + R_BOX / 4];
+    hit = !(x1 < b.x) & !(x0 > b.y) & !(y1 < b.z) & !(y0 > b.w);
+  }
   return __ballot(hit);
 }
 

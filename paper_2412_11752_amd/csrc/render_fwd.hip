@@ -138,6 +138,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   __shared__ float4 lds[kRound * RF4];
   __shared__ uint32_t lidx[kRound];
   __shared__ uint2 s_slots[FwdCfg<MODE>::kSlots ? kMaxCache * kBlock : 1];
+  __shared__ uint32_t s_live[2];   // round r sets s_live[r & 1] when a pixel is still compositing
   const CamDev& cam = *camp;
   const int tile = tile_order ? (int)tile_order[blockIdx.x] : (int)blockIdx.x;   // launch order
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -161,9 +162,14 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   // cache payload: (alpha, primitive index); the colour is gathered from the record at emission
   typename FwdCfg<MODE>::CacheT cache;
   cache.init(rp.cache_len, s_slots, tid);
+  if (tid < 2) s_live[tid] = 0u;
 
-  for (uint32_t b0 = start; b0 < end; b0 += kRound) {
-    if (__syncthreads_count(!done) == 0) break;
+  // The workgroup leaves the list once no pixel is compositing.  Round r's waves set s_live[r & 1]
+  // after their evaluations; round r + 1 reads it after the end-of-round barrier, and thread 0
+  // clears it again after round r + 1's staging barrier (it is next set in round r + 2).
+  uint32_t r = 0;
+  for (uint32_t b0 = start; b0 < end; b0 += kRound, ++r) {
+    if (r > 0 && s_live[(r - 1) & 1u] == 0u) break;
     const int nb = (int)min((uint32_t)kRound, end - b0);
     for (int q = tid; q < nb * RF4; q += kBlock) {
       const int ri = q / RF4, c = q - ri * RF4;
@@ -172,6 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
     }
     if (tid < nb) lidx[tid] = prims[b0 + tid];
     __syncthreads();
+    if (tid == 0 && r > 0) s_live[(r - 1) & 1u] = 0u;
     const uint64_t mask = batch_box_mask<RF4>(lds, nb, wx0, wx1, wy0, wy1);
     if (!done) {
       for (uint64_t m = mask; m; m &= m - 1) {
@@ -217,6 +224,8 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
         }
       }
     }
+    const bool live = __ballot(!done) != 0ull;
+    if ((tid & 63) == 0 && live) s_live[r & 1u] = 1u;
     __syncthreads();
   }
   if (!done) {
