@@ -180,48 +180,48 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
     __syncthreads();
     if (tid == 0 && r > 0) s_live[(r - 1) & 1u] = 0u;
     const uint64_t mask = batch_box_mask<RF4>(lds, nb, wx0, wx1, wy0, wy1);
-    if (!done) {
-      for (uint64_t m = mask; m; m &= m - 1) {
-        const int i = __builtin_ctzll(m);
-        const float* r = reinterpret_cast<const float*>(lds + i * RF4);
-        if constexpr (COUNT) ++n_hit;
-        float at, Z;
-        if (!drk_eval<K>(r, pix, rp, at, Z)) continue;
-        if constexpr (COUNT) ++n_full;
-        if (at >= rp.alpha_min) {
-          if constexpr (COUNT) ++n_contrib;
-          // pop the head (emit it), then insert the newcomer
-          const float a = cache.head_a;
-          if (a > 0.0f) {
-            const float test = T * (1.0f - a);
-            if (test < rp.T_min) {
-              done = true;
-              if constexpr (COUNT) consumed = (int)(b0 - start) + i + 1;
-              break;
-            }
-            const float* c = records + (size_t)cache.head_i * RF + R_RGB;
-            const float w = a * T;
-            C0 = fmaf(w, c[0], C0);
-            C1 = fmaf(w, c[1], C1);
-            C2 = fmaf(w, c[2], C2);
-            T = test;
-            if constexpr (TRACE) {
-              if (n_emit < trace_cap) {
-                trace_idx[trace_base + n_emit] = (int32_t)cache.head_i;
-                trace_z[trace_base + n_emit] = cache.key_at(0);
-              }
-            }
-            if constexpr (GEOM) {
-              const float* nr = c - R_RGB + R_NRM;
-              Dz = fmaf(w, cache.key_at(0), Dz);
-              N0 = fmaf(w, nr[0], N0);
-              N1 = fmaf(w, nr[1], N1);
-              N2 = fmaf(w, nr[2], N2);
-            }
-            ++n_emit;
+    // one exit for the loop (the mask); a pixel that stops only leaves the rest of the round's steps
+    for (uint64_t m = mask; m; m &= m - 1) {
+      if (done) continue;
+      const int i = __builtin_ctzll(m);
+      const float* r = reinterpret_cast<const float*>(lds + i * RF4);
+      if constexpr (COUNT) ++n_hit;
+      float at, Z;
+      if (!drk_eval<K>(r, pix, rp, at, Z)) continue;
+      if constexpr (COUNT) ++n_full;
+      if (at >= rp.alpha_min) {
+        if constexpr (COUNT) ++n_contrib;
+        // pop the head (emit it), then insert the newcomer
+        const float a = cache.head_a;
+        if (a > 0.0f) {
+          const float test = T * (1.0f - a);
+          if (test < rp.T_min) {
+            done = true;
+            if constexpr (COUNT) consumed = (int)(b0 - start) + i + 1;
+            continue;
           }
-          cache.pop_insert(Z, at, lidx[i]);
+          const float* c = records + (size_t)cache.head_i * RF + R_RGB;
+          const float w = a * T;
+          C0 = fmaf(w, c[0], C0);
+          C1 = fmaf(w, c[1], C1);
+          C2 = fmaf(w, c[2], C2);
+          T = test;
+          if constexpr (TRACE) {
+            if (n_emit < trace_cap) {
+              trace_idx[trace_base + n_emit] = (int32_t)cache.head_i;
+              trace_z[trace_base + n_emit] = cache.key_at(0);
+            }
+          }
+          if constexpr (GEOM) {
+            const float* nr = c - R_RGB + R_NRM;
+            Dz = fmaf(w, cache.key_at(0), Dz);
+            N0 = fmaf(w, nr[0], N0);
+            N1 = fmaf(w, nr[1], N1);
+            N2 = fmaf(w, nr[2], N2);
+          }
+          ++n_emit;
         }
+        cache.pop_insert(Z, at, lidx[i]);
       }
     }
     const bool live = __ballot(!done) != 0ull;
