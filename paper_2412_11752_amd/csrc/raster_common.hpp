@@ -88,7 +88,12 @@ struct Eval {
 // the weight after rounding; every other rounding step is monotone, so E >= E_lo = eta r1^2 +
 // (1 - eta) r2 w_lo, and E > R_ETHR (c^2 with a margin) gives o Psi(exp(-E/2)) < alpha_min.  Likewise r2 > R_R2CUT bounds E from below by
 // r2 / max_k s_k^2.  Either test only rejects when the low-pass term is also below alpha_min.
-template <int K>
+//
+// EARLY_MISS: the grazing, near-plane and radius tests return before the sector search (fewer
+// operations where many pixels miss, as with the many small DRKs of a converted mesh); otherwise
+// they join the energy cut's branch (one divergent branch less per evaluation).  The results are
+// the same either way.
+template <int K, bool EARLY_MISS = true>
 __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix& p, const RasterParams& rp, float& at,
                                          float& Z, Eval* ev = nullptr) {
   const float dx = p.px - r[R_AX];
@@ -109,7 +114,7 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
   // branch (the values computed for a grazing ray are discarded): divergent branches cost the wave
   // more than the few operations they would skip
   const bool miss = !(W2 >= 1e-12f * p.rd2) | !(Z > rp.near_plane) | ((r2 > r[R_R2CUT]) & !lp_in);
-  if (miss) return false;
+  if (EARLY_MISS && miss) return false;
   float E = 0.0f;
   int k = 0;
   float A = 0.f, B = 0.f, D = 0.f, phi = 0.f, t = 0.f, ch = 1.f, sh = 0.f, ws = 0.f, r1 = 0.f;
@@ -132,7 +137,7 @@ __device__ __forceinline__ bool drk_eval(const float* __restrict__ r, const Pix&
     const float eta = r[R_ETA];
     const float r1sq = r1 * r1, oeta = 1.0f - eta;
     const float E_lo = fmaf(eta, r1sq, oeta * (r2 * sec[S_WLO * K + k]));
-    if (E_lo > r[R_ETHR] && !lp_in) return false;
+    if ((!EARLY_MISS && miss) | ((E_lo > r[R_ETHR]) & !lp_in)) return false;
     phi = atan2_fast(A, D);
     t = phi * sec[S_ID * K + k];
     sh = sinhalf_fast(t);

@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
       const float* r = reinterpret_cast<const float*>(lds + i * RF4);
       if constexpr (COUNT) ++n_hit;
       float at, Z;
-      if (!drk_eval<K>(r, pix, rp, at, Z)) continue;
+      if (!drk_eval<K, MODE == kFwdDepthNormal>(r, pix, rp, at, Z)) continue;
       if constexpr (COUNT) ++n_full;
       if (at >= rp.alpha_min) {
         if constexpr (COUNT) ++n_contrib;
