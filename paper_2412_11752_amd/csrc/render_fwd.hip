@@ -24,7 +24,7 @@ constexpr int kFwdPlain = 0, kFwdTrace = 1, kFwdDepthNormal = 2;
 // leaves them out).
 // Records staged per round by the forward raster.  Small rounds keep the block's LDS (records plus
 // the cache slots below) at about 20 KB, so that 8 waves fit on each SIMD.
-constexpr int kFwdBatch = 8;
+constexpr int kFwdBatch = 10;
 
 // Cache of the forward raster (Sec. 4.4 Cache Sorting, Algorithm 1) with its payloads in LDS.
 // Registers hold the kMaxCache keys in order and one word of 4-bit slot ids: nibble j names the LDS
