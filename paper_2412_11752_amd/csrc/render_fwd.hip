@@ -20,8 +20,6 @@ namespace drk {
 // aux2 = trace_z or normal).
 constexpr int kFwdPlain = 0, kFwdTrace = 1, kFwdDepthNormal = 2;
 
-// COUNT: also write the per-pixel work counters (instrumentation; the production launch of MODE 0
-// leaves them out).
 // Records staged per round by the forward raster.  Small rounds keep the block's LDS (records plus
 // the cache slots below) at about 20 KB, so that 8 waves fit on each SIMD.
 constexpr int kFwdBatch = 10;
@@ -116,6 +114,8 @@ struct FwdCfg {
   using CacheT = typename std::conditional<kSlots, CacheSlots, CacheRegs>::type;
 };
 
+// COUNT: also write the per-pixel work counters (instrumentation; the production launch of MODE 0
+// leaves them out).
 template <int K, int MODE, bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__ records, const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ prims, const CamDev* __restrict__ camp,
@@ -164,12 +164,12 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   cache.init(rp.cache_len, s_slots, tid);
   if (tid < 2) s_live[tid] = 0u;
 
-  // The workgroup leaves the list once no pixel is compositing.  Round r's waves set s_live[r & 1]
-  // after their evaluations; round r + 1 reads it after the end-of-round barrier, and thread 0
-  // clears it again after round r + 1's staging barrier (it is next set in round r + 2).
-  uint32_t r = 0;
-  for (uint32_t b0 = start; b0 < end; b0 += kRound, ++r) {
-    if (r > 0 && s_live[(r - 1) & 1u] == 0u) break;
+  // The workgroup leaves the list once no pixel is compositing.  The waves of round r set
+  // s_live[r & 1] after their evaluations; round r + 1 reads it after the end-of-round barrier, and
+  // thread 0 clears it again after round r + 1's staging barrier (it is next set in round r + 2).
+  uint32_t round = 0;
+  for (uint32_t b0 = start; b0 < end; b0 += kRound, ++round) {
+    if (round > 0 && s_live[(round - 1) & 1u] == 0u) break;
     const int nb = (int)min((uint32_t)kRound, end - b0);
     for (int q = tid; q < nb * RF4; q += kBlock) {
       const int ri = q / RF4, c = q - ri * RF4;
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
     }
     if (tid < nb) lidx[tid] = prims[b0 + tid];
     __syncthreads();
-    if (tid == 0 && r > 0) s_live[(r - 1) & 1u] = 0u;
+    if (tid == 0 && round > 0) s_live[(round - 1) & 1u] = 0u;
     const uint64_t mask = batch_box_mask<RF4>(lds, nb, wx0, wx1, wy0, wy1);
     // one exit for the loop (the mask); a pixel that stops only leaves the rest of the round's steps
     for (uint64_t m = mask; m; m &= m - 1) {
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
       }
     }
     const bool live = __ballot(!done) != 0ull;
-    if ((tid & 63) == 0 && live) s_live[r & 1u] = 1u;
+    if ((tid & 63) == 0 && live) s_live[round & 1u] = 1u;
     __syncthreads();
   }
   if (!done) {
