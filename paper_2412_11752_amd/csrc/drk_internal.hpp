@@ -58,7 +58,7 @@ enum SecField : int {
   S_WLO = 7,   // min(1 / s_k^2, 1 / s_{k+1}^2) (1 - 1e-5): lower bound of the sector's L2 weight
   S_NFIELDS = 8
 };
-__host__ __device__ inline int rec_floats(int K) { return (R_SEC + S_NFIELDS * K + 3) & ~3; }
+__host__ __device__ constexpr int rec_floats(int K) { return (R_SEC + S_NFIELDS * K + 3) & ~3; }
 
 // ---------------------------------------------------------------------------------------------
 struct CamDev {

@@ -1,7 +1,7 @@
 // Forward DRK raster (Eq. 1; Sec. 3.3; Sec. 4.1-4.4; Algorithm 1 of the supplement).
 //
 // One 256-lane workgroup (four wave64s) per 16x16 tile; lane = pixel.  The tile's primitive list
-// (ordered by centre depth) is streamed through LDS in rounds of kFwdBatch records loaded with
+// (ordered by centre depth) is streamed through LDS in rounds of fwd_round(K) records loaded with
 // coalesced float4 reads.  Every lane evaluates every staged primitive at its pixel whose box
 // reaches its wave's pixels; contributors enter the per-pixel sorted cache (keys in VGPRs,
 // payloads in LDS slots), the popped head is composited front to back, and a pixel stops when its
@@ -20,9 +20,6 @@ namespace drk {
 // aux2 = trace_z or normal).
 constexpr int kFwdPlain = 0, kFwdTrace = 1, kFwdDepthNormal = 2;
 
-// Records staged per round by the forward raster.  Small rounds keep the block's LDS (records plus
-// the cache slots below) at about 20 KB, so that 8 waves fit on each SIMD.
-constexpr int kFwdBatch = 10;
 
 // Cache of the forward raster (Sec. 4.4 Cache Sorting, Algorithm 1) with its payloads in LDS.
 // Registers hold the kMaxCache keys in order and one word of 4-bit slot ids: nibble j names the LDS
@@ -107,10 +104,19 @@ struct CacheRegs {
   }
 };
 
-template <int MODE>
+// Records staged per round by the colour and trace rasters: as many as keep a workgroup's LDS
+// (records and their indices, the cache slots above, the exit flags) within 20 KB, so that 8
+// workgroups of 256 lanes (8 waves per SIMD) fit on a CU: 10 records of K = 8, 6 of K = 16, at
+// most 16.
+constexpr int fwd_round(int K) {
+  constexpr int kFree = 20480 - kMaxCache * kBlock * (int)sizeof(uint2) - 2 * (int)sizeof(uint32_t);
+  return kFree / (rec_floats(K) * 4 + 4) > 16 ? 16 : kFree / (rec_floats(K) * 4 + 4);
+}
+
+template <int MODE, int K>
 struct FwdCfg {
   static constexpr bool kSlots = MODE != 2;
-  static constexpr int kRound = kSlots ? kFwdBatch : kBatch;
+  static constexpr int kRound = kSlots ? fwd_round(K) : kBatch;
   using CacheT = typename std::conditional<kSlots, CacheSlots, CacheRegs>::type;
 };
 
@@ -134,10 +140,10 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   float* trace_z = aux2;
   constexpr int RF = (R_SEC + S_NFIELDS * K + 3) & ~3;
   constexpr int RF4 = RF / 4;
-  constexpr int kRound = FwdCfg<MODE>::kRound;
+  constexpr int kRound = FwdCfg<MODE, K>::kRound;
   __shared__ float4 lds[kRound * RF4];
   __shared__ uint32_t lidx[kRound];
-  __shared__ uint2 s_slots[FwdCfg<MODE>::kSlots ? kMaxCache * kBlock : 1];
+  __shared__ uint2 s_slots[FwdCfg<MODE, K>::kSlots ? kMaxCache * kBlock : 1];
   __shared__ uint32_t s_live[2];   // round r sets s_live[r & 1] when a pixel is still compositing
   const CamDev& cam = *camp;
   const int tile = tile_order ? (int)tile_order[blockIdx.x] : (int)blockIdx.x;   // launch order
@@ -160,7 +166,7 @@ __global__ void __launch_bounds__(kBlock) k_render_fwd(const float* __restrict__
   int consumed = (int)(end - start);
   bool done = !inside;
   // cache payload: (alpha, primitive index); the colour is gathered from the record at emission
-  typename FwdCfg<MODE>::CacheT cache;
+  typename FwdCfg<MODE, K>::CacheT cache;
   cache.init(rp.cache_len, s_slots, tid);
   if (tid < 2) s_live[tid] = 0u;
 
