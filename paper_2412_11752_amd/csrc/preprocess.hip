@@ -1065,9 +1065,11 @@ __global__ void __launch_bounds__(64 * kPolyWaves) __attribute__((amdgpu_waves_p
         for (int i = 0; i < 3; ++i) w[i] = (g.mu[i] + x * g.tu[i]) + y * g.tv[i];
         to_cam(cam, w, p);
         L.vx[q] = p[0]; L.vy[q] = p[1]; L.vz[q] = p[2];
-        double pxy[2] = {0.0, 0.0};
-        if (p[2] >= nearp) project(cam, p, pxy[0], pxy[1]);
-        L.px[q] = pxy[0]; L.py[q] = pxy[1];
+        // projected for every lane (no divergent branch); a vertex behind the near plane keeps 0
+        double qx, qy;
+        project(cam, p, qx, qy);
+        const bool front = p[2] >= nearp;
+        L.px[q] = front ? qx : 0.0; L.py[q] = front ? qy : 0.0;
       }
       wave_sync();
       // edges: near-plane crossings, and the exit edges as masks
