@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from drk_synth import (Camera, Scene, camera_lookat, config_c3, config_c5, draw_angles, intrinsics_hfov,
-                       scene_uniform_box)
+                       scene_sphere_shell, scene_uniform_box)
 from oracle import drk_oracle as O
 from tests._gpu_util import IMG_TOL, compare_image, compare_pixels, gpu_opts, log, need_gpu, oracle_opts
 
@@ -75,6 +75,40 @@ def test_views_of_different_sizes_in_one_call():
                 ot.append(t)
                 op.append(j)
         assert np.array_equal(gt, np.array(ot)) and np.array_equal(gp, np.array(op))
+
+
+def _tiny_views():
+    """A view smaller than two tiles, one pixel, one row, one column and a view inside one tile."""
+    return [camera_lookat((0.3, -3.2, 1.0), (0, 0, 0), (0, 0, 1), 40, 24, 60.0, bg=(0.1, 0.2, 0.3)),
+            camera_lookat((2.5, 1.0, 1.5), (0, 0, 0), (0, 0, 1), 1, 1, 20.0),
+            camera_lookat((-2.0, 2.5, 0.5), (0, 0, 0), (0, 0, 1), 37, 1, 60.0),
+            camera_lookat((0.0, 0.5, -3.5), (0, 0, 0), (0, 1, 0), 1, 29, 60.0),
+            camera_lookat((-3.0, -1.0, -1.0), (0, 0, 0), (0, 0, 1), 7, 5, 45.0, bg=(1.0, 1.0, 1.0))]
+
+
+@pytest.mark.parametrize("sh_degree", [0, 1, 2])
+def test_lower_sh_degrees_on_degenerate_views(sh_degree):
+    """SH colour of degree 0, 1 and 2 (Sec. 3.1; the other tests use plain RGB or degree 3), on
+    views of one pixel, one row, one column and less than a tile, all in one call: images within
+    the tolerance of the oracle, tile lists bit-exact."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene = scene_sphere_shell(21 + sh_degree, 1500, K=8, sh_degree=sh_degree)
+    assert scene.color.shape[0] == 3 * (sh_degree + 1) ** 2
+    cams = _tiny_views()
+    ras = _rasterizer(scene, cams, 1 << 20)
+    rgb, _ = ras.forward(DRKScene.from_host(scene), cams, gpu_opts())
+    for v, (g, cam) in enumerate(zip(_views(rgb, cams), cams)):
+        orc = O.render_image(scene, cam, oracle_opts())
+        worst, nk, _, _ = compare_image(g, orc, cam.height, cam.width)
+        log(f"SH{sh_degree} view {v} {cam.width}x{cam.height}: max err {worst:.2e}, knife {nk}, "
+            f"emitted {int(orc.n_emit.sum())}")
+        assert worst <= IMG_TOL
+        tiles, _, _ = O.tile_lists(scene, cam, oracle_opts())
+        ot = [t for t in sorted(tiles) for _ in tiles[t]]
+        op = [j for t in sorted(tiles) for _, j in tiles[t]]
+        assert np.array_equal(_u32(ras.export("pair_tiles", v)), np.array(ot, np.int64))
+        assert np.array_equal(_u32(ras.export("pair_prims", v)), np.array(op, np.int64))
 
 
 def _near_scene():
