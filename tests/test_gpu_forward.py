@@ -131,6 +131,34 @@ def test_no_lowpass_matches_oracle(c1):
     assert worst <= IMG_TOL
 
 
+@pytest.mark.parametrize("alpha_min,alpha_max,T_min,near,lowpass", [
+    (0.05, 0.6, 0.05, 0.2, True),       # tight supports, strong clamp, early stop
+    (1e-3, 0.999, 1e-5, 0.2, True),     # wide supports
+    (1e-3, 0.999, 1e-5, 3.6, False),    # near plane through the back half of the scene
+    (0.02, 0.9, 0.3, 3.0, True),        # near plane at the front face, stop at T < 0.3
+])
+def test_other_thresholds_match_oracle(c1, alpha_min, alpha_max, T_min, near, lowpass):
+    """The cutoffs the compositing takes as options (alpha_min, the alpha clamp, the transmittance
+    stop, the near plane; Sec. 4.4) set from the caller rather than their defaults: the image, the
+    per-DRK tile counts and the tile lists match the oracle run with the same values."""
+    from paper_2412_11752_amd import make_opts
+    ras, ds, cam, scene = c1["ras"], c1["ds"], c1["cam"], c1["scene"]
+    sl = math.sqrt(0.5) if lowpass else 0.0
+    a, _ = ras.forward(ds, [cam], make_opts(alpha_min=alpha_min, alpha_max=alpha_max, T_min=T_min, near=near,
+                                            lowpass_sl=sl))
+    oo = O.Opts(alpha_min=alpha_min, alpha_max=alpha_max, T_min=T_min, near=near, lowpass_sl=sl).f32()
+    orc = O.render_image(scene, cam, oo)
+    worst, nk, _, _ = compare_image(a[0].cpu().numpy(), orc, cam.height, cam.width)
+    log(f"alpha_min {alpha_min} alpha_max {alpha_max} T_min {T_min} near {near} lowpass {lowpass}: "
+        f"max err {worst:.2e}, knife {nk}")
+    assert worst <= IMG_TOL
+    tiles, per, _ = O.tile_lists(scene, cam, oo)
+    assert np.array_equal(_u32(ras.export("tile_counts")), np.array([len(per[j]) for j in range(scene.n)], np.int64))
+    ot, op = oracle_flat_lists(tiles)
+    np.testing.assert_array_equal(_u32(ras.export("pair_tiles")), ot)
+    np.testing.assert_array_equal(_u32(ras.export("pair_prims")), op)
+
+
 def test_ragged_image_and_background():
     """An image that is not a multiple of the tile size, a non-zero background, SH colours."""
     need_gpu()
