@@ -111,6 +111,56 @@ def test_lower_sh_degrees_on_degenerate_views(sh_degree):
         assert np.array_equal(_u32(ras.export("pair_prims", v)), np.array(op, np.int64))
 
 
+def _extreme_scene(seed=31, n=600, K=8):
+    """Valid parameters at the ends of their ranges, cycled over the primitives: eta 0 (pure L2) and
+    1 (pure L1), tau -0.99 and 0.99, opacity 1, 0.999 and just above the 1/255 cutoff, one basis 100x
+    shorter than the rest, and sectors of 1e-3 rad next to a 3.1 rad one (widest gap below pi)."""
+    base = scene_uniform_box(seed, n, K=K, s_lo=0.05, s_hi=0.4)
+    rng = np.random.default_rng(seed)
+    i = np.arange(n)
+    eta = np.choose(i % 3, [np.zeros(n), np.ones(n), base.eta]).astype(np.float32)
+    tau = np.choose(i % 4, [np.full(n, -0.99), np.full(n, 0.99), np.zeros(n), base.tau]).astype(np.float32)
+    o = np.choose(i % 5, [np.ones(n), np.full(n, 0.999), np.full(n, 0.0045), np.full(n, 0.5),
+                          base.opacity]).astype(np.float32)
+    s = base.scale.copy()
+    s[0, ::3] *= 0.01
+    th = base.theta.astype(np.float64)
+    rest = 3.101 + (2 * math.pi - 3.101) * np.arange(1, K - 2) / (K - 2)
+    for j in range(0, n, 2):
+        ang = np.concatenate([[0.0, 1e-3, 3.101], rest]) + rng.uniform(0, 2 * math.pi)
+        th[:, j] = np.sort(np.mod(ang, 2 * math.pi))
+    th = np.minimum(th, np.nextafter(np.float32(2 * math.pi), np.float32(0))).astype(np.float32)
+    return Scene(base.mu, base.q, s, th, eta, tau, o, base.color, -1)
+
+
+@pytest.mark.parametrize("lowpass", [True, False])
+def test_extreme_valid_parameters_match_oracle(lowpass):
+    """Primitives at the ends of the valid parameter ranges pass validation, and their image, tile
+    counts and tile lists match the oracle's."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene, make_opts
+    from paper_2412_11752_amd._lib import DRK_OK
+    scene = _extreme_scene()
+    assert all(O.primitive_valid(scene, j) for j in range(scene.n))
+    cam = camera_lookat((0.4, -0.3, -3.4), (0, 0, 0), (0, 1, 0), 72, 56, 60.0, bg=(0.05, 0.1, 0.15))
+    ras = _rasterizer(scene, [cam], 1 << 20)
+    ds = DRKScene.from_host(scene)
+    ras.preprocess(ds, [cam], make_opts(validate=1, lowpass_sl=math.sqrt(0.5) if lowpass else 0.0))
+    ras.bin_sort()
+    assert ras.status()[0] == DRK_OK
+    rgb, _ = ras.forward(ds, [cam], gpu_opts(lowpass=lowpass))
+    orc = O.render_image(scene, cam, oracle_opts(lowpass=lowpass))
+    worst, nk, _, _ = compare_image(rgb[0].cpu().numpy(), orc, cam.height, cam.width)
+    log(f"extreme parameters, lowpass {lowpass}: max err {worst:.2e}, knife {nk}, emitted {int(orc.n_emit.sum())}")
+    assert worst <= IMG_TOL
+    tiles, per, _ = O.tile_lists(scene, cam, oracle_opts(lowpass=lowpass))
+    assert np.array_equal(_u32(ras.export("tile_counts")), np.array([len(per[j]) for j in range(scene.n)]))
+    ot = [t for t in sorted(tiles) for _ in tiles[t]]
+    op = [j for t in sorted(tiles) for _, j in tiles[t]]
+    assert np.array_equal(_u32(ras.export("pair_tiles")), np.array(ot, np.int64))
+    assert np.array_equal(_u32(ras.export("pair_prims")), np.array(op, np.int64))
+
+
 def _near_scene():
     rng = np.random.default_rng(13)
     n, K = 12, 8
