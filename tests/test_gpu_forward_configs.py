@@ -239,6 +239,24 @@ def test_headline_1m_1080p_sampled():
     _tile_sample(ras, scene, cam, 0, 60, 32)
 
 
+@pytest.mark.timeout(600)
+def test_training_shape_1m_1297x840_sampled():
+    """The same 1M-DRK scene at 1297x840 (81 x 53 tiles, ragged in both directions), the image size of
+    the training-step workload, along its camera path: 4096 seeded pixels (and the image corners)
+    against the oracle, 60 listed DRKs' tile sets and keys bit-exact."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene
+    scene, cams = config_c3(width=1297, height=840)
+    cam = cams[7]
+    ras = _rasterizer(scene, [cam], 6_000_000)
+    rgb, _ = ras.forward(DRKScene.from_host(scene), [cam], gpu_opts())
+    g = rgb[0].cpu().numpy()
+    log("1M 1297x840 rendered")
+    prims = O.Prims.from_scene(scene)
+    _sampled_check(scene, cam, g, prims, 4096, 41, "1M 1297x840")
+    _tile_sample(ras, scene, cam, 0, 60, 42)
+
+
 @pytest.mark.timeout(400)
 def test_eight_views_3m_k16_sampled():
     """3M DRKs (K=16, SH3) in a 40-unit box, eight 1920x1080 views rendered in one call with
