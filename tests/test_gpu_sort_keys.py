@@ -58,6 +58,37 @@ def test_tile_key_lists_and_keys_bit_exact(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_tile_keys_of_several_views_in_one_call(mode):
+    """Three views of different sizes preprocessed and sorted in one call with per-tile keys: every
+    view's lists, keys and image match the oracle's for that view alone."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene, Rasterizer
+    scene = _scene()
+    cams = [_cam(80, 72),
+            camera_lookat((2.6, 0.4, -1.2), (0, 0, 0), (0, 1, 0), 45, 61, 70.0),
+            camera_lookat((-0.8, 2.7, 0.9), (0, 0, 0), (0, 0, 1), 33, 17, 50.0, bg=(0.3, 0.2, 0.1))]
+    ras = Rasterizer(scene.n, scene.K, 80, 72, max_views=len(cams), pair_capacity=1 << 20)
+    rgb, _ = ras.forward(DRKScene.from_host(scene), cams, gpu_opts(key_mode=mode))
+    flat = rgb.reshape(-1).cpu().numpy()
+    off = 0
+    for v, cam in enumerate(cams):
+        npx = cam.width * cam.height
+        g = flat[3 * off:3 * (off + npx)].reshape(3, cam.height, cam.width)
+        off += npx
+        gt, gp = _u32(ras.export("pair_tiles", v)), _u32(ras.export("pair_prims", v))
+        gk = _u32(ras.export("pair_keys", v))
+        tiles, _, _ = O.tile_lists(scene, cam, oracle_opts(key_mode=mode))
+        ot, op = oracle_flat_lists(tiles)
+        ok = np.array([k for t in sorted(tiles) for k, _ in tiles[t]], np.int64)
+        assert np.array_equal(gt, ot) and np.array_equal(gp, op), v
+        assert np.array_equal(gk, ok), v
+        orc = O.render_image(scene, cam, oracle_opts(key_mode=mode))
+        worst, nk, _, _ = compare_image(g, orc, cam.height, cam.width)
+        log(f"key mode {mode}, view {v} {cam.width}x{cam.height}: {gt.size} pairs, max err {worst:.2e}, knife {nk}")
+        assert worst <= IMG_TOL
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("cache_len", [1, 8])
 def test_images_and_traces_match_oracle(mode, cache_len):
     need_gpu()
