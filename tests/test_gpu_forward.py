@@ -113,7 +113,7 @@ def test_culling_changes_no_pixel(c1, cull_mode):
     assert np.array_equal(a[0].cpu().numpy(), c1["rgb"])
 
 
-@pytest.mark.parametrize("L", [1, 3, 8])
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_cache_lengths_match_oracle(c1, L):
     ras, ds, cam, scene = c1["ras"], c1["ds"], c1["cam"], c1["scene"]
     a, _ = ras.forward(ds, [cam], gpu_opts(cache_len=L))

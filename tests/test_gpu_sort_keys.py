@@ -88,6 +88,21 @@ def test_tile_keys_of_several_views_in_one_call(mode):
         assert worst <= IMG_TOL
 
 
+@pytest.mark.parametrize("cache_len", [2, 3, 4, 5, 6, 7])
+def test_every_cache_length_on_a_dense_scene(cache_len):
+    """Cache lengths between 1 and 8 on the overlapping scene, where each length gives a different
+    image (consecutive lengths differ by more than 0.16 somewhere): the image matches the oracle's."""
+    need_gpu()
+    from paper_2412_11752_amd import DRKScene, Rasterizer
+    scene, cam = _scene(), _cam()
+    ras = Rasterizer(scene.n, scene.K, cam.width, cam.height, pair_capacity=1 << 20)
+    rgb, _ = ras.forward(DRKScene.from_host(scene), [cam], gpu_opts(cache_len=cache_len))
+    orc = O.render_image(scene, cam, oracle_opts(cache_len=cache_len))
+    worst, nk, _, _ = compare_image(rgb[0].cpu().numpy(), orc, cam.height, cam.width)
+    log(f"dense scene, cache_len={cache_len}: max err {worst:.2e}, knife {nk}")
+    assert worst <= IMG_TOL
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("cache_len", [1, 8])
 def test_images_and_traces_match_oracle(mode, cache_len):
