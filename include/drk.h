@@ -157,7 +157,14 @@ drk_status drk_ws_size_query(int64_t max_n, int32_t K, int32_t max_views, int32_
  * calibrated support radius, conservative support polygon projected and clipped to the near
  * plane, the 16x16 tiles it touches, and the per-primitive record the raster kernels read.
  * cams: HOST array of n_views cameras (copied into the launch).  The scene must stay alive until
- * drk_render_fwd / drk_render_bwd of this frame have been enqueued and completed.            */
+ * drk_render_fwd / drk_render_bwd of this frame have been enqueued and completed.
+ * Returns DRK_EINVAL, before any device work, for options outside these ranges: alpha_min,
+ * alpha_max and T_min in (0, 1), near_plane > 0, lowpass_sl >= 0, cache_len in [1, 8] or
+ * >= 2^30, cull_mode and key_mode in [0, 2], launch_order and counters 0 or 1.  Likewise for
+ * n_views outside [1, max_views], a camera larger than the workspace's max_w x max_h, with a
+ * focal length that is not positive or a non-finite or singular R, and for a scene with more
+ * than max_n primitives, another K, an sh_degree outside [0, 3] with SH colour, or a null array
+ * when n > 0. */
 drk_status drk_preprocess(drk_ws* ws, const drk_scene* scene, const drk_camera* cams, int32_t n_views,
                           const drk_opts* opts, void* stream);
 
