@@ -158,6 +158,8 @@ drk_status drk_ws_size_query(int64_t max_n, int32_t K, int32_t max_views, int32_
  * plane, the 16x16 tiles it touches, and the per-primitive record the raster kernels read.
  * cams: HOST array of n_views cameras (copied into the launch).  The scene must stay alive until
  * drk_render_fwd / drk_render_bwd of this frame have been enqueued and completed.
+ * Every call ends the workspace's previous frame: after a refused call drk_bin_sort and the
+ * renders return DRK_EINVAL until a drk_preprocess succeeds.
  * Returns DRK_EINVAL, before any device work, for options outside these ranges: alpha_min,
  * alpha_max and T_min in (0, 1), near_plane > 0, lowpass_sl >= 0, cache_len in [1, 8] or
  * >= 2^30, cull_mode and key_mode in [0, 2], launch_order and counters 0 or 1.  Likewise for

@@ -261,17 +261,17 @@ static int64_t env_int(const char* name, int64_t def, int64_t lo, int64_t hi) {
   return (end != e && *end == '\0' && v >= lo && v <= hi) ? (int64_t)v : def;
 }
 
-drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts* opts, hipStream_t s) {
-  if (!ws || !scene || !opts) { set_error("null argument"); return DRK_EINVAL; }
-  if (ws->views.nv < 1) { set_error("no cameras set"); return DRK_EINVAL; }
-  if (scene->n < 0 || scene->n > ws->max_n) { set_error("scene n %lld exceeds workspace max_n %lld", (long long)scene->n, (long long)ws->max_n); return DRK_EINVAL; }
-  if (scene->K != ws->K) { set_error("scene K %d != workspace K %d", scene->K, ws->K); return DRK_EINVAL; }
-  if (scene->color_mode != 0 && scene->color_mode != 1) { set_error("color_mode must be 0 or 1"); return DRK_EINVAL; }
-  if (scene->color_mode == 1 && (scene->sh_degree < 0 || scene->sh_degree > 3)) { set_error("sh_degree must be in [0, 3]"); return DRK_EINVAL; }
+// Host-side checks of a frame's scene and options against the workspace (no device work).
+bool valid_frame_args(const drk_ws* ws, const drk_scene* scene, const drk_opts* opts) {
+  if (!ws || !scene || !opts) { set_error("null argument"); return false; }
+  if (scene->n < 0 || scene->n > ws->max_n) { set_error("scene n %lld exceeds workspace max_n %lld", (long long)scene->n, (long long)ws->max_n); return false; }
+  if (scene->K != ws->K) { set_error("scene K %d != workspace K %d", scene->K, ws->K); return false; }
+  if (scene->color_mode != 0 && scene->color_mode != 1) { set_error("color_mode must be 0 or 1"); return false; }
+  if (scene->color_mode == 1 && (scene->sh_degree < 0 || scene->sh_degree > 3)) { set_error("sh_degree must be in [0, 3]"); return false; }
   if (scene->n > 0 && (!scene->mu || !scene->q || !scene->scale || !scene->theta || !scene->eta || !scene->tau ||
                        !scene->opacity || !scene->color)) {
     set_error("scene array is null");
-    return DRK_EINVAL;
+    return false;
   }
   if (!(opts->alpha_min > 0.0f && opts->alpha_min < 1.0f) || !(opts->alpha_max > 0.0f && opts->alpha_max < 1.0f) ||
       !(opts->T_min > 0.0f && opts->T_min < 1.0f) || !(opts->near_plane > 0.0f) || !(opts->lowpass_sl >= 0.0f) ||
@@ -281,8 +281,14 @@ drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts
       opts->counters < 0 || opts->counters > 1) {
     set_error("invalid drk_opts (cache_len must be in [1, %d] or at least 2^30 for the exact order, key_mode in "
               "[0, 2], launch_order and counters 0 or 1)", kMaxCache);
-    return DRK_EINVAL;
+    return false;
   }
+  return true;
+}
+
+drk_status ws_preprocess_core(drk_ws* ws, const drk_scene* scene, const drk_opts* opts, hipStream_t s) {
+  if (!valid_frame_args(ws, scene, opts)) return DRK_EINVAL;
+  if (ws->views.nv < 1) { set_error("no cameras set"); return DRK_EINVAL; }
   SceneDev sc;
   sc.n = scene->n; sc.K = scene->K; sc.color_mode = scene->color_mode;
   sc.sh_degree = scene->color_mode == 1 ? scene->sh_degree : 0;
@@ -435,6 +441,10 @@ drk_status drk_ws_destroy(drk_ws* ws) {
 
 drk_status drk_preprocess(drk_ws* ws, const drk_scene* scene, const drk_camera* cams, int32_t n_views,
                           const drk_opts* opts, void* stream) {
+  if (!ws) { set_error("null workspace"); return DRK_EINVAL; }
+  // the earlier frame is given up whatever the outcome: past the checks its cameras are replaced
+  ws->have_pre = ws->have_bins = false;
+  if (!drk::valid_frame_args(ws, scene, opts)) return DRK_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   drk_status st = drk::ws_set_cameras(ws, cams, n_views, s);
   if (st) return st;

@@ -297,6 +297,42 @@ def test_validate_mode_reports_invalid_primitives(c1):
         assert worst <= IMG_TOL, name
 
 
+def test_invalid_frame_arguments_are_refused(c1):
+    """Options, cameras and scenes outside the accepted ranges give DRK_EINVAL from drk_preprocess,
+    and a refused call leaves no frame behind: drk_bin_sort then refuses too, until a valid frame."""
+    from paper_2412_11752_amd import DRKScene, make_opts
+    from paper_2412_11752_amd._lib import DRK_EINVAL, DrkError
+    ras, ds, cam, scene = c1["ras"], c1["ds"], c1["cam"], c1["scene"]
+
+    def refused(d, cams, opts):
+        with pytest.raises(DrkError) as e:
+            ras.preprocess(d, cams, opts)
+        assert e.value.code == DRK_EINVAL
+        with pytest.raises(DrkError) as e:
+            ras.bin_sort()
+        assert e.value.code == DRK_EINVAL
+
+    ras.preprocess(ds, [cam], gpu_opts())
+    ras.bin_sort()
+    for kw in (dict(alpha_min=0.0), dict(alpha_min=1.0), dict(alpha_max=0.0), dict(alpha_max=1.0),
+               dict(T_min=0.0), dict(T_min=1.0), dict(near=0.0), dict(near=float("nan")), dict(lowpass_sl=-1.0),
+               dict(cache_len=0), dict(cache_len=9), dict(cache_len=(1 << 30) - 1), dict(cull_mode=3),
+               dict(key_mode=3), dict(launch_order=2), dict(counters=2)):
+        refused(ds, [cam], make_opts(**kw))
+    wide = Camera(cam.width + 1, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.R, cam.t)
+    flat = Camera(cam.width, cam.height, 0.0, cam.fy, cam.cx, cam.cy, cam.R, cam.t)
+    bad_r = Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, np.full((3, 3), np.nan, np.float32), cam.t)
+    singular = Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, np.zeros((3, 3), np.float32), cam.t)
+    for c in (wide, flat, bad_r, singular):
+        refused(ds, [c], gpu_opts())
+    refused(ds, [cam, cam], gpu_opts())                                   # more views than the workspace has
+    refused(DRKScene.from_host(scene_uniform_box(1, scene.n + 1, K=8)), [cam], gpu_opts())
+    refused(DRKScene.from_host(scene_uniform_box(1, 16, K=5)), [cam], gpu_opts())
+    # a valid frame afterwards renders as before
+    rgb, _ = ras.forward(ds, [cam], gpu_opts(counters=1))
+    assert np.array_equal(rgb[0].cpu().numpy(), c1["rgb"])
+
+
 def _validate_opts(v):
     from paper_2412_11752_amd import make_opts
     return make_opts(validate=v)
