@@ -7,7 +7,7 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import DRK_EAGAIN, DRK_OK, check, lib
+from ._lib import DRK_EAGAIN, check, lib
 from .rasterizer import DRKScene, camera_struct, make_opts
 
 

@@ -1,7 +1,6 @@
 """Mesh to DRK and the depth / normal channels (section "Converting Mesh to DRK" and its
 supplement) of the HIP path against the FP64 oracle: converted parameters, rejected faces, and
 colour, depth and normal images of converted meshes."""
-import math
 
 import numpy as np
 import pytest

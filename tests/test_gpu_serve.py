@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from drk_synth import camera_lookat, config_c1, config_c2, scene_uniform_box
+from drk_synth import camera_lookat, config_c2, scene_uniform_box
 from oracle import drk_oracle as O
 from tests._gpu_util import IMG_TOL, compare_image, gpu_opts, log, need_gpu, oracle_opts
 
@@ -79,7 +79,7 @@ def test_served_request_matches_oracle(scenes):
 
 
 def test_admission_errors(scenes):
-    from paper_2412_11752_amd._lib import DRK_EAGAIN, DRK_ENOMEM, DRK_ENOTFOUND, DrkError
+    from paper_2412_11752_amd._lib import DRK_EAGAIN, DRK_ENOMEM, DRK_ENOTFOUND
     from paper_2412_11752_amd.serving import Server
     hs, ds = scenes
     cam = _cams(3, [(800, 800)], 1)[0]

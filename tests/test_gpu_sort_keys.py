@@ -2,13 +2,12 @@
 cache-sorting evaluation) of the HIP path against the FP64 oracle: tile lists and keys bit-exact,
 images and composited sequences equal, and the metrics kernel equal to the oracle's measures of the
 same traces."""
-import math
 
 import numpy as np
 import pytest
 import torch
 
-from drk_synth import Camera, camera_lookat, config_c3, intrinsics_hfov, scene_uniform_box
+from drk_synth import camera_lookat, config_c3, scene_uniform_box
 from oracle import drk_oracle as O
 from tests._gpu_util import IMG_TOL, compare_image, gpu_opts, log, need_gpu, oracle_flat_lists, oracle_opts
 

@@ -6,7 +6,6 @@ solve for the ray-plane hit, heapq for the cache, scipy for spherical harmonics)
 (telescoping weights, Psi identities) and brute force on tiny inputs.
 """
 import heapq
-import itertools
 import math
 import os
 
