@@ -454,6 +454,7 @@ drk_status drk_preprocess(drk_ws* ws, const drk_scene* scene, const drk_camera* 
 drk_status drk_bin_sort(drk_ws* ws, void* stream) {
   if (!ws) { set_error("null workspace"); return DRK_EINVAL; }
   if (!ws->have_pre) { set_error("drk_bin_sort before drk_preprocess"); return DRK_EINVAL; }
+  ws->have_bins = false;   // until every view's lists are enqueued again
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t N = ws->scene.n;
   drk_status st = DRK_OK;
