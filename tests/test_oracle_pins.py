@@ -273,6 +273,56 @@ def test_p7_cache_semantics():
     assert O.cache_emit(r, 8) == sorted(r)                                  # reversed input, n <= L
 
 
+# ---- Two Gaussian-reduced DRKs on planes that cross along the optical axis (Sec. 4.1 reduction,
+# Eq. 1, Sec. 4.4 Cache Sorting): their centres coincide, so the centre-depth pre-sort is the index
+# order on every pixel, while the hit depths swap sides at the crossing.  Every expected value is
+# elementary geometry written out here: ray-plane hit, in-plane distance, o exp(-r^2 / 2s^2), and the
+# two-layer blend in hit-depth order (index order for a cache of one slot).
+def test_crossing_planes_order_by_hit_depth():
+    W, H, s, phi = 48, 32, 3.0, math.radians(30.0)
+    o = (0.6, 0.5)
+    col = np.array([[1.0, 0.0], [0.0, 1.0], [0.0, 0.0]], np.float32)    # A red, B green
+    bg = np.array([0.0, 0.0, 1.0])
+    K = 8
+    q = np.array([[math.cos(phi / 2), math.cos(-phi / 2)], [0.0, 0.0],
+                  [math.sin(phi / 2), math.sin(-phi / 2)], [0.0, 0.0]], np.float32)
+    theta = np.tile((np.arange(K) * 2 * math.pi / K)[:, None], (1, 2)).astype(np.float32)
+    sc = Scene(np.array([[0.0, 0.0], [0.0, 0.0], [4.0, 4.0]], np.float32), q, np.full((K, 2), s, np.float32), theta,
+               np.zeros(2, np.float32), np.zeros(2, np.float32), np.array(o, np.float32), col, -1)
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.zeros(3, np.float32), bg.astype(np.float32))
+    # expected, from the float32 inputs in float64
+    yy, xx = np.mgrid[0:H, 0:W]
+    ray = np.stack([(xx.ravel() + 0.5 - float(cx)) / float(fx), (yy.ravel() + 0.5 - float(cy)) / float(fy),
+                    np.ones(W * H)], 1)
+    p0 = np.array([0.0, 0.0, 4.0])
+    Z, alpha = [], []
+    for j in range(2):
+        w, y = float(q[0, j]), float(q[2, j])
+        nrm = np.array([2 * w * y, 0.0, 1 - 2 * y * y]) / (w * w + y * y)   # third column of R(q)
+        t = (nrm @ p0) / (ray @ nrm)
+        hit = ray * t[:, None]
+        r2 = ((hit - p0) ** 2).sum(1)
+        Z.append(t)
+        alpha.append(float(np.float32(o[j])) * np.exp(-r2 / (2 * float(np.float32(s)) ** 2)))
+    Z, alpha = np.array(Z), np.array(alpha)
+
+    def blend(first):
+        f, b = first, 1 - first
+        af, ab = alpha[f, np.arange(W * H)], alpha[b, np.arange(W * H)]
+        return (af[:, None] * col.T[f] + ((1 - af) * ab)[:, None] * col.T[b]
+                + ((1 - af) * (1 - ab))[:, None] * bg)
+
+    by_depth = blend((Z[1] < Z[0]).astype(int))
+    by_index = blend(np.zeros(W * H, int))
+    assert (Z[0] < Z[1]).any() and (Z[1] < Z[0]).any()
+    assert np.abs(by_depth - by_index).max() > 0.05
+    for L, want in ((O.EXACT, by_depth), (8, by_depth), (2, by_depth), (1, by_index)):
+        r = O.render_image(sc, cam, O.Opts(cache_len=L, lowpass_sl=0.0))
+        assert not r.knife.any()
+        np.testing.assert_allclose(r.rgb, want, atol=1e-7, err_msg=f"cache_len {L}")
+
+
 # ---- P8: fronto-parallel scene (all normals along the optical axis): r_t order equals centre-depth
 # order, so the 8-slot cache reproduces the exact per-pixel sort.
 def test_p8_frontoparallel_cache_equals_exact():
