@@ -323,6 +323,41 @@ def test_crossing_planes_order_by_hit_depth():
         np.testing.assert_allclose(r.rgb, want, atol=1e-7, err_msg=f"cache_len {L}")
 
 
+# ---- The near plane cuts hits, not only centres: one Gaussian-reduced DRK on a steep plane whose
+# centre lies just beyond the near plane.  Where the ray meets the plane at or before the near plane
+# the pixel keeps the background; elsewhere it is o exp(-r^2 / 2s^2) over the background, from the
+# ray-plane hit written out here.
+def test_near_plane_cuts_hits_of_a_tilted_plane():
+    W, H, s, phi, near, o = 40, 24, 2.0, math.radians(60.0), 0.9, 0.8
+    K = 8
+    q = np.array([[math.cos(phi / 2)], [0.0], [math.sin(phi / 2)], [0.0]], np.float32)
+    theta = (np.arange(K) * 2 * math.pi / K)[:, None].astype(np.float32)
+    sc = Scene(np.array([[0.0], [0.0], [1.0]], np.float32), q, np.full((K, 1), s, np.float32), theta,
+               np.zeros(1, np.float32), np.zeros(1, np.float32), np.array([o], np.float32),
+               np.array([[1.0], [1.0], [0.0]], np.float32), -1)
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 90.0)
+    bg = np.array([0.0, 0.0, 1.0])
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.zeros(3, np.float32), bg.astype(np.float32))
+    yy, xx = np.mgrid[0:H, 0:W]
+    ray = np.stack([(xx.ravel() + 0.5 - float(cx)) / float(fx), (yy.ravel() + 0.5 - float(cy)) / float(fy),
+                    np.ones(W * H)], 1)
+    w, y = float(q[0, 0]), float(q[2, 0])
+    nrm = np.array([2 * w * y, 0.0, 1 - 2 * y * y]) / (w * w + y * y)
+    p0 = np.array([0.0, 0.0, 1.0])
+    den = ray @ nrm
+    Z = np.where(den > 0, (nrm @ p0) / np.where(den > 0, den, 1.0), -1.0)   # hit depth (ray z = 1)
+    r2 = ((ray * Z[:, None] - p0) ** 2).sum(1)
+    a = np.where(Z > near, float(np.float32(o)) * np.exp(-r2 / (2 * s * s)), 0.0)
+    want = a[:, None] * np.array([1.0, 1.0, 0.0]) + (1 - a)[:, None] * bg
+    cut = Z <= near
+    assert cut.sum() > W * H // 10 and (~cut).sum() > W * H // 10
+    r = O.render_image(sc, cam, O.Opts(near=near, lowpass_sl=0.0))
+    ok = ~r.knife
+    assert ok.sum() >= W * H - 2
+    np.testing.assert_allclose(r.rgb[ok], want[ok], atol=1e-7)
+    np.testing.assert_array_equal(r.n_emit[cut & ok], 0)
+
+
 # ---- P8: fronto-parallel scene (all normals along the optical axis): r_t order equals centre-depth
 # order, so the 8-slot cache reproduces the exact per-pixel sort.
 def test_p8_frontoparallel_cache_equals_exact():
