@@ -358,6 +358,34 @@ def test_near_plane_cuts_hits_of_a_tilted_plane():
     np.testing.assert_array_equal(r.n_emit[cut & ok], 0)
 
 
+# ---- The alpha clamp and the alpha cutoff on one opaque fronto-parallel Gaussian-reduced DRK:
+# alpha = min(exp(-r^2 / 2s^2), alpha_max) where that is at least alpha_min, else nothing.
+def test_alpha_clamp_and_cutoff_of_one_opaque_drk():
+    W = H = 49                      # odd: one pixel centre on the axis, where alpha is clamped
+    s, depth, K = 0.3, 3.0, 8
+    sc = Scene(np.array([[0.0], [0.0], [depth]], np.float32), np.array([[1.0], [0.0], [0.0], [0.0]], np.float32),
+               np.full((K, 1), s, np.float32), (np.arange(K) * 2 * math.pi / K)[:, None].astype(np.float32),
+               np.zeros(1, np.float32), np.zeros(1, np.float32), np.ones(1, np.float32),
+               np.array([[0.2], [0.9], [0.4]], np.float32), -1)
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 60.0)
+    bg = np.array([0.5, 0.0, 0.5])
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.zeros(3, np.float32), bg.astype(np.float32))
+    yy, xx = np.mgrid[0:H, 0:W]
+    u = (xx.ravel() + 0.5 - float(cx)) / float(fx) * depth
+    v = (yy.ravel() + 0.5 - float(cy)) / float(fy) * depth
+    g = np.exp(-(u * u + v * v) / (2 * float(np.float32(s)) ** 2))
+    opts = O.Opts(lowpass_sl=0.0)
+    amax, amin = float(np.float32(opts.alpha_max)), float(np.float32(opts.alpha_min))
+    a = np.where(g >= amin, np.minimum(g, amax), 0.0)
+    want = a[:, None] * np.array([0.2, 0.9, 0.4], np.float32).astype(np.float64) + (1 - a)[:, None] * bg
+    assert (g > amax).sum() >= 1 and (g < amin).sum() > W * H // 4
+    r = O.render_image(sc, cam, opts.f32())
+    ok = ~r.knife
+    assert ok[np.argmax(g)] and ok.sum() >= W * H - 4
+    np.testing.assert_allclose(r.rgb[ok], want[ok], atol=1e-7)
+    np.testing.assert_array_equal(r.n_emit[ok], (a[ok] > 0).astype(int))
+
+
 # ---- P8: fronto-parallel scene (all normals along the optical axis): r_t order equals centre-depth
 # order, so the 8-slot cache reproduces the exact per-pixel sort.
 def test_p8_frontoparallel_cache_equals_exact():
