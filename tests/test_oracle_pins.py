@@ -386,6 +386,40 @@ def test_alpha_clamp_and_cutoff_of_one_opaque_drk():
     np.testing.assert_array_equal(r.n_emit[ok], (a[ok] > 0).astype(int))
 
 
+# ---- View-dependent colour in the render (Sec. 3.1, SH as in 3D-GS): degree-1 SH evaluated at the
+# direction from the camera centre to the DRK's centre, plus 0.5, clamped at 0, and the same colour
+# on every pixel of that DRK.  The basis is written out: Y_0 = 1/(2 sqrt(pi)), (Y_1, Y_2, Y_3) =
+# sqrt(3/(4 pi)) (y, z, x).
+def test_sh_colour_of_an_off_axis_drk():
+    W = H = 33
+    mu = np.array([0.6, -0.4, 3.0])
+    campos = np.array([0.2, 0.3, -1.0])
+    K = 8
+    coef = np.array([[0.1, -2.5, 0.3],      # l = 0, channels r g b
+                     [0.5, 0.2, -0.6],      # Y_1 ~ y
+                     [-0.3, 0.4, 0.1],      # Y_2 ~ z
+                     [0.7, -0.2, 0.9]])     # Y_3 ~ x
+    color = coef.reshape(12, 1).astype(np.float32)     # row 3 * coefficient + channel
+    sc = Scene(mu[:, None].astype(np.float32), np.array([[1.0], [0.0], [0.0], [0.0]], np.float32),
+               np.full((K, 1), 0.4, np.float32), (np.arange(K) * 2 * math.pi / K)[:, None].astype(np.float32),
+               np.zeros(1, np.float32), np.zeros(1, np.float32), np.full(1, 0.9, np.float32), color, 1)
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 50.0)
+    R = np.eye(3, dtype=np.float32)
+    t = (-campos).astype(np.float32)
+    cam = Camera(W, H, fx, fy, cx, cy, R, t, np.zeros(3, np.float32))
+    d = mu.astype(np.float32).astype(np.float64) - campos.astype(np.float32).astype(np.float64)
+    x, y, z = d / np.linalg.norm(d)
+    Y = np.array([0.5 / math.sqrt(math.pi)] + [math.sqrt(3 / (4 * math.pi)) * c for c in (y, z, x)])
+    rgb = np.maximum(Y @ coef.astype(np.float32).astype(np.float64) + 0.5, 0.0)
+    assert rgb.min() == 0.0 and rgb.max() > 0.5                # one channel is clamped
+    r = O.render_image(sc, cam, O.Opts(lowpass_sl=0.0))
+    T = r.T
+    hit = (r.n_emit == 1) & ~r.knife
+    assert hit.sum() > 20
+    # one layer over a black background: colour = (1 - T) * rgb
+    np.testing.assert_allclose(r.rgb[hit], (1 - T[hit])[:, None] * rgb[None, :], atol=1e-9)
+
+
 # ---- P8: fronto-parallel scene (all normals along the optical axis): r_t order equals centre-depth
 # order, so the 8-slot cache reproduces the exact per-pixel sort.
 def test_p8_frontoparallel_cache_equals_exact():
