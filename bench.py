@@ -675,6 +675,9 @@ def main():
                    "one_frame_launch_order": "longest lists first"},
         "one_frame_in_flight_mpix_s": round(result["fwd1"]["mpix"], 3) if "fwd1" in result else None,
         "fwd_bwd_it_per_s": round(result["fwdbwd"]["its"], 3) if "fwdbwd" in result else None,
+        "fwd_bwd_note": None if "fwdbwd" in result else
+        "not measured: drk_render_bwd is switched off (returns DRK_EDEVICE) until the cause of its "
+        "illegal memory access on gfx950 is shown",
         "ms_breakdown": {k: round(float(result.get("fwd1", fwd)["ms"][:, i].mean()), 4) for i, k in
                          enumerate(["preprocess", "bin_sort", "render_fwd"])} if fwd else None,
         "roofline": roofline,
