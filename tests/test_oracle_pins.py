@@ -420,6 +420,34 @@ def test_sh_colour_of_an_off_axis_drk():
     np.testing.assert_allclose(r.rgb[hit], (1 - T[hit])[:, None] * rgb[None, :], atol=1e-9)
 
 
+# ---- The transmittance stop in the render (Eq. 1 with the T_min rule): five fronto-parallel
+# Gaussian-reduced DRKs stacked on the optical axis, each of opacity 0.92.  On the axis pixel every
+# layer has alpha 0.92, so T runs 0.08, 0.0064, 5.12e-4, and the fourth layer (4.1e-5 < 1e-4) stops
+# the pixel unadded: three layers composite and the background enters with T = 0.08^3.
+def test_transmittance_stop_on_stacked_layers():
+    W = H = 9
+    K, n, s, o = 8, 5, 0.5, 0.92
+    depths = 3.0 + 0.25 * np.arange(n)
+    cols = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0], [0, 1, 1]], np.float32)
+    sc = Scene(np.stack([np.zeros(n), np.zeros(n), depths]).astype(np.float32),
+               np.tile(np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), (1, n)), np.full((K, n), s, np.float32),
+               np.tile((np.arange(K) * 2 * math.pi / K)[:, None], (1, n)).astype(np.float32),
+               np.zeros(n, np.float32), np.zeros(n, np.float32), np.full(n, o, np.float32), cols.T.copy(), -1)
+    fx, fy, cx, cy = intrinsics_hfov(W, H, 30.0)
+    bg = np.array([0.3, 0.3, 0.3])
+    cam = Camera(W, H, fx, fy, cx, cy, np.eye(3, dtype=np.float32), np.zeros(3, np.float32), bg.astype(np.float32))
+    r = O.render_image(sc, cam, O.Opts(lowpass_sl=0.0))
+    c = (H // 2) * W + W // 2
+    a = float(np.float32(o))
+    Ts = [1.0, 1 - a, (1 - a) ** 2, (1 - a) ** 3]
+    want = sum(Ts[i] * a * cols[i].astype(np.float64) for i in range(3)) + Ts[3] * bg
+    assert Ts[3] * (1 - a) < 1e-4 <= Ts[3]
+    assert not r.knife[c] and r.n_emit[c] == 3
+    assert r.emitted[c] == [0, 1, 2]
+    np.testing.assert_allclose(r.rgb[c], want, atol=1e-12)
+    assert r.T[c] == pytest.approx(Ts[3], rel=1e-12)
+
+
 # ---- P8: fronto-parallel scene (all normals along the optical axis): r_t order equals centre-depth
 # order, so the 8-slot cache reproduces the exact per-pixel sort.
 def test_p8_frontoparallel_cache_equals_exact():
